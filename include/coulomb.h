@@ -1,0 +1,219 @@
+/*
+ * coulomb.h -- C ABI of libcoulomb_mi355x.so: direct all-pairs Coulomb forces
+ * and velocity-Verlet motion of ions in a linear Paul trap, on one MI355X
+ * (gfx950) GPU.
+ *
+ * Physics (paper, section 2, eq. (1), with the readings below):
+ *   F_i   = k_C q_i sum_{j != i} q_j (r_i - r_j) / (|r_i - r_j|^2 + eps2)^{3/2}
+ *   a_i   = F_i / m_i - (kx(t) x_i, ky(t) y_i, kz(t) z_i)
+ *   U_C   = k_C sum_{i<j} q_i q_j (|r_i - r_j|^2 + eps2)^{-1/2}
+ *   U_trap= sum_i m_i (kx x_i^2 + ky y_i^2 + kz z_i^2) / 2,  K = sum_i m_i |v_i|^2 / 2
+ * with k_C = 1/(4 pi eps0) (CODATA 2018 eps0), the self pair excluded, eps2
+ * (softening) added to r^2 as in the paper's section 3 double loop, and the
+ * trap spring constants per unit mass k(t) given by cb_trap below.
+ * Velocity-Verlet is the paper's three-step list (section 2):
+ *   r' = r + v dt + a dt^2/2;  a' = a(r', t + dt);  v' = v + (a + a') dt/2.
+ *
+ * Conventions shared by every call:
+ *  - Units are SI (m, s, kg, C, N, J).  Every array argument is a DEVICE
+ *    pointer to contiguous float64 data of length n (structure of arrays)
+ *    unless stated otherwise; host pointers are marked "host".
+ *  - The caller owns all buffers.  The library never allocates or frees
+ *    device memory in these calls and keeps no pointer after it returns.
+ *    Scratch space is the caller's workspace `ws` of `ws_bytes` bytes (device
+ *    memory, any alignment of 256 bytes or more), sized by
+ *    cb_workspace_size(); too small a workspace returns CB_ENOWS.
+ *  - All work is enqueued on `stream` (a hipStream_t; NULL is the default
+ *    stream) and the call returns after enqueueing.  Host arrays passed in
+ *    (offsets, traps) may be reused as soon as the call returns.
+ *  - Argument errors are detected before anything is enqueued and returned as
+ *    CB_EINVAL / CB_ENOWS / CB_EUNSUPPORTED; a failed launch returns CB_EHIP.
+ *    cb_last_error() then describes the failure (thread-local string).
+ *  - Outputs must not alias inputs except for the documented in-place state.
+ *  - Results are deterministic: the same inputs, precision and launch
+ *    configuration (see cb_autotune) give bitwise identical outputs; no
+ *    floating-point atomics are used.
+ *  - Non-finite outputs (e.g. two coincident ions with eps2 = 0) are not an
+ *    error; they set a device flag that cb_poll_flags() reports.
+ *
+ * Readings of the paper (it is silent or inconsistent on these points):
+ *  - the sum of eq. (1) excludes j = i;
+ *  - the trap term of eq. (1) acts on ion i (it prints x_j, y_j);
+ *  - the RF drive 2 Q V_RF cos(.) / (m r0^2) is written in Mathieu form
+ *    q Omega^2/2 cos(Omega t + phi) with Omega in rad/s;
+ *  - charges and masses are per ion.
+ */
+#ifndef COULOMB_MI355X_H
+#define COULOMB_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes returned by every call. */
+typedef enum {
+    CB_OK = 0,
+    CB_EINVAL = 1,        /* bad argument (NULL, n < 1, dt <= 0, aliasing, ...) */
+    CB_EHIP = 2,          /* a HIP runtime call or kernel launch failed */
+    CB_ENOWS = 3,         /* workspace too small */
+    CB_ENONFINITE = 4,    /* reported by cb_poll_flags when the flag is set */
+    CB_EUNSUPPORTED = 5   /* valid request this build does not handle */
+} cb_status;
+
+/* How 1/sqrt(r^2 + eps2) is evaluated (paper, sections 2 and 4: the cost and
+ * accuracy of the inverse square root decide the speed of the pair loop).
+ *  CB_FP64      hardware FP64 reciprocal-square-root estimate refined by
+ *               Newton-Raphson steps y <- y (3 - x y^2)/2 (section 4) to full
+ *               double precision; FP64 throughout.  The default.
+ *  CB_MIXED     FP32 hardware estimate of the FP32-rounded r^2 followed by ONE
+ *               FP64 Newton-Raphson step on the FP64 r^2 (the analogue of the
+ *               paper's "RSQRT14 + 1 N-W"); displacements, r^2, the force
+ *               numerator and all accumulation stay FP64.  Relative force
+ *               error well below 1e-7.  Requires r^2 + eps2 inside the FP32
+ *               normal range (1.2e-38 .. 3.4e38 m^2).
+ *  CB_FP64_IEEE one correctly rounded square root and one correctly rounded
+ *               division (the paper's "SQRT+DIV"); the slow reference.
+ *  CB_FP32_RSQ  the FP32 hardware estimate alone, no refinement (the
+ *               analogue of the paper's lowest-accuracy "RSQRT14"). */
+typedef enum { CB_FP64 = 0, CB_MIXED = 1, CB_FP64_IEEE = 2, CB_FP32_RSQ = 3 } cb_precision;
+
+/* Operation codes for cb_workspace_size / cb_autotune. */
+typedef enum { CB_OP_FORCES = 0, CB_OP_ENERGY = 1, CB_OP_MD_STEP = 2, CB_OP_MD_RUN = 3,
+               CB_OP_HVP = 4, CB_OP_ADJOINT = 5 } cb_op;
+
+/* md_run flags. */
+#define CB_INIT_ACCEL 1u /* compute a(r_0, t0) before the first step instead of using s->a* */
+
+/* md_adjoint_step flags. */
+#define CB_ADJ_FINAL 1u  /* only add the trap-frequency term of (r, la); no HVP, no update */
+
+/* Trap (host struct, passed by pointer, read during the call only).
+ *  kind 0: static pseudo-potential, k = (wx^2, wy^2, wz^2), with an optional
+ *          linear ramp of wx, wy from (wx, wy) at t_ramp0 to (wx1, wy1) at
+ *          t_ramp1, constant outside; the ramp is off when t_ramp1 <= t_ramp0.
+ *  kind 1: explicit RF drive in Mathieu form plus a static axial well:
+ *          kx = rf_a rf_omega^2/4 + rf_q rf_omega^2/2 cos(rf_omega t + rf_phase),
+ *          ky = -kx, kz = wz^2.
+ *  gamma (friction, kg/s) must be 0 in this build (CB_EUNSUPPORTED otherwise).
+ *  All frequencies in rad/s. */
+typedef struct {
+    int32_t kind;
+    double wx, wy, wz;
+    double rf_a, rf_q, rf_omega, rf_phase;
+    double gamma;
+    double wx1, wy1, t_ramp0, t_ramp1;
+} cb_trap;
+
+/* Velocity-Verlet state: nine device arrays (positions, velocities,
+ * accelerations), in/out.  For md_run with several runs they hold the runs
+ * packed one after the other (see offsets). */
+typedef struct {
+    double *x, *y, *z, *vx, *vy, *vz, *ax, *ay, *az;
+} cb_state;
+
+/* Size in bytes of the workspace the call `op` needs for n ions (n_total for
+ * md_run), nrun runs, nvec HVP vectors and precision prec.  0 on bad input. */
+size_t cb_workspace_size(int32_t op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec);
+
+/* Forces F_i (N) on all n ions (eq. (1), Coulomb term times m; section 3
+ * double loop).  x, y, z, q: inputs (m, C).  fx, fy, fz: outputs, must not
+ * alias the inputs.  n = 1 gives zero force.  eps2 >= 0 (m^2). */
+cb_status coulomb_forces(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                         double eps2, int32_t prec, double* fx, double* fy, double* fz,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* The first stage of coulomb_forces on its own: the all-pairs kernel writes
+ * its j-split partial force sums (before the fixed-order sum over splits and
+ * the k_C q_i scaling) into the start of ws, as [splits][3][n] doubles;
+ * *splits_out (host) receives the number of splits.  For timing the pair loop
+ * and for callers that reduce the partials themselves. */
+cb_status coulomb_pair_stage(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                             double eps2, int32_t prec, int32_t* splits_out, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* Coulomb energy U_C (J) into u_out[0] (device, one double).  Summed in a
+ * fixed order (deterministic). */
+cb_status coulomb_energy(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                         double eps2, int32_t prec, double* u_out, void* ws, size_t ws_bytes, void* stream);
+
+/* One velocity-Verlet step from time t (section 2): s holds (r_n, v_n, a_n)
+ * on entry and (r_{n+1}, v_{n+1}, a_{n+1}) on return, with a_{n+1} taken at
+ * t + dt.  q (C), m (kg): per-ion charges and masses.  dt > 0. */
+cb_status md_step(int64_t n, const cb_state* s, const double* q, const double* m, const cb_trap* trap,
+                  double t, double dt, double eps2, int32_t prec, void* ws, size_t ws_bytes, void* stream);
+
+/* nsteps velocity-Verlet steps of nrun independent runs packed in s, q, m:
+ * run r owns ions offsets[r] .. offsets[r+1]-1 (offsets: host, nrun+1
+ * entries, offsets[0] = 0, strictly increasing) and follows traps[r] (host,
+ * nrun entries).  Step k of every run is at time t0 + k dt.  With flags &
+ * CB_INIT_ACCEL, a_0 = a(r_0, t0) is computed first; otherwise s->a* must
+ * hold a_0.  When energies is non-NULL (device, [nrun][nsteps/every + 1][4])
+ * it receives (K, U_C, U_trap, K + U_C + U_trap) of steps 0, every, 2 every,
+ * ..., for each run; every >= 1 then.
+ * nrun = 1 runs the multi-workgroup step kernels (any n); nrun > 1 runs the
+ * batched persistent kernel, one workgroup per run, which needs every run to
+ * hold at most 4096 ions (CB_EUNSUPPORTED otherwise). */
+cb_status md_run(int32_t nrun, const int64_t* offsets, const cb_state* s, const double* q, const double* m,
+                 const cb_trap* traps, double t0, double dt, int64_t nsteps, double eps2, int32_t prec,
+                 uint32_t flags, double* energies, int64_t every, void* ws, size_t ws_bytes, void* stream);
+
+/* Hessian-vector products of U = U_C (+ U_trap(t) when m is non-NULL) with
+ * nvec vectors v (device, [nvec][3][n]: x block, y block, z block per vector)
+ * into hv (same layout, must not alias v):
+ *   (H v)_i = k_C q_i sum_{j != i} q_j [3 d (d . (v_i - v_j)) s^5 - (v_i - v_j) s^3]
+ *             + m_i k(t) v_i,     d = r_i - r_j, s = (|d|^2 + eps2)^{-1/2}.
+ * (Not in the paper: the second derivative of its eq. (1) energy, used for
+ * normal modes and trajectory gradients.)  1 <= nvec <= 8. */
+cb_status coulomb_hvp(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                      int32_t nvec, const double* v, double* hv, const double* m, const cb_trap* trap,
+                      double t, double eps2, int32_t prec, void* ws, size_t ws_bytes, void* stream);
+
+/* One step of the discrete adjoint (reverse mode) of md_step, for a static
+ * pseudo-potential trap (kind 0, no ramp).  x, y, z hold r_{n+1}; lam
+ * (device, [9][n]) holds the adjoints (l_r, l_v, l_a) of (r_{n+1}, v_{n+1},
+ * a_{n+1}) on entry and those of (r_n, v_n, a_n) on return:
+ *   la* = la + dt/2 lv;  lr* = lr + J^T la*,  J = da/dr at r_{n+1};
+ *   dldw[c] += sum_i (-2 w_c r_ic) la*_ic   (c = x, y, z; dldw device, 3 doubles);
+ *   lr <- lr*;  lv <- lv + dt lr*;  la <- dt/2 lv + dt^2/2 lr*  (old lv).
+ * With flags & CB_ADJ_FINAL it only adds sum_i (-2 w_c r_ic) la_ic (the a_0
+ * term) and leaves lam unchanged. */
+cb_status md_adjoint_step(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                          const double* m, const cb_trap* trap, double dt, double eps2, int32_t prec,
+                          uint32_t flags, double* lam, double* dldw, void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronises `stream`, writes the device flag word to *flags_out (bit 0:
+ * a non-finite value was produced since the last poll), clears it, and
+ * returns CB_ENONFINITE when bit 0 was set, CB_OK otherwise. */
+cb_status cb_poll_flags(void* stream, uint32_t* flags_out);
+
+/* Thread-local description of the last error ("" if none). */
+const char* cb_last_error(void);
+
+/* Times the candidate launch configurations (i-particles per lane, workgroup
+ * size, j-split count) of `op` at n ions and precision prec on the current
+ * device, keeps the fastest for all later calls with n in the same
+ * power-of-two bucket, and, when cache_path is non-NULL, merges it into that
+ * JSON-lines file.  Uses synthetic inputs it allocates itself (this call, and
+ * cb_load_tuning, are the only ones that allocate).  Synchronous. */
+cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_path);
+
+/* Loads tuned configurations written by cb_autotune (missing file: CB_OK). */
+cb_status cb_load_tuning(const char* cache_path);
+
+/* The launch configuration the next call of `op` at (n, prec) will use:
+ * out[0] = i-particles per lane, out[1] = workgroup size, out[2] = j-splits,
+ * out[3] = 1 if it came from tuning. */
+cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[4]);
+
+/* Forces the launch configuration for (op, n bucket, prec); p, wg, splits as
+ * in cb_get_config.  p = wg = splits = 0 removes a forced or tuned entry (back
+ * to the built-in heuristic).  CB_EINVAL if unsupported. */
+cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t p, int32_t wg, int32_t splits);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COULOMB_MI355X_H */

@@ -1,0 +1,229 @@
+// Host side of libcoulomb_mi355x.so: argument checking, workspace layout,
+// launch-configuration table, kernel dispatch.  Declarations and the contract
+// of every entry point are in include/coulomb.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "coulomb.h"
+#include "internal.hpp"
+
+__device__ unsigned int g_cb_flags;
+
+namespace cb {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string t_err;
+
+cb_status fail(cb_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return st;
+}
+
+cb_status ok() {
+    t_err.clear();
+    return CB_OK;
+}
+
+cb_status check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CB_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return CB_OK;
+}
+
+unsigned* flags_ptr() {
+    static std::mutex mu;
+    static std::map<int, unsigned*> per_dev;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = per_dev.find(dev);
+    if (it != per_dev.end()) return it->second;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_cb_flags)) != hipSuccess) return nullptr;
+    per_dev[dev] = static_cast<unsigned*>(p);
+    return static_cast<unsigned*>(p);
+}
+
+// ------------------------------------------------------- configurations
+static std::mutex g_cfg_mu;
+static std::map<long long, LaunchCfg> g_cfg;
+
+int n_bucket(int64_t n) {
+    int b = 0;
+    while ((int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+static long long cfg_key(int op, int prec, int64_t n) {
+    return ((long long)op << 40) | ((long long)prec << 32) | (long long)n_bucket(n);
+}
+
+// Heuristic default: enough i-particles per lane for instruction-level
+// parallelism once n is large, and enough j-splits that the launch holds
+// about two waves per SIMD (256 CUs x 4 SIMDs).
+LaunchCfg default_cfg(int op, int64_t n, int prec) {
+    LaunchCfg c;
+    c.wg = 256;
+    c.p = n >= 16384 ? 4 : (n >= 4096 ? 2 : 1);
+    if (op == CB_OP_HVP || op == CB_OP_ADJOINT) c.p = n >= 8192 ? 2 : 1;
+    const int64_t waves = (n + 64 * c.p - 1) / (64 * c.p);
+    int64_t s = (2048 + waves - 1) / waves;
+    s = std::max<int64_t>(1, std::min<int64_t>(s, kMaxSplits));
+    s = std::min<int64_t>(s, std::max<int64_t>(1, n / 64));
+    c.splits = (int)s;
+    c.tuned = 0;
+    (void)prec;
+    return c;
+}
+
+LaunchCfg get_cfg(int op, int64_t n, int prec) {
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    auto it = g_cfg.find(cfg_key(op, prec, n));
+    if (it != g_cfg.end()) return it->second;
+    return default_cfg(op, n, prec);
+}
+
+void put_cfg(int op, int64_t n, int prec, LaunchCfg c) {
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    g_cfg[cfg_key(op, prec, n)] = c;
+}
+
+void drop_cfg(int op, int64_t n, int prec) {
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    g_cfg.erase(cfg_key(op, prec, n));
+}
+
+bool valid_cfg(int op, const LaunchCfg& c) {
+    const bool p_ok = (op == CB_OP_HVP || op == CB_OP_ADJOINT) ? (c.p == 1 || c.p == 2)
+                                                                 : (c.p == 1 || c.p == 2 || c.p == 4);
+    return p_ok && (c.wg == 64 || c.wg == 128 || c.wg == 256) && c.splits >= 1 && c.splits <= kMaxSplits;
+}
+
+// Actual j-range per split for a requested split count (multiple of 8).
+int split_len(int64_t n, int splits) {
+    int64_t len = (n + splits - 1) / splits;
+    len = (len + 7) / 8 * 8;
+    return (int)std::max<int64_t>(len, 8);
+}
+
+int n_splits(int64_t n, int jlen) { return (int)((n + jlen - 1) / jlen); }
+
+// ------------------------------------------------------------- workspace
+static size_t al(size_t b) { return (b + 255) / 256 * 256; }
+
+WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec) {
+    WsLayout L{};
+    const size_t N = (size_t)n;
+    const size_t nv = (size_t)std::max(1, (int)nvec);
+    size_t off = 0;
+    const bool batched = (op == CB_OP_MD_RUN && nrun > 1);
+    const bool hv = (op == CB_OP_HVP || op == CB_OP_ADJOINT);
+    if (!batched) {
+        L.part = off;
+        off += al(sizeof(double) * (size_t)kMaxSplits * 3 * (hv ? nv : 1) * N);
+        L.ppot = off;
+        if (op == CB_OP_ENERGY || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN)
+            off += al(sizeof(double) * (size_t)kMaxSplits * N);
+        L.eblk = off;
+        off += al(sizeof(double) * 3 * (N / kEpiBlock + 2));
+        L.aux = off;
+        if (op == CB_OP_ADJOINT) off += al(sizeof(double) * 3 * N);
+    } else {
+        L.batch = off;
+        off += al((sizeof(int64_t) * 2 + sizeof(cb_trap) + sizeof(int)) * (size_t)nrun + 64);
+    }
+    L.total = off + 256;
+    return L;
+}
+
+bool trap_ok(const cb_trap* t, const char* who, cb_status* st) {
+    if (!t) {
+        *st = fail(CB_EINVAL, "%s: trap is NULL", who);
+        return false;
+    }
+    const double v[] = {t->wx, t->wy, t->wz, t->rf_a, t->rf_q, t->rf_omega, t->rf_phase, t->gamma,
+                        t->wx1, t->wy1, t->t_ramp0, t->t_ramp1};
+    for (double d : v)
+        if (!std::isfinite(d)) {
+            *st = fail(CB_EINVAL, "%s: non-finite trap parameter", who);
+            return false;
+        }
+    if (t->kind != 0 && t->kind != 1) {
+        *st = fail(CB_EINVAL, "%s: trap kind must be 0 or 1", who);
+        return false;
+    }
+    if (t->gamma != 0.0) {
+        *st = fail(CB_EUNSUPPORTED, "%s: friction (gamma != 0) is not supported", who);
+        return false;
+    }
+    return true;
+}
+
+}  // namespace cb
+
+using namespace cb;
+
+// ======================================================================= ABI
+extern "C" {
+
+const char* cb_last_error(void) { return t_err.c_str(); }
+
+size_t cb_workspace_size(int32_t op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec) {
+    if (n < 1 || op < 0 || op > CB_OP_ADJOINT || prec < 0 || prec > CB_FP32_RSQ) return 0;
+    if (op == CB_OP_HVP && (nvec < 1 || nvec > kMaxVec)) return 0;
+    return ws_layout(op, n, nrun, nvec).total;
+}
+
+cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[4]) {
+    if (!out || n < 1 || op < 0 || op > CB_OP_ADJOINT) return fail(CB_EINVAL, "cb_get_config: bad argument");
+    LaunchCfg c = get_cfg(op, n, prec);
+    out[0] = c.p;
+    out[1] = c.wg;
+    out[2] = c.splits;
+    out[3] = c.tuned;
+    return ok();
+}
+
+cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t p, int32_t wg, int32_t splits) {
+    LaunchCfg c{p, wg, splits, 1};
+    if (p == 0 && wg == 0 && splits == 0 && n >= 1 && op >= 0 && op <= CB_OP_ADJOINT) {
+        drop_cfg(op, n, prec);
+        return ok();
+    }
+    if (n < 1 || op < 0 || op > CB_OP_ADJOINT || !valid_cfg(op, c))
+        return fail(CB_EINVAL, "cb_set_config: unsupported configuration p=%d wg=%d splits=%d", p, wg, splits);
+    put_cfg(op, n, prec, c);
+    return ok();
+}
+
+cb_status cb_poll_flags(void* stream, uint32_t* flags_out) {
+    if (!flags_out) return fail(CB_EINVAL, "cb_poll_flags: flags_out is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(CB_EHIP, "cb_poll_flags: stream sync failed");
+    unsigned* d = flags_ptr();
+    if (!d) return fail(CB_EHIP, "cb_poll_flags: flag symbol not found");
+    unsigned v = 0;
+    if (hipMemcpy(&v, d, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(CB_EHIP, "cb_poll_flags: read failed");
+    unsigned z = 0;
+    if (hipMemcpy(d, &z, sizeof z, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(CB_EHIP, "cb_poll_flags: clear failed");
+    *flags_out = v;
+    if (v & 1u) return fail(CB_ENONFINITE, "non-finite values were produced");
+    return ok();
+}
+
+}  // extern "C"

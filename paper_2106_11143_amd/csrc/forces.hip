@@ -1,0 +1,273 @@
+// Entry points coulomb_forces, coulomb_energy, md_step and md_run (single
+// run): argument checks, workspace carving and the launch sequence of the
+// pair kernel and the element-wise epilogue.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "internal.hpp"
+#include "step_kernels.hpp"
+
+namespace cb {
+
+static bool overlaps(const void* a, const void* b, int64_t n) {
+    if (!a || !b) return false;
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    const int64_t bytes = n * (int64_t)sizeof(double);
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+static cb_status check_common(const char* who, int64_t n, int32_t prec, double eps2, void* ws, size_t ws_bytes,
+                              size_t need) {
+    if (n < 1 || n > (int64_t(1) << 28)) return fail(CB_EINVAL, "%s: n = %lld out of range [1, 2^28]", who, (long long)n);
+    if (prec < CB_FP64 || prec > CB_FP32_RSQ) return fail(CB_EINVAL, "%s: unknown precision %d", who, prec);
+    if (!(eps2 >= 0.0) || !std::isfinite(eps2)) return fail(CB_EINVAL, "%s: eps2 must be finite and >= 0", who);
+    if (!ws) return fail(CB_EINVAL, "%s: workspace is NULL", who);
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(CB_EINVAL, "%s: workspace not 256-byte aligned", who);
+    if (ws_bytes < need)
+        return fail(CB_ENOWS, "%s: workspace has %zu bytes, needs %zu", who, ws_bytes, need);
+    return CB_OK;
+}
+
+static double* at(void* ws, size_t off) { return reinterpret_cast<double*>(static_cast<char*>(ws) + off); }
+
+struct PairRun {
+    LaunchCfg cfg;
+    int jlen, S;
+};
+
+static PairRun plan(int op, int64_t n, int prec) {
+    PairRun r;
+    r.cfg = get_cfg(op, n, prec);
+    r.jlen = split_len(n, r.cfg.splits);
+    r.S = n_splits(n, r.jlen);
+    return r;
+}
+
+// Single-run velocity-Verlet driver shared by md_step and md_run.
+static cb_status md_single(int64_t n, const cb_state* s, const double* q, const double* m, const cb_trap* trap,
+                           double t0, double dt, int64_t nsteps, double eps2, int32_t prec, uint32_t flags,
+                           double* energies, int64_t every, void* ws, int op, hipStream_t st) {
+    const WsLayout L = ws_layout(op, n, 1, 1);
+    const PairRun pr = plan(op, n, prec);
+    double* part = at(ws, L.part);
+    double* ppot = at(ws, L.ppot);
+    double* eblk = at(ws, L.eblk);
+    unsigned* fl = flags_ptr();
+    if (!fl) return fail(CB_EHIP, "md_run: device flag symbol not found");
+    const int nb = (int)((n + kEpiThreads - 1) / kEpiThreads);
+
+    EpiParams E{};
+    E.n = (int)n;
+    E.S = pr.S;
+    E.part = part;
+    E.ppot = ppot;
+    E.q = q;
+    E.m = m;
+    E.x = s->x; E.y = s->y; E.z = s->z;
+    E.vx = s->vx; E.vy = s->vy; E.vz = s->vz;
+    E.ax = s->ax; E.ay = s->ay; E.az = s->az;
+    E.trap = *trap;
+    E.t0 = t0;
+    E.dt = dt;
+    E.eblk = eblk;
+    E.flags = fl;
+    cb_status rc;
+    const bool rec0 = energies && every > 0;
+    const bool init = (flags & CB_INIT_ACCEL) != 0;
+
+    // Step 0: initial acceleration and/or energies, then the first drift.
+    if (init || rec0) {
+        if ((rc = launch_pair(prec, pr.cfg, init, rec0, (int)n, s->x, s->y, s->z, q, eps2, pr.jlen, part, ppot, st)))
+            return rc;
+    }
+    E.step = 0;
+    E.mode = (init ? EPI_ACCEL : 0u) | (rec0 ? EPI_ENERGY : 0u) | (nsteps > 0 ? EPI_DRIFT : 0u);
+    if (E.mode) {
+        k_epilogue<<<nb, kEpiThreads, 0, st>>>(E);
+        if ((rc = check_launch("k_epilogue"))) return rc;
+    }
+    if (rec0) {
+        k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, eblk, energies, 0);
+        if ((rc = check_launch("k_energy_final"))) return rc;
+    }
+    for (int64_t k = 1; k <= nsteps; ++k) {
+        const bool rec = rec0 && (k % every == 0);
+        if ((rc = launch_pair(prec, pr.cfg, true, rec, (int)n, s->x, s->y, s->z, q, eps2, pr.jlen, part, ppot, st)))
+            return rc;
+        E.step = k;
+        E.mode = EPI_KICK | (rec ? EPI_ENERGY : 0u) | (k < nsteps ? EPI_DRIFT : 0u);
+        k_epilogue<<<nb, kEpiThreads, 0, st>>>(E);
+        if ((rc = check_launch("k_epilogue"))) return rc;
+        if (rec) {
+            k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, eblk, energies + 4 * (k / every), 0);
+            if ((rc = check_launch("k_energy_final"))) return rc;
+        }
+    }
+    return ok();
+}
+
+static bool state_ok(const cb_state* s, int64_t n, const double* q, const double* m, const char* who,
+                     cb_status* st) {
+    if (!s) {
+        *st = fail(CB_EINVAL, "%s: state is NULL", who);
+        return false;
+    }
+    double* arr[9] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->ax, s->ay, s->az};
+    for (int a = 0; a < 9; ++a) {
+        if (!arr[a]) {
+            *st = fail(CB_EINVAL, "%s: state array %d is NULL", who, a);
+            return false;
+        }
+        for (int b = a + 1; b < 9; ++b)
+            if (overlaps(arr[a], arr[b], n)) {
+                *st = fail(CB_EINVAL, "%s: state arrays %d and %d overlap", who, a, b);
+                return false;
+            }
+        if (overlaps(arr[a], q, n) || overlaps(arr[a], m, n)) {
+            *st = fail(CB_EINVAL, "%s: state array %d overlaps q or m", who, a);
+            return false;
+        }
+    }
+    if (!q || !m) {
+        *st = fail(CB_EINVAL, "%s: q or m is NULL", who);
+        return false;
+    }
+    return true;
+}
+
+}  // namespace cb
+
+using namespace cb;
+
+extern "C" {
+
+cb_status coulomb_forces(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                         double eps2, int32_t prec, double* fx, double* fy, double* fz, void* ws, size_t ws_bytes,
+                         void* stream) {
+    const WsLayout L = ws_layout(CB_OP_FORCES, n > 0 ? n : 1, 1, 1);
+    cb_status rc = check_common("coulomb_forces", n, prec, eps2, ws, ws_bytes, L.total);
+    if (rc) return rc;
+    if (!x || !y || !z || !q || !fx || !fy || !fz) return fail(CB_EINVAL, "coulomb_forces: NULL array");
+    const void* in[4] = {x, y, z, q};
+    const void* out[3] = {fx, fy, fz};
+    for (auto o : out) {
+        for (auto i : in)
+            if (overlaps(o, i, n)) return fail(CB_EINVAL, "coulomb_forces: output aliases an input");
+    }
+    if (overlaps(fx, fy, n) || overlaps(fx, fz, n) || overlaps(fy, fz, n))
+        return fail(CB_EINVAL, "coulomb_forces: outputs overlap");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const PairRun pr = plan(CB_OP_FORCES, n, prec);
+    double* part = at(ws, L.part);
+    if ((rc = launch_pair(prec, pr.cfg, true, false, (int)n, x, y, z, q, eps2, pr.jlen, part, nullptr, st)))
+        return rc;
+    EpiParams E{};
+    E.n = (int)n;
+    E.S = pr.S;
+    E.part = part;
+    E.q = q;
+    E.fx = fx;
+    E.fy = fy;
+    E.fz = fz;
+    E.mode = EPI_FORCES;
+    E.flags = flags_ptr();
+    if (!E.flags) return fail(CB_EHIP, "coulomb_forces: device flag symbol not found");
+    k_epilogue<<<(int)((n + kEpiThreads - 1) / kEpiThreads), kEpiThreads, 0, st>>>(E);
+    if ((rc = check_launch("k_epilogue"))) return rc;
+    return ok();
+}
+
+cb_status coulomb_pair_stage(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                             double eps2, int32_t prec, int32_t* splits_out, void* ws, size_t ws_bytes,
+                             void* stream) {
+    const WsLayout L = ws_layout(CB_OP_FORCES, n > 0 ? n : 1, 1, 1);
+    cb_status rc = check_common("coulomb_pair_stage", n, prec, eps2, ws, ws_bytes, L.total);
+    if (rc) return rc;
+    if (!x || !y || !z || !q || !splits_out) return fail(CB_EINVAL, "coulomb_pair_stage: NULL argument");
+    const PairRun pr = plan(CB_OP_FORCES, n, prec);
+    if ((rc = launch_pair(prec, pr.cfg, true, false, (int)n, x, y, z, q, eps2, pr.jlen, at(ws, L.part), nullptr,
+                          static_cast<hipStream_t>(stream))))
+        return rc;
+    *splits_out = pr.S;
+    return ok();
+}
+
+cb_status coulomb_energy(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                         double eps2, int32_t prec, double* u_out, void* ws, size_t ws_bytes, void* stream) {
+    const WsLayout L = ws_layout(CB_OP_ENERGY, n > 0 ? n : 1, 1, 1);
+    cb_status rc = check_common("coulomb_energy", n, prec, eps2, ws, ws_bytes, L.total);
+    if (rc) return rc;
+    if (!x || !y || !z || !q || !u_out) return fail(CB_EINVAL, "coulomb_energy: NULL argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const PairRun pr = plan(CB_OP_ENERGY, n, prec);
+    double* ppot = at(ws, L.ppot);
+    double* eblk = at(ws, L.eblk);
+    if ((rc = launch_pair(prec, pr.cfg, false, true, (int)n, x, y, z, q, eps2, pr.jlen, nullptr, ppot, st)))
+        return rc;
+    EpiParams E{};
+    E.n = (int)n;
+    E.S = pr.S;
+    E.ppot = ppot;
+    E.q = q;
+    E.mode = EPI_ENERGY | EPI_UC_ONLY;
+    E.eblk = eblk;
+    E.flags = flags_ptr();
+    if (!E.flags) return fail(CB_EHIP, "coulomb_energy: device flag symbol not found");
+    const int nb = (int)((n + kEpiThreads - 1) / kEpiThreads);
+    k_epilogue<<<nb, kEpiThreads, 0, st>>>(E);
+    if ((rc = check_launch("k_epilogue"))) return rc;
+    k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, eblk, u_out, 1);
+    if ((rc = check_launch("k_energy_final"))) return rc;
+    return ok();
+}
+
+cb_status md_step(int64_t n, const cb_state* s, const double* q, const double* m, const cb_trap* trap, double t,
+                  double dt, double eps2, int32_t prec, void* ws, size_t ws_bytes, void* stream) {
+    const WsLayout L = ws_layout(CB_OP_MD_STEP, n > 0 ? n : 1, 1, 1);
+    cb_status rc = check_common("md_step", n, prec, eps2, ws, ws_bytes, L.total);
+    if (rc) return rc;
+    if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t)) return fail(CB_EINVAL, "md_step: need finite t and dt > 0");
+    if (!trap_ok(trap, "md_step", &rc)) return rc;
+    if (!state_ok(s, n, q, m, "md_step", &rc)) return rc;
+    return md_single(n, s, q, m, trap, t, dt, 1, eps2, prec, 0u, nullptr, 0, ws, CB_OP_MD_STEP,
+                     static_cast<hipStream_t>(stream));
+}
+
+cb_status md_run(int32_t nrun, const int64_t* offsets, const cb_state* s, const double* q, const double* m,
+                 const cb_trap* traps, double t0, double dt, int64_t nsteps, double eps2, int32_t prec,
+                 uint32_t flags, double* energies, int64_t every, void* ws, size_t ws_bytes, void* stream) {
+    if (nrun < 1 || !offsets) return fail(CB_EINVAL, "md_run: need nrun >= 1 and host offsets");
+    if (offsets[0] != 0) return fail(CB_EINVAL, "md_run: offsets[0] must be 0");
+    for (int r = 0; r < nrun; ++r)
+        if (offsets[r + 1] <= offsets[r]) return fail(CB_EINVAL, "md_run: offsets must increase strictly");
+    const int64_t n = offsets[nrun];
+    const WsLayout L = ws_layout(CB_OP_MD_RUN, n, nrun, 1);
+    cb_status rc = check_common("md_run", n, prec, eps2, ws, ws_bytes, L.total);
+    if (rc) return rc;
+    if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t0)) return fail(CB_EINVAL, "md_run: need finite t0 and dt > 0");
+    if (nsteps < 0) return fail(CB_EINVAL, "md_run: nsteps < 0");
+    if (energies && every < 1) return fail(CB_EINVAL, "md_run: every must be >= 1 when energies are requested");
+    if (flags & ~CB_INIT_ACCEL) return fail(CB_EINVAL, "md_run: unknown flags 0x%x", flags);
+    if (!traps) return fail(CB_EINVAL, "md_run: traps is NULL");
+    for (int r = 0; r < nrun; ++r)
+        if (!trap_ok(&traps[r], "md_run", &rc)) return rc;
+    if (!state_ok(s, n, q, m, "md_run", &rc)) return rc;
+    if (energies) {
+        const int64_t nrec = nsteps / every + 1;
+        double* arr[9] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->ax, s->ay, s->az};
+        for (auto a : arr)
+            if (overlaps(a, energies, std::max<int64_t>(n, 4 * nrec * nrun)))
+                return fail(CB_EINVAL, "md_run: energies overlaps the state");
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (nrun > 1)
+        return md_run_batched(nrun, offsets, s, q, m, traps, t0, dt, nsteps, eps2, prec, flags, energies, every, ws,
+                              ws_bytes, st);
+    return md_single(n, s, q, m, &traps[0], t0, dt, nsteps, eps2, prec, flags, energies, every, ws, CB_OP_MD_RUN, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// Host-side declarations shared by the translation units of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "coulomb.h"
+
+namespace cb {
+
+constexpr int kMaxSplits = 64;       // j-splits per launch
+constexpr int kMaxVec = 8;           // HVP vectors per call
+constexpr int kMaxBatchIons = 4096;  // ions per run in the batched kernel (LDS bound)
+constexpr int kEpiBlock = 256;       // threads per element-wise block
+
+struct LaunchCfg {
+    int p;       // i-particles per lane
+    int wg;      // threads per workgroup
+    int splits;  // requested j-splits
+    int tuned;   // 1 if set by tuning or cb_set_config
+};
+
+struct WsLayout {
+    size_t part, ppot, eblk, aux, batch, total;
+};
+
+cb_status fail(cb_status st, const char* fmt, ...);
+cb_status ok();
+cb_status check_launch(const char* what);
+unsigned* flags_ptr();
+
+int n_bucket(int64_t n);
+LaunchCfg default_cfg(int op, int64_t n, int prec);
+LaunchCfg get_cfg(int op, int64_t n, int prec);
+void put_cfg(int op, int64_t n, int prec, LaunchCfg c);
+void drop_cfg(int op, int64_t n, int prec);
+bool valid_cfg(int op, const LaunchCfg& c);
+int split_len(int64_t n, int splits);
+int n_splits(int64_t n, int jlen);
+WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec);
+
+bool trap_ok(const cb_trap* t, const char* who, cb_status* st);
+
+// Launches of the pair kernels (pair.hip).
+cb_status launch_pair(int prec, const LaunchCfg& c, bool force, bool pot, int n, const double* x,
+                      const double* y, const double* z, const double* q, double eps2, int jlen, double* part,
+                      double* ppot, hipStream_t st);
+cb_status launch_hvp(int prec, const LaunchCfg& c, int nvec, int n, const double* x, const double* y,
+                     const double* z, const double* q, const double* v, double eps2, int jlen, double* part,
+                     hipStream_t st);
+
+// Batched persistent md_run (batched.hip).
+cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s, const double* q,
+                         const double* m, const cb_trap* traps, double t0, double dt, int64_t nsteps,
+                         double eps2, int32_t prec, uint32_t flags, double* energies, int64_t every, void* ws,
+                         size_t ws_bytes, hipStream_t st);
+
+}  // namespace cb

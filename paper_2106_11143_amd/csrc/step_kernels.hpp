@@ -1,0 +1,212 @@
+// Element-wise kernels around the pair loop: fixed-order sum of the j-split
+// partials, scaling to forces, trap, velocity-Verlet kick and drift (paper,
+// section 2), per-ion energy terms and their deterministic reduction.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "coulomb.h"
+
+namespace cb {
+
+// k_C = 1 / (4 pi eps0), CODATA 2018 vacuum permittivity.
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kCoulomb = 1.0 / (4.0 * kPi * kEps0);
+
+constexpr int kEpiThreads = 256;
+
+struct TrapK {
+    double kx, ky, kz;
+};
+
+// Spring constants per unit mass of the trap at time t (see cb_trap).
+__device__ __forceinline__ TrapK trap_k(const cb_trap& tr, double t) {
+    TrapK k;
+    if (tr.kind == 1) {
+        const double w2 = tr.rf_omega * tr.rf_omega;
+        const double kx = tr.rf_a * w2 * 0.25 + tr.rf_q * w2 * 0.5 * cos(tr.rf_omega * t + tr.rf_phase);
+        k.kx = kx;
+        k.ky = -kx;
+        k.kz = tr.wz * tr.wz;
+        return k;
+    }
+    double wx = tr.wx, wy = tr.wy;
+    if (tr.t_ramp1 > tr.t_ramp0) {
+        double s = (t - tr.t_ramp0) / (tr.t_ramp1 - tr.t_ramp0);
+        s = fmin(fmax(s, 0.0), 1.0);
+        wx = tr.wx + s * (tr.wx1 - tr.wx);
+        wy = tr.wy + s * (tr.wy1 - tr.wy);
+    }
+    k.kx = wx * wx;
+    k.ky = wy * wy;
+    k.kz = tr.wz * tr.wz;
+    return k;
+}
+
+// Time of step `step` of a run started at t0 (one rounding per operation,
+// never contracted, so every kernel computes the same value).
+__device__ __forceinline__ double step_time(double t0, double dt, long long step) {
+    return __dadd_rn(t0, __dmul_rn(static_cast<double>(step), dt));
+}
+
+enum : unsigned {
+    EPI_FORCES = 1u,   // write F to fx, fy, fz
+    EPI_ACCEL = 2u,    // a <- F/m + trap (initial acceleration)
+    EPI_KICK = 4u,     // a_new = F/m + trap; v += dt/2 (a + a_new); a <- a_new
+    EPI_DRIFT = 8u,    // r += v dt + a dt^2/2 (after any kick)
+    EPI_ENERGY = 16u,  // per-block sums of K, U_C, U_trap of the resulting state
+    EPI_UC_ONLY = 32u  // energy: only U_C (no m, v, trap)
+};
+
+struct EpiParams {
+    int n, S;
+    const double* part;  // [S][3][n]
+    const double* ppot;  // [S][n]
+    const double* q;
+    const double* m;
+    double *x, *y, *z, *vx, *vy, *vz, *ax, *ay, *az;
+    double *fx, *fy, *fz;
+    cb_trap trap;
+    double t0, dt;
+    long long step;  // the trap is taken at step_time(t0, dt, step)
+    unsigned mode;
+    double* eblk;  // [gridDim.x][3]
+    unsigned* flags;
+};
+
+// Fixed-order tree sum of three values over the 256 threads of a block; the
+// result is valid in thread 0.
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c) {
+    __shared__ double sh[3][kEpiThreads];
+    const int t = threadIdx.x;
+    sh[0][t] = a;
+    sh[1][t] = b;
+    sh[2][t] = c;
+    __syncthreads();
+    for (int w = kEpiThreads / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            sh[0][t] += sh[0][t + w];
+            sh[1][t] += sh[1][t + w];
+            sh[2][t] += sh[2][t + w];
+        }
+        __syncthreads();
+    }
+    a = sh[0][0];
+    b = sh[1][0];
+    c = sh[2][0];
+}
+
+__device__ __forceinline__ bool finite3(double a, double b, double c) {
+    return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c);
+}
+
+__global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
+    const int i = blockIdx.x * kEpiThreads + threadIdx.x;
+    double eK = 0.0, eC = 0.0, eT = 0.0;
+    const unsigned mode = P.mode;
+    if (i < P.n) {
+        const int n = P.n;
+        double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+        const bool need_f = (mode & (EPI_FORCES | EPI_ACCEL | EPI_KICK)) != 0;
+        const bool need_p = (mode & EPI_ENERGY) && P.ppot != nullptr;
+        if (need_f)
+            for (int s = 0; s < P.S; ++s) {
+                sx += P.part[(size_t)(s * 3 + 0) * n + i];
+                sy += P.part[(size_t)(s * 3 + 1) * n + i];
+                sz += P.part[(size_t)(s * 3 + 2) * n + i];
+            }
+        if (need_p)
+            for (int s = 0; s < P.S; ++s) sp += P.ppot[(size_t)s * n + i];
+        const double c = kCoulomb * P.q[i];
+        const double Fx = c * sx, Fy = c * sy, Fz = c * sz;
+        bool ok = true;
+        if (mode & EPI_FORCES) {
+            P.fx[i] = Fx;
+            P.fy[i] = Fy;
+            P.fz[i] = Fz;
+            ok = finite3(Fx, Fy, Fz);
+        }
+        if (mode & EPI_UC_ONLY) {
+            eC = 0.5 * c * sp;
+            ok = ok && __builtin_isfinite(eC);
+        } else if (mode & (EPI_ACCEL | EPI_KICK | EPI_DRIFT | EPI_ENERGY)) {
+            double x = P.x[i], y = P.y[i], z = P.z[i];
+            double vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
+            double ax = P.ax[i], ay = P.ay[i], az = P.az[i];
+            const double mi = P.m[i];
+            const double t = step_time(P.t0, P.dt, P.step);
+            const TrapK k = trap_k(P.trap, t);
+            if (mode & (EPI_ACCEL | EPI_KICK)) {
+                const double anx = Fx / mi - k.kx * x;
+                const double any = Fy / mi - k.ky * y;
+                const double anz = Fz / mi - k.kz * z;
+                if (mode & EPI_KICK) {
+                    const double h = 0.5 * P.dt;
+                    vx = vx + h * (ax + anx);
+                    vy = vy + h * (ay + any);
+                    vz = vz + h * (az + anz);
+                    P.vx[i] = vx;
+                    P.vy[i] = vy;
+                    P.vz[i] = vz;
+                }
+                ax = anx;
+                ay = any;
+                az = anz;
+                P.ax[i] = ax;
+                P.ay[i] = ay;
+                P.az[i] = az;
+                ok = ok && finite3(ax, ay, az) && finite3(vx, vy, vz);
+            }
+            if (mode & EPI_ENERGY) {
+                eK = 0.5 * mi * (vx * vx + vy * vy + vz * vz);
+                eC = 0.5 * c * sp;
+                eT = 0.5 * mi * (k.kx * x * x + k.ky * y * y + k.kz * z * z);
+                ok = ok && finite3(eK, eC, eT);
+            }
+            if (mode & EPI_DRIFT) {
+                const double dt = P.dt, h2 = 0.5 * dt * dt;
+                x = x + vx * dt + h2 * ax;
+                y = y + vy * dt + h2 * ay;
+                z = z + vz * dt + h2 * az;
+                P.x[i] = x;
+                P.y[i] = y;
+                P.z[i] = z;
+                ok = ok && finite3(x, y, z);
+            }
+        }
+        if (!ok) atomicOr(P.flags, 1u);
+    }
+    if (mode & EPI_ENERGY) {
+        block_sum3(eK, eC, eT);
+        if (threadIdx.x == 0) {
+            P.eblk[blockIdx.x * 3 + 0] = eK;
+            P.eblk[blockIdx.x * 3 + 1] = eC;
+            P.eblk[blockIdx.x * 3 + 2] = eT;
+        }
+    }
+}
+
+// Sums nb block partials [nb][3] in a fixed order into out: with uc_only,
+// out[0] = U_C; otherwise out[0..3] = K, U_C, U_trap, K + U_C + U_trap.
+__global__ void __launch_bounds__(kEpiThreads) k_energy_final(int nb, const double* __restrict__ eblk,
+                                                             double* __restrict__ out, int uc_only) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int k = threadIdx.x; k < nb; k += kEpiThreads) {
+        a += eblk[k * 3 + 0];
+        b += eblk[k * 3 + 1];
+        c += eblk[k * 3 + 2];
+    }
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) {
+        if (uc_only) {
+            out[0] = b;
+        } else {
+            out[0] = a;
+            out[1] = b;
+            out[2] = c;
+            out[3] = a + b + c;
+        }
+    }
+}
+
+}  // namespace cb

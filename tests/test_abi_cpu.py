@@ -1,0 +1,126 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every function include/coulomb.h declares, sizes workspaces, keeps launch
+configurations, and rejects bad arguments before enqueueing anything (every
+call below fails validation, so no kernel is ever launched)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2106_11143_amd import api as A
+    if not os.path.exists(A.LIB_PATH):
+        from paper_2106_11143_amd import build
+        build.build(verbose=False)
+    A.lib()
+    return A
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "coulomb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_function(api):
+    names = header_functions()
+    assert {"coulomb_forces", "coulomb_energy", "md_step", "md_run", "coulomb_hvp"} <= set(names)
+    L = api.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(api.EXPORTS) == set(names)
+
+
+def test_workspace_sizes(api):
+    L = api.lib()
+    assert L.cb_workspace_size(0, 0, 1, 1, 0) == 0
+    assert L.cb_workspace_size(0, 10, 1, 1, 9) == 0
+    assert L.cb_workspace_size(4, 10, 1, 9, 0) == 0
+    f = L.cb_workspace_size(0, 100000, 1, 1, 0)
+    assert f >= 64 * 3 * 100000 * 8
+    assert L.cb_workspace_size(4, 1000, 1, 4, 0) >= 64 * 12 * 1000 * 8
+    assert L.cb_workspace_size(3, 10000, 16, 1, 0) < L.cb_workspace_size(3, 10000, 1, 1, 0)
+
+
+def test_config_roundtrip(api):
+    api.set_config("forces", 5000, "mixed", p=2, wg=128, splits=7)
+    c = api.get_config("forces", 4500, "mixed")  # same power-of-two bucket
+    assert (c["p"], c["wg"], c["splits"], c["tuned"]) == (2, 128, 7, True)
+    d = api.get_config("forces", 5000, "fp64")
+    assert not d["tuned"]
+    with pytest.raises(api.CoulombError) as e:
+        api.set_config("forces", 5000, "fp64", p=3, wg=256, splits=1)
+    assert e.value.status == api.CB_EINVAL
+    with pytest.raises(api.CoulombError):
+        api.set_config("hvp", 5000, "fp64", p=4, wg=256, splits=1)
+    with pytest.raises(api.CoulombError):
+        api.set_config("forces", 5000, "fp64", p=1, wg=256, splits=65)
+
+
+def _ws():
+    return C.c_void_p(1 << 20)  # never dereferenced: every call below fails validation first
+
+
+def test_forces_argument_errors(api):
+    L = api.lib()
+    P = C.c_void_p(1 << 21)
+    big = 1 << 40
+    # n out of range
+    assert L.coulomb_forces(0, P, P, P, P, 0.0, 0, P, P, P, _ws(), big, None) == api.CB_EINVAL
+    assert "n = 0" in api.last_error()
+    # bad precision, bad eps2
+    assert L.coulomb_forces(10, P, P, P, P, 0.0, 7, P, P, P, _ws(), big, None) == api.CB_EINVAL
+    assert L.coulomb_forces(10, P, P, P, P, -1.0, 0, P, P, P, _ws(), big, None) == api.CB_EINVAL
+    assert L.coulomb_forces(10, P, P, P, P, float("nan"), 0, P, P, P, _ws(), big, None) == api.CB_EINVAL
+    # workspace problems
+    assert L.coulomb_forces(10, P, P, P, P, 0.0, 0, P, P, P, None, big, None) == api.CB_EINVAL
+    assert L.coulomb_forces(10, P, P, P, P, 0.0, 0, P, P, P, C.c_void_p((1 << 20) + 8), big, None) == api.CB_EINVAL
+    assert L.coulomb_forces(10, P, P, P, P, 0.0, 0, P, P, P, _ws(), 100, None) == api.CB_ENOWS
+    assert "workspace" in api.last_error()
+    # NULL arrays and aliasing
+    assert L.coulomb_forces(10, None, P, P, P, 0.0, 0, P, P, P, _ws(), big, None) == api.CB_EINVAL
+    a, b = C.c_void_p(1 << 22), C.c_void_p((1 << 22) + 40)
+    o1, o2, o3 = C.c_void_p(1 << 23), C.c_void_p(1 << 24), C.c_void_p(1 << 25)
+    assert L.coulomb_forces(10, a, o1, o1, o1, 0.0, 0, b, o2, o3, _ws(), big, None) == api.CB_EINVAL
+    assert "alias" in api.last_error()
+
+
+def test_md_argument_errors(api):
+    L = api.lib()
+    big = 1 << 40
+    arrs = [C.c_void_p((k + 1) << 24) for k in range(11)]
+    s = api.State(*arrs[:9])
+    q, m = arrs[9], arrs[10]
+    tr = api.make_trap(dict(kind=0, wx=1e6, wy=1e6, wz=1e5))
+    # dt <= 0
+    assert L.md_step(10, C.byref(s), q, m, C.byref(tr), 0.0, 0.0, 0.0, 0, _ws(), big, None) == api.CB_EINVAL
+    # friction is not supported
+    tg = api.make_trap(dict(kind=0, wx=1e6, wy=1e6, wz=1e5, gamma=1e-20))
+    assert L.md_step(10, C.byref(s), q, m, C.byref(tg), 0.0, 1e-9, 0.0, 0, _ws(), big, None) == api.CB_EUNSUPPORTED
+    # non-finite trap, bad kind
+    tn = api.make_trap(dict(kind=0, wx=float("inf")))
+    assert L.md_step(10, C.byref(s), q, m, C.byref(tn), 0.0, 1e-9, 0.0, 0, _ws(), big, None) == api.CB_EINVAL
+    tk = api.make_trap(dict(kind=3))
+    assert L.md_step(10, C.byref(s), q, m, C.byref(tk), 0.0, 1e-9, 0.0, 0, _ws(), big, None) == api.CB_EINVAL
+    # overlapping state arrays
+    s2 = api.State(*([arrs[0]] * 9))
+    assert L.md_step(10, C.byref(s2), q, m, C.byref(tr), 0.0, 1e-9, 0.0, 0, _ws(), big, None) == api.CB_EINVAL
+    # md_run: offsets not increasing / not starting at 0, every < 1 with energies
+    offs = (C.c_int64 * 3)(0, 5, 5)
+    trs = (api.Trap * 2)(tr, tr)
+    assert L.md_run(2, offs, C.byref(s), q, m, trs, 0.0, 1e-9, 10, 0.0, 0, 1, None, 0, _ws(), big, None) == api.CB_EINVAL
+    offs = (C.c_int64 * 2)(1, 5)
+    assert L.md_run(1, offs, C.byref(s), q, m, trs, 0.0, 1e-9, 10, 0.0, 0, 1, None, 0, _ws(), big, None) == api.CB_EINVAL
+    offs = (C.c_int64 * 2)(0, 10)
+    en = C.c_void_p(1 << 30)
+    assert L.md_run(1, offs, C.byref(s), q, m, trs, 0.0, 1e-9, 10, 0.0, 0, 1, en, 0, _ws(), big, None) == api.CB_EINVAL
+    assert L.md_run(1, offs, C.byref(s), q, m, trs, 0.0, 1e-9, 10, 0.0, 0, 8, None, 0, _ws(), big, None) == api.CB_EINVAL
+
+
+def test_poll_flags_rejects_null(api):
+    assert api.lib().cb_poll_flags(None, None) == api.CB_EINVAL

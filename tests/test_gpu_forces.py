@@ -1,0 +1,134 @@
+"""GPU parity of coulomb_forces / coulomb_energy against the FP64 oracle
+(called through the C ABI via the Python binding)."""
+import numpy as np
+import pytest
+
+from paper_2106_11143_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_11143_amd import api as A
+    A.lib()
+    return A
+
+
+def _forces(api, d, prec, eps2=0.0):
+    from _gpu_util import dev, host
+    f = api.coulomb_forces(dev(d["x"]), dev(d["y"]), dev(d["z"]), dev(d["q"]), eps2=eps2, prec=prec)
+    return np.stack([host(t) for t in f])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "ieee", "mixed", "fp32"])
+def test_forces_cloud1024_all_precisions(api, oracle, prec):
+    from _gpu_util import PREC_TOL, per_ion_rel, report
+    d = inputs.cloud1024()
+    fx, fy, fz, kappa = oracle.forces(d["x"], d["y"], d["z"], d["q"], kappa=True)
+    ref = np.stack([fx, fy, fz])
+    F = _forces(api, d, prec)
+    err = per_ion_rel(F, ref)
+    report(f"cloud1024/{prec}", err, kappa)
+    if prec == "fp32":
+        assert np.all(err <= 2e-6 * np.maximum(kappa, 1.0))
+    else:
+        assert err.max() <= PREC_TOL[prec]
+    assert api.poll_flags() == 0
+
+
+RAGGED = [1, 2, 3, 7, 63, 64, 65, 127, 129, 255, 257, 1000, 1023, 1025, 2049]
+CONFIGS = [(1, 64, 1), (1, 256, 3), (2, 128, 64), (4, 256, 5), (4, 64, 64), (2, 256, 1)]
+
+
+@pytest.mark.parametrize("p,wg,splits", CONFIGS)
+def test_forces_ragged_sizes_and_launch_shapes(api, oracle, p, wg, splits):
+    from _gpu_util import per_ion_rel
+    for n in RAGGED:
+        g = np.random.Generator(np.random.PCG64(1000 + n))
+        d = dict(x=g.normal(0, 20e-6, n), y=g.normal(0, 20e-6, n), z=g.normal(0, 20e-6, n),
+                 q=inputs.E_CHARGE * g.choice([1.0, 2.0, -1.0], n))
+        for prec in ("fp64", "mixed"):
+            api.set_config("forces", n, prec, p=p, wg=wg, splits=splits)
+            F = _forces(api, d, prec, eps2=(1e-7) ** 2 if n % 2 else 0.0)
+            ref = np.stack(oracle.forces(d["x"], d["y"], d["z"], d["q"], eps2=(1e-7) ** 2 if n % 2 else 0.0))
+            if n == 1:
+                assert np.all(F == 0.0)
+                continue
+            err = per_ion_rel(F, ref)
+            tol = 1e-12 if prec == "fp64" else 1e-7
+            assert err.max() <= tol, (n, prec, err.max())
+            api.reset_config("forces", n, prec)
+    api.clear_workspace_cache()
+
+
+def test_forces_rf32768_full(api, oracle):
+    from _gpu_util import per_ion_rel, report
+    d = inputs.rf32768()
+    fx, fy, fz, kappa = oracle.forces(d["x"], d["y"], d["z"], d["q"], kappa=True)
+    ref = np.stack([fx, fy, fz])
+    for prec in ("fp64", "mixed"):
+        F = _forces(api, d, prec)
+        err = per_ion_rel(F, ref)
+        report(f"rf32768/{prec}", err, kappa)
+        assert err.max() <= (1e-12 if prec == "fp64" else 1e-7)
+
+
+def test_forces_cloud100k_sampled(api, oracle):
+    """Full-size workload in the default launch configuration: every GPU force
+    is computed, a sample of ions is checked against the oracle one by one,
+    and Newton's third law is checked on the whole result."""
+    from _gpu_util import per_ion_rel, report
+    d = inputs.cloud100k()
+    n = d["n"]
+    g = np.random.Generator(np.random.PCG64(77))
+    idx = np.unique(np.concatenate([np.arange(64), np.arange(n - 64, n), g.choice(n, 1500, replace=False),
+                                    np.flatnonzero(d["q"] > 1.5 * inputs.E_CHARGE)[:200]]))
+    fx, fy, fz, kappa = oracle.forces(d["x"], d["y"], d["z"], d["q"], idx=idx, kappa=True)
+    ref = np.stack([fx, fy, fz])
+    for prec in ("fp64", "mixed"):
+        F = _forces(api, d, prec)
+        err = per_ion_rel(F[:, idx], ref)
+        report(f"cloud100k/{prec} ({len(idx)} sampled)", err, kappa)
+        assert err.max() <= (1e-12 if prec == "fp64" else 1e-7)
+        tot = np.linalg.norm(F.sum(axis=1))
+        assert tot <= 1e-12 * np.linalg.norm(F, axis=0).sum()
+
+
+def test_forces_are_deterministic(api):
+    from _gpu_util import dev
+    d = inputs.cloud1024(n=5000, seed=5)
+    args = [dev(d[k]) for k in ("x", "y", "z", "q")]
+    a = [t.clone() for t in api.coulomb_forces(*args)]
+    b = api.coulomb_forces(*args)
+    for u, v in zip(a, b):
+        assert bool((u == v).all())
+
+
+@pytest.mark.parametrize("n", [2, 1024, 32768])
+def test_energy_parity(api, oracle, n):
+    from _gpu_util import dev
+    d = inputs.rf32768(n=n) if n > 1024 else inputs.cloud1024(n=n)
+    ref, _ = oracle.coulomb_energy(d["x"], d["y"], d["z"], d["q"])
+    for prec in ("fp64", "ieee", "mixed"):
+        u = float(api.coulomb_energy(dev(d["x"]), dev(d["y"]), dev(d["z"]), dev(d["q"]), prec=prec)[0])
+        tol = 1e-12 if prec != "mixed" else 1e-9
+        assert abs(u - ref) <= tol * abs(ref), (prec, u, ref)
+
+
+def test_nonfinite_flag_on_coincident_ions(api):
+    from _gpu_util import dev
+    x = np.array([0.0, 1e-6, 1e-6, 3e-6])
+    z = np.zeros(4)
+    q = np.full(4, inputs.E_CHARGE)
+    api.poll_flags()
+    f = api.coulomb_forces(dev(x), dev(z), dev(z), dev(q))
+    assert api.poll_flags() & 1
+    assert api.poll_flags() == 0  # cleared by the poll
+    # softening makes the same configuration finite
+    f = api.coulomb_forces(dev(x), dev(z), dev(z), dev(q), eps2=1e-14)
+    assert api.poll_flags() == 0
+    assert np.isfinite(np.stack([t.cpu().numpy() for t in f])).all()
