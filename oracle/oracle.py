@@ -185,7 +185,7 @@ def md_run(state, q, m, trap, t0, dt, nsteps, eps2=0.0, init_accel=True, every=0
     (ax.. ignored when init_accel).  Returns (new_state, energies or None,
     traj or None); energies has shape (nsteps//every + 1, 4) = K, U_C, U_trap, E;
     traj has shape (nsteps, 9, n)."""
-    st = np.array(state, dtype=np.float64, copy=True).reshape(9, -1)
+    st = np.array(state, dtype=np.float64, order="C", copy=True).reshape(9, -1)
     n = st.shape[1]
     q, pq = _d(q)
     m, pm = _d(m)

@@ -106,6 +106,17 @@ def test_single_ion_feels_no_coulomb_force(oracle):
     assert all(v[0] == 0.0 for v in f)
 
 
+def test_md_run_accepts_strided_state(oracle):
+    # a reversed (negative-stride) view must be copied to C order, not read raw
+    d = inputs.cloud1024(n=50, seed=19)
+    st = inputs.state9(d)
+    perm = np.arange(50)[::-1]
+    a, ea, _ = oracle.md_run(st[:, perm], d["q"][perm], d["m"][perm], d["trap"], 0.0, 1e-9, 3, every=1)
+    b, eb, _ = oracle.md_run(np.ascontiguousarray(st[:, perm]), d["q"][perm].copy(), d["m"][perm].copy(),
+                             d["trap"], 0.0, 1e-9, 3, every=1)
+    assert np.array_equal(a, b) and np.array_equal(ea, eb) and np.isfinite(a).all()
+
+
 def test_sampled_forces_equal_full_forces(oracle):
     pos, q = _cloud(300, 7, charges=(1.0, 2.0))
     full = np.stack(oracle.forces(*pos, q))
