@@ -1,0 +1,225 @@
+"""Benchmark: all-pairs Coulomb velocity-Verlet step at N = 100000 on one MI355X.
+
+One step = one md step of the whole hot path on the N = 100000 workload
+(cloud100k: Gaussian cloud, 1% of ions at +2e, static pseudo-potential trap,
+dt = 1 ns): the all-pairs force kernel (j-split partial sums), then the fixed
+order sum over splits fused with the trap, the velocity-Verlet kick and the
+next drift.  ``value`` is pair interactions per second, N^2 per step.
+
+Prints one JSON line with the contract fields plus ``roofline`` (the
+all-pairs kernel against the FP64 vector peak, 20 FLOPs per pair),
+``cpu_baseline`` (the oracle's plain double loop timed on this host on a
+bounded sample) and ``mixed`` (the FP32-seeded one-Newton-step path: speed and
+its force error).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_PAIR = 20  # the paper's double loop with +,-,*,/,sqrt counted once each
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2106_11143_amd/csrc/pair_kernels.hpp", "paper_2106_11143_amd/csrc/rsqrt.hpp",
+                  "paper_2106_11143_amd/csrc/pair.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_fp64_cloud100k_traffic.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP64 all-pairs kernel from the committed
+    rocprofv3 counter summary, or None if absent or taken on other code."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (rocprofv3 counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
+              "described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2106_11143_amd import api, inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    d = inputs.cloud100k(n=args.n)
+    n = d["n"]
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    q, m = dev(d["q"]), dev(d["m"])
+    trap, dt = d["trap"], d["dt"]
+
+    if args.calib_copy_mib:
+        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    def fresh_state():
+        st = inputs.state9(d)
+        return [dev(st[k]) for k in range(9)]
+
+    def time_steps(prec, K, W):
+        st = fresh_state()
+        api.md_run(st, q, m, trap, 0.0, dt, 0, prec=prec, init_accel=True)  # a_0
+        if W:
+            api.md_run(st, q, m, trap, 0.0, dt, W, prec=prec, init_accel=False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        api.md_run(st, q, m, trap, W * dt, dt, K, prec=prec, init_accel=False)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), st
+
+    def time_pair_kernel(prec, reps):
+        x, y, z = (dev(d[k]) for k in ("x", "y", "z"))
+        api.coulomb_pair_stage(x, y, z, q, prec=prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            api.coulomb_pair_stage(x, y, z, q, prec=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_fp64, st64 = time_steps("fp64", args.steps, args.warmup)
+    ms_mixed, _ = time_steps("mixed", args.steps, args.warmup)
+    reps = max(5, args.steps // 2)
+    kt64 = time_pair_kernel("fp64", reps)
+    kt_mixed = time_pair_kernel("mixed", reps)
+    cfg = api.get_config("md_run", n, "fp64")
+    pairs_step = float(n) * float(n)
+    ms_per_step = ms_fp64 / args.steps
+    value = pairs_step * args.steps / (ms_fp64 * 1e-3)
+    achieved = FLOPS_PER_PAIR * pairs_step / (kt64 * 1e-3) / 1e12
+    traffic = measured_traffic()
+
+    # force error of the mixed path against the FP64 path, all ions
+    x, y, z = (dev(d[k]) for k in ("x", "y", "z"))
+    F64 = torch.stack(api.coulomb_forces(x, y, z, q, prec="fp64")).cpu().numpy()
+    Fmx = torch.stack(api.coulomb_forces(x, y, z, q, prec="mixed")).cpu().numpy()
+    emx = np.linalg.norm(Fmx - F64, axis=0) / np.linalg.norm(F64, axis=0)
+
+    out = {
+        "metric": "pair interactions/s (FP64, N=100000, one velocity-Verlet step per step)",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Gaussian ion cloud, inputs.cloud100k)",
+        "config": {
+            "workload": f"cloud100k: N={n} ions, Gaussian sigma=(150,150,800) um, 1% at +2e, static trap "
+                        "2pi(1,1,0.2) MHz, dt=1 ns, FP64 all-pairs Coulomb + velocity-Verlet",
+            "n": n, "launch": cfg, "flops_per_pair": FLOPS_PER_PAIR,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "cb::k_pair<FP64> (all-pairs force, j-split partials)",
+            "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS,
+            "frac_fp32_peak": achieved / PEAK_FP32_TFLOPS,
+            "traffic": traffic,
+            "kernel_ms": kt64,
+            "algorithmic_flops_per_launch": FLOPS_PER_PAIR * pairs_step,
+        },
+        "mixed": {
+            "pairs_per_s": pairs_step * args.steps / (ms_mixed * 1e-3),
+            "ms_per_step": ms_mixed / args.steps,
+            "kernel_ms": kt_mixed,
+            "kernel_tflops": FLOPS_PER_PAIR * pairs_step / (kt_mixed * 1e-3) / 1e12,
+            "speedup_vs_fp64_step": ms_fp64 / ms_mixed,
+            "speedup_vs_fp64_kernel": kt64 / kt_mixed,
+            "max_rel_force_err_vs_fp64": float(emx.max()),
+            "rms_rel_force_err_vs_fp64": float(np.sqrt(np.mean(emx ** 2))),
+        },
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"], out["oracle_error"] = cpu_leg(d, F64, Fmx, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_leg(d, F64, Fmx, seconds):
+    """The oracle on this host: its plain double loop timed on a bounded sample
+    of rows (all j for ions 0..k-1), and the GPU force errors against its
+    compensated forces on a sample of ions."""
+    import numpy as np
+
+    from oracle import oracle as O
+
+    n = d["n"]
+    args = (d["x"], d["y"], d["z"], d["q"])
+    t0 = time.perf_counter()
+    k0 = min(n, 2000)
+    O.forces_plain_range(*args, 0, k0)
+    t_cal = time.perf_counter() - t0
+    k = int(min(n, max(k0, k0 * seconds / max(t_cal, 1e-6))))
+    reps = max(1, int(seconds / max(t_cal * k / k0, 1e-6)))
+    t0 = time.perf_counter()
+    used = 0
+    for _ in range(reps):
+        _, _, _, used = O.forces_plain_range(*args, 0, k)
+    t = time.perf_counter() - t0
+    pairs = float(reps) * k * (n - 1)
+    base = {"value": pairs / t, "unit": "pairs/s", "cores": int(used), "kind": "oracle",
+            "sample": f"plain FP64 double loop (SQRT+DIV), rows 0..{k - 1} x all {n} ions, {reps} pass(es), "
+                      f"{t:.1f} s"}
+    g = np.random.Generator(np.random.PCG64(5))
+    idx = np.sort(g.choice(n, min(n, 1000), replace=False))
+    ref = np.stack(O.forces(*args, idx=idx))
+    err = {}
+    for name, F in (("fp64", F64), ("mixed", Fmx)):
+        e = np.linalg.norm(F[:, idx] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        err[name] = {"max_rel": float(e.max()), "rms_rel": float(np.sqrt(np.mean(e ** 2))), "ions": len(idx)}
+    return base, err
+
+
+if __name__ == "__main__":
+    main()

@@ -71,16 +71,16 @@ static long long cfg_key(int op, int prec, int64_t n) {
     return ((long long)op << 40) | ((long long)prec << 32) | (long long)n_bucket(n);
 }
 
-// Heuristic default: enough i-particles per lane for instruction-level
-// parallelism once n is large, and enough j-splits that the launch holds
-// about two waves per SIMD (256 CUs x 4 SIMDs).
+// Heuristic default (measured on MI355X at n = 1e5): one i-particle per
+// lane and many short waves -- about 64 waves per SIMD over the launch, by
+// j-splits -- so that the last waves of the launch leave little of the chip
+// idle; ILP comes from the independent FMA chains within a pair.
 LaunchCfg default_cfg(int op, int64_t n, int prec) {
     LaunchCfg c;
-    c.wg = 256;
-    c.p = n >= 16384 ? 4 : (n >= 4096 ? 2 : 1);
-    if (op == CB_OP_HVP || op == CB_OP_ADJOINT) c.p = n >= 8192 ? 2 : 1;
+    c.wg = 64;
+    c.p = 1;
     const int64_t waves = (n + 64 * c.p - 1) / (64 * c.p);
-    int64_t s = (2048 + waves - 1) / waves;
+    int64_t s = (65536 + waves - 1) / waves;
     s = std::max<int64_t>(1, std::min<int64_t>(s, kMaxSplits));
     s = std::min<int64_t>(s, std::max<int64_t>(1, n / 64));
     c.splits = (int)s;
