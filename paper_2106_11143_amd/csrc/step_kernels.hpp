@@ -4,50 +4,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-#include "coulomb.h"
+#include "step_common.hpp"
 
 namespace cb {
-
-// k_C = 1 / (4 pi eps0), CODATA 2018 vacuum permittivity.
-constexpr double kPi = 3.14159265358979323846;
-constexpr double kEps0 = 8.8541878128e-12;
-constexpr double kCoulomb = 1.0 / (4.0 * kPi * kEps0);
-
-constexpr int kEpiThreads = 256;
-
-struct TrapK {
-    double kx, ky, kz;
-};
-
-// Spring constants per unit mass of the trap at time t (see cb_trap).
-__device__ __forceinline__ TrapK trap_k(const cb_trap& tr, double t) {
-    TrapK k;
-    if (tr.kind == 1) {
-        const double w2 = tr.rf_omega * tr.rf_omega;
-        const double kx = tr.rf_a * w2 * 0.25 + tr.rf_q * w2 * 0.5 * cos(tr.rf_omega * t + tr.rf_phase);
-        k.kx = kx;
-        k.ky = -kx;
-        k.kz = tr.wz * tr.wz;
-        return k;
-    }
-    double wx = tr.wx, wy = tr.wy;
-    if (tr.t_ramp1 > tr.t_ramp0) {
-        double s = (t - tr.t_ramp0) / (tr.t_ramp1 - tr.t_ramp0);
-        s = fmin(fmax(s, 0.0), 1.0);
-        wx = tr.wx + s * (tr.wx1 - tr.wx);
-        wy = tr.wy + s * (tr.wy1 - tr.wy);
-    }
-    k.kx = wx * wx;
-    k.ky = wy * wy;
-    k.kz = tr.wz * tr.wz;
-    return k;
-}
-
-// Time of step `step` of a run started at t0 (one rounding per operation,
-// never contracted, so every kernel computes the same value).
-__device__ __forceinline__ double step_time(double t0, double dt, long long step) {
-    return __dadd_rn(t0, __dmul_rn(static_cast<double>(step), dt));
-}
 
 enum : unsigned {
     EPI_FORCES = 1u,   // write F to fx, fy, fz
@@ -73,32 +32,6 @@ struct EpiParams {
     double* eblk;  // [gridDim.x][3]
     unsigned* flags;
 };
-
-// Fixed-order tree sum of three values over the 256 threads of a block; the
-// result is valid in thread 0.
-__device__ __forceinline__ void block_sum3(double& a, double& b, double& c) {
-    __shared__ double sh[3][kEpiThreads];
-    const int t = threadIdx.x;
-    sh[0][t] = a;
-    sh[1][t] = b;
-    sh[2][t] = c;
-    __syncthreads();
-    for (int w = kEpiThreads / 2; w > 0; w >>= 1) {
-        if (t < w) {
-            sh[0][t] += sh[0][t + w];
-            sh[1][t] += sh[1][t + w];
-            sh[2][t] += sh[2][t + w];
-        }
-        __syncthreads();
-    }
-    a = sh[0][0];
-    b = sh[1][0];
-    c = sh[2][0];
-}
-
-__device__ __forceinline__ bool finite3(double a, double b, double c) {
-    return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c);
-}
 
 __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
     const int i = blockIdx.x * kEpiThreads + threadIdx.x;

@@ -1,0 +1,248 @@
+"""Drivers built on the library's entry points (support code around the hot
+path; every force, energy, Hessian product and integration step runs in the
+HIP kernels, torch only supplies element-wise glue and the small dense
+algebra of Lanczos).
+
+- minimise: FIRE relaxation (Bitzek et al., PRL 97, 170201 (2006)) followed by
+  Newton-CG steps whose Hessian products come from coulomb_hvp; gives the
+  Coulomb crystal of a trap.
+- lanczos_lowest: block Lanczos with full reorthogonalisation on the
+  mass-weighted Hessian M^-1/2 H M^-1/2 (eigenvalues = squared normal-mode
+  angular frequencies), several vectors per HVP kernel pass.
+- traj_grad: d(mean-square displacement after T steps)/d(wx, wy, wz) by the
+  discrete adjoint of velocity-Verlet with checkpointed recomputation.
+- count_defects: kink count of a quasi-one-dimensional zigzag chain.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import api
+from .autograd import trap_k
+
+
+def _rows(r):
+    return r[0].contiguous(), r[1].contiguous(), r[2].contiguous()
+
+
+def total_force(r, q, m, trap, t=0.0, eps2=0.0, prec="fp64"):
+    """Coulomb + trap force (3, n)."""
+    F = torch.stack(api.coulomb_forces(*_rows(r), q, eps2, prec))
+    k = torch.tensor(trap_k(trap, t), dtype=r.dtype, device=r.device).reshape(3, 1)
+    return F - m.reshape(1, -1) * k * r
+
+
+def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, fire_tol_rel=1e-5, max_fire=200000, max_newton=30,
+             cg_iters=400, verbose=False):
+    """Relaxes positions r (3, n) (copied) to a minimum of U_C + U_trap.
+    Stops when max_i |F_i| <= ftol_rel * k_C e^2 / a^2 with a the ion spacing
+    scale (3 k_C e^2 / (m w_max^2))^(1/3).  Returns (r_min, info)."""
+    r = r.clone()
+    k = trap_k(trap, 0.0)
+    wmax = math.sqrt(max(k))
+    e2kc = 2.307077552e-28  # k_C e^2 (J m), only for the stopping scale
+    mbar = float(m.mean())
+    a = (3.0 * e2kc / (mbar * wmax * wmax)) ** (1.0 / 3.0)
+    fscale = e2kc / (a * a)
+    v = torch.zeros_like(r)
+    dt_max, dt = 0.2 / wmax, 0.05 / wmax
+    alpha, n_pos = 0.1, 0
+    it = 0
+    F = total_force(r, q, m, trap, 0.0, eps2)
+    for it in range(max_fire):
+        fmax = float(F.norm(dim=0).max())
+        if fmax <= fire_tol_rel * fscale:
+            break
+        acc = F / m.reshape(1, -1)
+        v = v + dt * acc
+        P = float((F * v).sum())
+        if P > 0:
+            vn, fn = v.norm(), F.norm()
+            v = (1 - alpha) * v + alpha * vn * F / fn
+            n_pos += 1
+            if n_pos > 5:
+                dt = min(dt * 1.1, dt_max)
+                alpha *= 0.99
+        else:
+            v.zero_()
+            dt *= 0.5
+            alpha, n_pos = 0.1, 0
+        r = r + dt * v
+        F = total_force(r, q, m, trap, 0.0, eps2)
+    info = {"fire_iters": it, "fire_fmax_rel": float(F.norm(dim=0).max()) / fscale}
+    # Newton-CG: solve H d = F (H from the HVP kernel), r += d
+    for nit in range(max_newton):
+        fmax = float(F.norm(dim=0).max())
+        if fmax <= ftol_rel * fscale:
+            break
+        d = _cg(lambda u: api.coulomb_hvp(*_rows(r), q, u.contiguous(), m, trap, 0.0, eps2), F, cg_iters)
+        # backtracking on the force norm
+        step, best = 1.0, None
+        for _ in range(20):
+            rt = r + step * d
+            Ft = total_force(rt, q, m, trap, 0.0, eps2)
+            if float(Ft.norm()) < float(F.norm()):
+                best = (rt, Ft)
+                break
+            step *= 0.5
+        if best is None:
+            break
+        r, F = best
+        if verbose:
+            print(f"newton {nit}: fmax_rel {float(F.norm(dim=0).max()) / fscale:.3e}")
+    info["newton_fmax_rel"] = float(F.norm(dim=0).max()) / fscale
+    info["force_scale"] = fscale
+    return r, info
+
+
+def _cg(Hmul, b, iters, rtol=1e-12):
+    x = torch.zeros_like(b)
+    rr = b.clone()
+    p = rr.clone()
+    rs = float((rr * rr).sum())
+    b2 = rs
+    for _ in range(iters):
+        Hp = Hmul(p)
+        pHp = float((p * Hp).sum())
+        if pHp <= 0:
+            break
+        al = rs / pHp
+        x = x + al * p
+        rr = rr - al * Hp
+        rs_new = float((rr * rr).sum())
+        if rs_new <= rtol * rtol * b2:
+            break
+        p = rr + (rs_new / rs) * p
+        rs = rs_new
+    return x
+
+
+def lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=2400, eps2=0.0, seed=0, tol=1e-9):
+    """Lowest k eigenpairs of the mass-weighted Hessian of U_C + U_trap at r.
+    Returns (eigenvalues (k,), eigenvectors (k, 3, n) in mass-weighted
+    coordinates, residual norms (k,))."""
+    n = r.shape[1]
+    N3 = 3 * n
+    dev = r.device
+    sm = torch.sqrt(m).reshape(1, -1)
+
+    def A(V):  # V: (N3, B) -> (N3, B)
+        B = V.shape[1]
+        vv = (V.T.reshape(B, 3, n) / sm).contiguous()
+        hv = api.coulomb_hvp(*_rows(r), q, vv, m, trap, 0.0, eps2)
+        return (hv / sm).reshape(B, N3).T
+
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    Q0 = torch.randn(N3, block, generator=g, dtype=torch.float64).to(dev)
+    Q0, _ = torch.linalg.qr(Q0)
+    Qs = [Q0]
+    As, Bs = [], []
+    Bprev = None
+    steps = max(1, min(maxdim, N3) // block)
+    theta = None
+    for j in range(steps):
+        Qj = Qs[-1]
+        W = A(Qj)
+        if Bprev is not None:
+            W = W - Qs[-2] @ Bprev.T
+        Aj = Qj.T @ W
+        Aj = 0.5 * (Aj + Aj.T)
+        W = W - Qj @ Aj
+        Qall = torch.cat(Qs, dim=1)
+        for _ in range(2):
+            W = W - Qall @ (Qall.T @ W)
+        Qn, Bj = torch.linalg.qr(W)
+        As.append(Aj)
+        Bs.append(Bj)
+        Bprev = Bj
+        Qs.append(Qn)
+        if (j + 1) % 25 == 0 or j == steps - 1:
+            T = _block_tridiag(As, Bs[:-1])
+            theta, S = torch.linalg.eigh(T)
+            res = (Bs[-1] @ S[-block:, :k]).norm(dim=0)
+            scale = float(theta.abs().max())
+            if float(res.max()) <= tol * scale:
+                break
+    T = _block_tridiag(As, Bs[:-1])
+    theta, S = torch.linalg.eigh(T)
+    res = (Bs[-1] @ S[-block:, :k]).norm(dim=0)
+    Qall = torch.cat(Qs[:-1], dim=1)
+    Y = Qall @ S[:, :k]
+    return theta[:k], Y.T.reshape(k, 3, n), res
+
+
+def _block_tridiag(As, Bs):
+    b = As[0].shape[0]
+    s = len(As)
+    T = torch.zeros(s * b, s * b, dtype=As[0].dtype, device=As[0].device)
+    for i, Ai in enumerate(As):
+        T[i * b:(i + 1) * b, i * b:(i + 1) * b] = Ai
+    for i, Bi in enumerate(Bs):
+        T[(i + 1) * b:(i + 2) * b, i * b:(i + 1) * b] = Bi
+        T[i * b:(i + 1) * b, (i + 1) * b:(i + 2) * b] = Bi.T
+    return 0.5 * (T + T.T)
+
+
+def traj_grad(state0, q, m, trap, dt, nsteps, checkpoint_every=50, eps2=0.0, prec="fp64"):
+    """Mean-square displacement L = (1/n) sum_i |r_i(T) - r_i(0)|^2 after
+    nsteps velocity-Verlet steps from state0 ((9, n) or (6, n) tensor; the
+    accelerations are recomputed), and dL/d(wx, wy, wz) by the discrete
+    adjoint, storing a checkpoint every `checkpoint_every` steps and
+    recomputing each segment's positions in the backward pass.
+    Returns (L, grad (3,), info)."""
+    n = q.numel()
+    dev = q.device
+    st = torch.zeros(9, n, dtype=torch.float64, device=dev)
+    st[:6] = state0[:6]
+    S = [st[k] for k in range(9)]
+    api.md_run(S, q, m, trap, 0.0, dt, 0, eps2=eps2, prec=prec, init_accel=True)
+    r0 = st[:3].clone()
+    ckpts = {0: st.clone()}
+    done = 0
+    while done < nsteps:
+        k = min(checkpoint_every, nsteps - done)
+        api.md_run(S, q, m, trap, done * dt, dt, k, eps2=eps2, prec=prec, init_accel=False)
+        done += k
+        if done < nsteps:
+            ckpts[done] = st.clone()
+    rT = st[:3].clone()
+    L = float(((rT - r0) ** 2).sum()) / n
+    lam = torch.zeros(9, n, dtype=torch.float64, device=dev)
+    lam[:3] = 2.0 * (rT - r0) / n
+    dldw = torch.zeros(3, dtype=torch.float64, device=dev)
+    seg_starts = sorted(ckpts.keys())
+    for s0 in reversed(seg_starts):
+        s1 = min(s0 + checkpoint_every, nsteps)
+        cur = ckpts[s0].clone()
+        C = [cur[k] for k in range(9)]
+        pos = []  # positions r_{s0+1} .. r_{s1}
+        for step in range(s0, s1):
+            api.md_step(C, q, m, trap, step * dt, dt, eps2=eps2, prec=prec)
+            pos.append(cur[:3].clone())
+        for step in range(s1 - 1, s0 - 1, -1):
+            rp = pos[step - s0]
+            api.md_adjoint_step(rp[0].contiguous(), rp[1].contiguous(), rp[2].contiguous(), q, m, trap, dt, lam,
+                                dldw, eps2=eps2, prec=prec)
+    api.md_adjoint_step(r0[0].contiguous(), r0[1].contiguous(), r0[2].contiguous(), q, m, trap, dt, lam, dldw,
+                        eps2=eps2, prec=prec, final=True)
+    return L, dldw, {"checkpoints": len(ckpts)}
+
+
+def count_defects(x, y, z):
+    """Kinks of a zigzag chain: ions sorted along z, the transverse
+    displacement projected on the principal transverse axis, s_k = sign; a
+    defect is a place where the zigzag order s_k = -s_{k+1} breaks
+    (s_k = s_{k+1}).  Meaningful for quasi-one-dimensional crystals only."""
+    x, y, z = (np.asarray(a, dtype=np.float64) for a in (x, y, z))
+    order = np.argsort(z)
+    P = np.stack([x[order] - x.mean(), y[order] - y.mean()])
+    if P.shape[1] < 3:
+        return 0
+    w, V = np.linalg.eigh(P @ P.T)
+    e = V[:, np.argmax(w)]
+    s = np.sign(e @ P)
+    s[s == 0] = 1
+    return int(np.sum(s[1:] == s[:-1]))

@@ -1,0 +1,150 @@
+"""GPU Hessian-vector products, autograd double backward, minimiser, Lanczos
+normal modes and the checkpointed discrete adjoint, against the oracle, exact
+identities and finite differences."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2106_11143_amd import inputs
+
+pytestmark = pytest.mark.gpu
+E = inputs.E_CHARGE
+M40 = inputs.MASS_40U
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_11143_amd import api as A
+    A.lib()
+    return A
+
+
+def _cloud(n, seed, charges=(1.0,)):
+    g = np.random.Generator(np.random.PCG64(seed))
+    pos = g.normal(0.0, 20e-6, size=(3, n))
+    return pos, E * g.choice(np.asarray(charges), size=n)
+
+
+@pytest.mark.parametrize("n,nvec,with_trap", [(1024, 1, False), (1023, 3, True), (777, 8, True), (65, 5, False),
+                                              (8192, 2, True)])
+def test_hvp_matches_oracle(api, oracle, n, nvec, with_trap):
+    from _gpu_util import dev, host
+    pos, q = _cloud(n, 40 + n, charges=(1.0, 2.0))
+    g = np.random.Generator(np.random.PCG64(n))
+    v = g.normal(size=(nvec, 3, n))
+    m = np.full(n, M40)
+    trap = inputs.rf_trap(0.0, 0.3, 10e6, 0.1e6) if with_trap else None
+    ref = oracle.hvp(*pos, q, v, m=m if with_trap else None, trap=trap, t=1.3e-8)
+    for prec, tol in (("fp64", 1e-12), ("mixed", 1e-8)):
+        hv = host(api.coulomb_hvp(dev(pos[0]), dev(pos[1]), dev(pos[2]), dev(q), dev(v),
+                                  dev(m) if with_trap else None, trap, 1.3e-8, prec=prec))
+        err = np.linalg.norm(hv - ref, axis=1).max() / np.linalg.norm(ref, axis=1).max()
+        print(f"[hvp n={n} nvec={nvec} {prec}] normwise err {err:.3e}", flush=True)
+        assert err <= tol
+
+
+def test_hvp_exact_identities(api, oracle):
+    from _gpu_util import dev, host
+    pos, q = _cloud(2000, 5, charges=(1.0, 2.0))
+    P = [dev(pos[c]) for c in range(3)]
+    F = np.stack([host(t) for t in api.coulomb_forces(*P, dev(q))])
+    scale = np.linalg.norm(F, axis=0).max()
+    Hr = host(api.coulomb_hvp(*P, dev(q), dev(pos)))
+    assert np.abs(Hr - 2.0 * F).max() <= 1e-11 * scale  # degree -1 homogeneity
+    for e in np.eye(3):
+        Kr = np.cross(e, pos.T).T
+        HK = host(api.coulomb_hvp(*P, dev(q), dev(Kr)))
+        assert np.abs(HK + np.cross(e, F.T).T).max() <= 1e-11 * scale  # rotation invariance
+    g = np.random.Generator(np.random.PCG64(9))
+    u, w = g.normal(size=(3, 2000)), g.normal(size=(3, 2000))
+    Hu, Hw = host(api.coulomb_hvp(*P, dev(q), dev(u))), host(api.coulomb_hvp(*P, dev(q), dev(w)))
+    assert abs(np.sum(u * Hw) - np.sum(w * Hu)) <= 1e-12 * np.abs(u * Hw).sum()
+
+
+def test_autograd_double_backward_is_hvp(api):
+    import torch
+    from paper_2106_11143_amd import autograd as AG
+    from _gpu_util import dev
+    pos, q = _cloud(700, 6)
+    m = dev(np.full(700, M40))
+    trap = inputs.pseudo_trap(1e6, 1e6, 0.2e6)
+    r = dev(pos).requires_grad_(True)
+    U = AG.energy(r, dev(q), m, trap)
+    (G,) = torch.autograd.grad(U, r, create_graph=True)
+    F = torch.stack(api.coulomb_forces(*[dev(pos[c]) for c in range(3)], dev(q)))
+    k = torch.tensor(AG.trap_k(trap), dtype=torch.float64, device="cuda").reshape(3, 1)
+    assert torch.allclose(G, -F + m.reshape(1, -1) * k * r.detach(), rtol=0, atol=1e-14 * float(F.abs().max()))
+    w = dev(np.random.Generator(np.random.PCG64(2)).normal(size=(3, 700)))
+    (Hw,) = torch.autograd.grad(G, r, grad_outputs=w)
+    direct = api.coulomb_hvp(*[dev(pos[c]) for c in range(3)], dev(q), w, m, trap)
+    assert torch.equal(Hw, direct)
+    # the energy itself against the oracle-free closed form pieces
+    Uc = float(api.coulomb_energy(*[dev(pos[c]) for c in range(3)], dev(q))[0])
+    Ut = 0.5 * float((m.reshape(1, -1) * k * r.detach() ** 2).sum())
+    assert abs(float(U) - (Uc + Ut)) <= 1e-14 * abs(Uc + Ut)
+
+
+def _crystal(n, fr, fz, seed=1):
+    import torch
+    from paper_2106_11143_amd import drivers
+    from _gpu_util import dev
+    trap = inputs.pseudo_trap(fr, fr, fz)
+    sig = inputs.crystal_sigma(n, trap["wx"], trap["wy"], trap["wz"])
+    g = np.random.Generator(np.random.PCG64(seed))
+    r0 = dev(g.normal(size=(3, n)) * sig[:, None])
+    q, m = dev(np.full(n, E)), dev(np.full(n, M40))
+    r, info = drivers.minimise(r0, q, m, trap, ftol_rel=1e-12)
+    return r, q, m, trap, info
+
+
+def test_minimiser_and_lanczos_normal_modes(api):
+    import torch
+    from paper_2106_11143_amd import drivers
+    n = 300
+    r, q, m, trap, info = _crystal(n, 1.0e6, 0.05e6)
+    print(f"[minimise n={n}] {info}", flush=True)
+    assert info["newton_fmax_rel"] <= 1e-12
+    lam, vecs, res = drivers.lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=1200)
+    wz2 = trap["wz"] ** 2
+    lam = lam.cpu().numpy()
+    print(f"[lanczos] lowest/wz^2: {np.round(lam[:8] / wz2, 6)} max res {float(res.max()):.2e}", flush=True)
+    # the rotation about z (wx = wy) is a zero mode and the axial centre-of-mass
+    # mode has exactly wz^2 (Kohn), for any crystal
+    assert abs(lam[0]) <= 1e-8 * wz2
+    assert np.min(np.abs(lam - wz2)) <= 1e-8 * wz2
+    assert np.all(np.diff(lam) >= -1e-9 * wz2)
+
+
+def test_trajectory_gradient_matches_oracle_and_fd(api, oracle):
+    import torch
+    from paper_2106_11143_amd import drivers
+    from _gpu_util import dev
+    d = inputs.crystal8192(n=96, seed=21)
+    trap = d["trap"]
+    st = inputs.state9(d)
+    q, m = dev(d["q"]), dev(d["m"])
+    dt, nsteps = 1e-9, 120
+    L, g, info = drivers.traj_grad(dev(st), q, m, trap, dt, nsteps, checkpoint_every=50)
+    Lr, gr = oracle.msd_grad(st[:6], d["q"], d["m"], trap, dt, nsteps)
+    g = g.cpu().numpy()
+    print(f"[traj_grad] L {L:.6e} vs {Lr:.6e}; grad {g} vs {gr}", flush=True)
+    assert L == pytest.approx(Lr, rel=1e-10)
+    assert np.allclose(g, gr, rtol=1e-8, atol=1e-12 * np.abs(gr).max())
+
+    def loss(tr):
+        s = [dev(st[k]) for k in range(9)]
+        api.md_run(s, q, m, tr, 0.0, dt, nsteps)
+        return float(sum(((s[c] - dev(st[c])) ** 2).sum() for c in range(3))) / 96
+
+    for c, key in enumerate(("wx", "wz")):
+        h = 1e-6 * trap[key]
+        tp, tm = dict(trap), dict(trap)
+        tp[key] += h
+        tm[key] -= h
+        fd = (loss(tp) - loss(tm)) / (2 * h)
+        gc = g[0] if key == "wx" else g[2]
+        assert gc == pytest.approx(fd, rel=1e-5)
