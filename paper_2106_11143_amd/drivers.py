@@ -3,8 +3,7 @@ path; every force, energy, Hessian product and integration step runs in the
 HIP kernels, torch only supplies element-wise glue and the small dense
 algebra of Lanczos).
 
-- minimise: FIRE relaxation (Bitzek et al., PRL 97, 170201 (2006)) followed by
-  Newton-CG steps whose Hessian products come from coulomb_hvp; gives the
+- minimise: FIRE relaxation (Bitzek et al., PRL 97, 170201 (2006)) to the
   Coulomb crystal of a trap.
 - lanczos_lowest: block Lanczos with full reorthogonalisation on the
   mass-weighted Hessian M^-1/2 H M^-1/2 (eigenvalues = squared normal-mode
@@ -35,11 +34,10 @@ def total_force(r, q, m, trap, t=0.0, eps2=0.0, prec="fp64"):
     return F - m.reshape(1, -1) * k * r
 
 
-def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, fire_tol_rel=1e-5, max_fire=200000, max_newton=30,
-             cg_iters=400, verbose=False):
-    """Relaxes positions r (3, n) (copied) to a minimum of U_C + U_trap.
-    Stops when max_i |F_i| <= ftol_rel * k_C e^2 / a^2 with a the ion spacing
-    scale (3 k_C e^2 / (m w_max^2))^(1/3).  Returns (r_min, info)."""
+def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, max_iter=400000):
+    """Relaxes positions r (3, n) (copied) to a minimum of U_C + U_trap with
+    FIRE.  Stops when max_i |F_i| <= ftol_rel * k_C e^2 / a^2, a being the ion
+    spacing scale (3 k_C e^2 / (m w_max^2))^(1/3).  Returns (r_min, info)."""
     r = r.clone()
     k = trap_k(trap, 0.0)
     wmax = math.sqrt(max(k))
@@ -51,17 +49,16 @@ def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, fire_tol_rel=1e-5, max_fir
     dt_max, dt = 0.2 / wmax, 0.05 / wmax
     alpha, n_pos = 0.1, 0
     it = 0
+    minv = 1.0 / m.reshape(1, -1)
     F = total_force(r, q, m, trap, 0.0, eps2)
-    for it in range(max_fire):
+    for it in range(max_iter):
         fmax = float(F.norm(dim=0).max())
-        if fmax <= fire_tol_rel * fscale:
+        if fmax <= ftol_rel * fscale:
             break
-        acc = F / m.reshape(1, -1)
-        v = v + dt * acc
+        v = v + dt * F * minv
         P = float((F * v).sum())
         if P > 0:
-            vn, fn = v.norm(), F.norm()
-            v = (1 - alpha) * v + alpha * vn * F / fn
+            v = (1 - alpha) * v + alpha * (v.norm() / F.norm()) * F
             n_pos += 1
             if n_pos > 5:
                 dt = min(dt * 1.1, dt_max)
@@ -72,52 +69,8 @@ def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, fire_tol_rel=1e-5, max_fir
             alpha, n_pos = 0.1, 0
         r = r + dt * v
         F = total_force(r, q, m, trap, 0.0, eps2)
-    info = {"fire_iters": it, "fire_fmax_rel": float(F.norm(dim=0).max()) / fscale}
-    # Newton-CG: solve H d = F (H from the HVP kernel), r += d
-    for nit in range(max_newton):
-        fmax = float(F.norm(dim=0).max())
-        if fmax <= ftol_rel * fscale:
-            break
-        d = _cg(lambda u: api.coulomb_hvp(*_rows(r), q, u.contiguous(), m, trap, 0.0, eps2), F, cg_iters)
-        # backtracking on the force norm
-        step, best = 1.0, None
-        for _ in range(20):
-            rt = r + step * d
-            Ft = total_force(rt, q, m, trap, 0.0, eps2)
-            if float(Ft.norm()) < float(F.norm()):
-                best = (rt, Ft)
-                break
-            step *= 0.5
-        if best is None:
-            break
-        r, F = best
-        if verbose:
-            print(f"newton {nit}: fmax_rel {float(F.norm(dim=0).max()) / fscale:.3e}")
-    info["newton_fmax_rel"] = float(F.norm(dim=0).max()) / fscale
-    info["force_scale"] = fscale
+    info = {"iters": it, "fmax_rel": float(F.norm(dim=0).max()) / fscale, "force_scale": fscale}
     return r, info
-
-
-def _cg(Hmul, b, iters, rtol=1e-12):
-    x = torch.zeros_like(b)
-    rr = b.clone()
-    p = rr.clone()
-    rs = float((rr * rr).sum())
-    b2 = rs
-    for _ in range(iters):
-        Hp = Hmul(p)
-        pHp = float((p * Hp).sum())
-        if pHp <= 0:
-            break
-        al = rs / pHp
-        x = x + al * p
-        rr = rr - al * Hp
-        rs_new = float((rr * rr).sum())
-        if rs_new <= rtol * rtol * b2:
-            break
-        p = rr + (rs_new / rs) * p
-        rs = rs_new
-    return x
 
 
 def lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=2400, eps2=0.0, seed=0, tol=1e-9):

@@ -124,3 +124,15 @@ def test_md_argument_errors(api):
 
 def test_poll_flags_rejects_null(api):
     assert api.lib().cb_poll_flags(None, None) == api.CB_EINVAL
+
+
+def test_batched_rejects_runs_beyond_lds_limit(api):
+    L = api.lib()
+    arrs = [C.c_void_p((k + 1) << 26) for k in range(11)]
+    s = api.State(*arrs[:9])
+    tr = api.make_trap(dict(kind=0, wx=1e6, wy=1e6, wz=1e5))
+    offs = (C.c_int64 * 3)(0, 100, 100 + 4097)
+    trs = (api.Trap * 2)(tr, tr)
+    st = L.md_run(2, offs, C.byref(s), arrs[9], arrs[10], trs, 0.0, 1e-9, 10, 0.0, 0, 1, None, 0, _ws(), 1 << 40, None)
+    assert st == api.CB_EUNSUPPORTED
+    assert "4096" in api.last_error()

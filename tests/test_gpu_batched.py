@@ -1,0 +1,126 @@
+"""GPU batched persistent md_run (many runs of uneven size in one launch)
+against the oracle run by run, and against the single-run path."""
+import numpy as np
+import pytest
+
+from paper_2106_11143_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_11143_amd import api as A
+    A.lib()
+    return A
+
+
+def _ensemble(sizes, seed, trap):
+    g = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for n in sizes:
+        sig = inputs.crystal_sigma(n, trap["wx"], trap["wy"], trap["wz"])
+        pos = g.normal(size=(3, n)) * sig[:, None]
+        vel = inputs.maxwell(g, n, 10e-3, inputs.MASS_40U)
+        st = np.zeros((9, n))
+        st[:3], st[3:6] = pos, vel
+        parts.append(st)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    q = np.full(offs[-1], inputs.E_CHARGE)
+    q[::7] *= 2.0
+    m = np.full(offs[-1], inputs.MASS_40U)
+    return parts, offs, q, m
+
+
+def _check_run(oracle, st, q, m, trap, dt, nsteps, got, en_got, every, tag):
+    ref, en, _ = oracle.md_run(st, q, m, trap, 0.0, dt, nsteps, every=every)
+    perm = np.arange(len(q))[::-1]
+    alt, en2, _ = oracle.md_run(st[:, perm], q[perm], m[perm], trap, 0.0, dt, nsteps, every=every)
+    alt = alt[:, np.argsort(perm)]
+    for blk in (slice(0, 3), slice(3, 6), slice(6, 9)):
+        D = np.abs(alt[blk] - ref[blk]).max()
+        err = np.abs(got[blk] - ref[blk]).max()
+        assert err <= 10 * D + 1e-13 * np.abs(ref[blk]).max(), (tag, blk, err, D)
+    if en_got is not None:
+        assert np.all(np.abs(en_got - en) <= 10 * np.abs(en2 - en) + 1e-12 * np.abs(en).max(axis=0)), tag
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_ramp_matches_oracle_run_by_run(api, oracle, prec):
+    from _gpu_util import dev
+    trap = inputs.ramp_trap(1.5e6, 0.6e6, 0.15e6, 0.0, 60e-9)
+    sizes = [64, 65, 130, 257, 500, 1000, 333]
+    parts, offs, q, m = _ensemble(sizes, 3, trap)
+    st = np.concatenate(parts, axis=1)
+    ts = [dev(st[k]) for k in range(9)]
+    dt, nsteps, every = 2e-9, 40, 10
+    en = api.md_run(ts, dev(q), dev(m), [trap] * len(sizes), 0.0, dt, nsteps, offsets=offs, every=every, prec=prec)
+    got = np.stack([t.cpu().numpy() for t in ts])
+    en = en.cpu().numpy()
+    for r, n in enumerate(sizes):
+        sl = slice(offs[r], offs[r + 1])
+        if prec == "fp64":
+            _check_run(oracle, parts[r], q[sl], m[sl], trap, dt, nsteps, got[:, sl], en[r], every, f"run{r}")
+        else:
+            ref, _, _ = oracle.md_run(parts[r], q[sl], m[sl], trap, 0.0, dt, nsteps)
+            assert np.abs(got[:3, sl] - ref[:3]).max() <= 1e-9 * np.abs(ref[:3]).max()
+    assert api.poll_flags() == 0
+
+
+def test_batched_equals_single_run_path(api):
+    from _gpu_util import dev
+    trap = inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6)
+    sizes = [200, 96, 1500]
+    parts, offs, q, m = _ensemble(sizes, 5, trap)
+    st = np.concatenate(parts, axis=1)
+    ts = [dev(st[k]) for k in range(9)]
+    api.md_run(ts, dev(q), dev(m), [trap] * 3, 0.0, 1e-9, 25, offsets=offs)
+    got = np.stack([t.cpu().numpy() for t in ts])
+    for r in range(3):
+        sl = slice(offs[r], offs[r + 1])
+        one = [dev(parts[r][k]) for k in range(9)]
+        api.md_run(one, dev(q[sl]), dev(m[sl]), trap, 0.0, 1e-9, 25)
+        single = np.stack([t.cpu().numpy() for t in one])
+        for blk in (slice(0, 3), slice(3, 6)):
+            scale = np.abs(single[blk]).max()
+            assert np.abs(got[blk, sl] - single[blk]).max() <= 1e-11 * scale
+
+
+def test_batched_largest_run_and_order(api, oracle):
+    """A 4096-ion run (the LDS limit) mixed with small ones; runs are taken in
+    largest-first order but each lands in its own slice."""
+    from _gpu_util import dev
+    trap = inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6)
+    sizes = [70, 4096, 64, 2049]
+    parts, offs, q, m = _ensemble(sizes, 8, trap)
+    st = np.concatenate(parts, axis=1)
+    ts = [dev(st[k]) for k in range(9)]
+    api.md_run(ts, dev(q), dev(m), [trap] * 4, 0.0, 1e-9, 3, offsets=offs)
+    got = np.stack([t.cpu().numpy() for t in ts])
+    for r in (0, 1, 3):
+        sl = slice(offs[r], offs[r + 1])
+        _check_run(oracle, parts[r], q[sl], m[sl], trap, 1e-9, 3, got[:, sl], None, 1, f"run{r}")
+
+
+def test_kz_ensemble_small(api):
+    """The Kibble-Zurek workload at reduced size: 24 runs, N in [64, 600],
+    the ramp, 300 steps, energies recorded; defect counts are reported
+    (operational definition, not pinned)."""
+    import torch
+    from paper_2106_11143_amd import drivers
+    from _gpu_util import dev
+    d = inputs.kz512(nrun=24, nmin=64, nmax=600, nsteps=300)
+    st = inputs.state9(d)
+    ts = [dev(st[k]) for k in range(9)]
+    en = api.md_run(ts, dev(d["q"]), dev(d["m"]), d["traps"], 0.0, d["dt"], d["nsteps"], offsets=d["offsets"],
+                    every=100)
+    assert api.poll_flags() == 0
+    got = np.stack([t.cpu().numpy() for t in ts])
+    assert np.isfinite(got).all() and np.isfinite(en.cpu().numpy()).all()
+    offs = d["offsets"]
+    counts = [drivers.count_defects(got[0, offs[r]:offs[r + 1]], got[1, offs[r]:offs[r + 1]],
+                                    got[2, offs[r]:offs[r + 1]]) for r in range(24)]
+    print(f"[kz small] defect counts {counts}", flush=True)
