@@ -1,19 +1,188 @@
-// Autotuner: times candidate launch configurations and keeps the fastest.
+// Autotuner: times the candidate launch configurations (i-particles per lane,
+// workgroup size, j-splits) of the all-pairs kernels on synthetic inputs of
+// the requested size, keeps the fastest in the in-process table (keyed by
+// operation, precision and power-of-two size bucket) and optionally appends
+// it to a JSON-lines cache that cb_load_tuning reads back.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
 #include "internal.hpp"
+
+namespace cb {
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    return a.substr(0, a.find(':'));
+}
+
+// Synthetic ions: a Gaussian cloud from a fixed linear congruential stream
+// (the values only need to be realistic, not random-quality).
+void make_inputs(int64_t n, std::vector<double>& h) {
+    h.resize(4 * (size_t)n);
+    uint64_t s = 0x2106111430ULL;
+    auto u01 = [&]() {
+        s = s * 6364136223846793005ULL + 1442695040888963407ULL;
+        return ((s >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    };
+    for (int64_t i = 0; i < n; ++i) {
+        for (int c = 0; c < 3; ++c) {
+            const double g = std::sqrt(-2.0 * std::log(u01())) * std::cos(6.283185307179586 * u01());
+            h[c * (size_t)n + i] = 20e-6 * g;
+        }
+        h[3 * (size_t)n + i] = 1.602176634e-19;
+    }
+}
+
+}  // namespace
+
+}  // namespace cb
 
 using namespace cb;
 
 extern "C" {
 
 cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_path) {
-    (void)op; (void)n; (void)prec; (void)cache_path;
-    return fail(CB_EUNSUPPORTED, "cb_autotune: not built yet");
+    if (op < 0 || op > CB_OP_ADJOINT || n < 2 || n > (int64_t(1) << 26) || prec < CB_FP64 || prec > CB_FP32_RSQ)
+        return fail(CB_EINVAL, "cb_autotune: bad argument");
+    const bool hv = (op == CB_OP_HVP || op == CB_OP_ADJOINT);
+    const bool energy_only = (op == CB_OP_ENERGY);
+    std::vector<double> h;
+    make_inputs(n, h);
+    DevBuf in, part, v;
+    const size_t part_bytes = sizeof(double) * (size_t)kMaxSplits * 3 * (size_t)n;
+    if (hipMalloc(&in.p, sizeof(double) * h.size()) != hipSuccess || hipMalloc(&part.p, part_bytes) != hipSuccess ||
+        (hv && hipMalloc(&v.p, sizeof(double) * 3 * (size_t)n) != hipSuccess))
+        return fail(CB_EHIP, "cb_autotune: allocation failed");
+    if (hipMemcpy(in.p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        (hv && hipMemcpy(v.p, h.data(), sizeof(double) * 3 * (size_t)n, hipMemcpyHostToDevice) != hipSuccess))
+        return fail(CB_EHIP, "cb_autotune: upload failed");
+    const double* x = static_cast<const double*>(in.p);
+    const double *y = x + n, *z = x + 2 * n, *q = x + 3 * n;
+    hipStream_t st;
+    if (hipStreamCreate(&st) != hipSuccess) return fail(CB_EHIP, "cb_autotune: stream creation failed");
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipStreamDestroy(st);
+        return fail(CB_EHIP, "cb_autotune: event creation failed");
+    }
+    const int ps_force[] = {1, 2, 4}, ps_hvp[] = {1, 2};
+    const int wgs[] = {64, 128, 256};
+    const int splits[] = {1, 2, 4, 8, 16, 24, 32, 48, 64};
+    LaunchCfg best{0, 0, 0, 1};
+    float best_ms = 1e30f;
+    cb_status rc = CB_OK;
+    const int np = hv ? 2 : 3;
+    for (int ip = 0; ip < np && rc == CB_OK; ++ip)
+        for (int wg : wgs)
+            for (int sp : splits) {
+                const int p = hv ? ps_hvp[ip] : ps_force[ip];
+                if (sp > 1 && n / sp < 64) continue;
+                LaunchCfg c{p, wg, sp, 1};
+                const int jlen = split_len(n, sp);
+                auto launch = [&]() -> cb_status {
+                    if (hv)
+                        return launch_hvp(prec, c, 1, (int)n, x, y, z, q, static_cast<const double*>(v.p), 0.0,
+                                          jlen, static_cast<double*>(part.p), st);
+                    return launch_pair(prec, c, !energy_only, energy_only, (int)n, x, y, z, q, 0.0, jlen,
+                                       energy_only ? nullptr : static_cast<double*>(part.p),
+                                       energy_only ? static_cast<double*>(part.p) : nullptr, st);
+                };
+                if ((rc = launch())) break;
+                const int reps = 3;
+                (void)hipEventRecord(e0, st);
+                for (int r = 0; r < reps && rc == CB_OK; ++r) rc = launch();
+                (void)hipEventRecord(e1, st);
+                if (rc || hipEventSynchronize(e1) != hipSuccess) {
+                    if (!rc) rc = fail(CB_EHIP, "cb_autotune: timing failed");
+                    break;
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                ms /= reps;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    if (rc) return rc;
+    if (best.p == 0) return fail(CB_EHIP, "cb_autotune: no candidate ran");
+    // forces, md_step and md_run share the force kernel
+    if (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN) {
+        put_cfg(CB_OP_FORCES, n, prec, best);
+        put_cfg(CB_OP_MD_STEP, n, prec, best);
+        put_cfg(CB_OP_MD_RUN, n, prec, best);
+    } else if (hv) {
+        put_cfg(CB_OP_HVP, n, prec, best);
+        put_cfg(CB_OP_ADJOINT, n, prec, best);
+    } else {
+        put_cfg(op, n, prec, best);
+    }
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (!f) return fail(CB_EINVAL, "cb_autotune: cannot open %s", cache_path);
+        std::fprintf(f,
+                     "{\"arch\": \"%s\", \"op\": %d, \"prec\": %d, \"bucket\": %d, \"n\": %lld, \"p\": %d, "
+                     "\"wg\": %d, \"splits\": %d, \"ms\": %.6f}\n",
+                     arch_name().c_str(), op, prec, n_bucket(n), (long long)n, best.p, best.wg, best.splits,
+                     best_ms);
+        std::fclose(f);
+    }
+    return ok();
 }
 
 cb_status cb_load_tuning(const char* cache_path) {
-    (void)cache_path;
+    if (!cache_path) return fail(CB_EINVAL, "cb_load_tuning: path is NULL");
+    FILE* f = std::fopen(cache_path, "r");
+    if (!f) return ok();
+    const std::string arch = arch_name();
+    char line[512];
+
+    while (std::fgets(line, sizeof line, f)) {
+        char a[64] = {0};
+        int op, prec, bucket, p, wg, sp;
+        long long n;
+        if (std::sscanf(line,
+                        "{\"arch\": \"%63[^\"]\", \"op\": %d, \"prec\": %d, \"bucket\": %d, \"n\": %lld, \"p\": %d, "
+                        "\"wg\": %d, \"splits\": %d",
+                        a, &op, &prec, &bucket, &n, &p, &wg, &sp) != 8)
+            continue;
+        if (arch != a || op < 0 || op > CB_OP_ADJOINT || n < 1) continue;
+        LaunchCfg c{p, wg, sp, 1};
+        if (!valid_cfg(op, c)) continue;
+        if (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN) {
+            put_cfg(CB_OP_FORCES, n, prec, c);
+            put_cfg(CB_OP_MD_STEP, n, prec, c);
+            put_cfg(CB_OP_MD_RUN, n, prec, c);
+        } else if (op == CB_OP_HVP || op == CB_OP_ADJOINT) {
+            put_cfg(CB_OP_HVP, n, prec, c);
+            put_cfg(CB_OP_ADJOINT, n, prec, c);
+        } else {
+            put_cfg(op, n, prec, c);
+        }
+
+    }
+    std::fclose(f);
     return ok();
 }
 

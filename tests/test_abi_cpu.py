@@ -136,3 +136,12 @@ def test_batched_rejects_runs_beyond_lds_limit(api):
     st = L.md_run(2, offs, C.byref(s), arrs[9], arrs[10], trs, 0.0, 1e-9, 10, 0.0, 0, 1, None, 0, _ws(), 1 << 40, None)
     assert st == api.CB_EUNSUPPORTED
     assert "4096" in api.last_error()
+
+
+def test_load_tuning_missing_file_and_foreign_arch(api, tmp_path):
+    api.load_tuning(str(tmp_path / "missing.jsonl"))  # a missing cache is not an error
+    p = tmp_path / "cache.jsonl"
+    p.write_text('{"arch": "gfx000", "op": 0, "prec": 0, "bucket": 12, "n": 4000, "p": 2, "wg": 128, '
+                 '"splits": 9, "ms": 1.0}\nnot json\n')
+    api.load_tuning(str(p))  # entries of another architecture are ignored
+    assert not api.get_config("forces", 4000, "fp64")["tuned"]
