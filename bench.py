@@ -66,7 +66,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (rocprofv3 counter calibration)")
+    ap.add_argument("--workload", default="cloud100k",
+                    choices=["cloud100k", "cloud1024", "rf32768", "kz512", "crystal8192"],
+                    help="cloud100k is the headline; the others time the remaining workloads")
     args = ap.parse_args()
+    if args.workload != "cloud100k":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps(OTHER_WORKLOADS[args.workload](args)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
               "described in DESIGN.md and not built", file=sys.stderr)
@@ -219,6 +228,202 @@ def cpu_leg(d, F64, Fmx, seconds):
         e = np.linalg.norm(F[:, idx] - ref, axis=0) / np.linalg.norm(ref, axis=0)
         err[name] = {"max_rel": float(e.max()), "rms_rel": float(np.sqrt(np.mean(e ** 2))), "ions": len(idx)}
     return base, err
+
+
+# ----------------------------------------------------------------------------
+# The other workloads (not the headline line): same JSON contract fields.
+def _setup():
+    import numpy as np
+    import torch
+
+    from paper_2106_11143_amd import api, inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    return np, torch, api, inputs, dev
+
+
+def _timer(torch):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    return e0, e1
+
+
+def _line(metric, value, unit, steps, warmup, ms_per_step, workload, extra, higher=True):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms_per_step, "higher_is_better": higher, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic (seeded, paper_2106_11143_amd.inputs)",
+           "config": {"workload": workload}}
+    out.update(extra)
+    return out
+
+
+def bench_md_single(args, which):
+    """cloud1024 (100 steps, energies every step) or rf32768 (explicit RF,
+    energies every 50 steps): time of whole runs, pairs/s = N^2 per step."""
+    np, torch, api, inputs, dev = _setup()
+    d = inputs.cloud1024() if which == "cloud1024" else inputs.rf32768()
+    n, nsteps = d["n"], d["nsteps"]
+    every = 1 if which == "cloud1024" else 50
+    q, m = dev(d["q"]), dev(d["m"])
+    st0 = inputs.state9(d)
+    reps = max(1, args.steps if which == "cloud1024" else 1)
+
+    def one():
+        ts = [dev(st0[k]) for k in range(9)]
+        return api.md_run(ts, q, m, d["trap"], 0.0, d["dt"], nsteps, every=every), ts
+
+    for _ in range(max(1, args.warmup if which == "cloud1024" else 1)):
+        one()
+    torch.cuda.synchronize()
+    e0, e1 = _timer(torch)
+    e0.record()
+    for _ in range(reps):
+        en, ts = one()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    E = en[0, :, 3].cpu().numpy()
+    extra = {"energy_rel_range": float((E.max() - E.min()) / abs(E[0])), "nsteps_per_run": nsteps,
+             "launch": api.get_config("md_run", n, "fp64")}
+    if not args.no_cpu:
+        from oracle import oracle as O
+
+        k = 3 if which == "rf32768" else nsteps
+        t0 = time.perf_counter()
+        O.md_run(st0, d["q"], d["m"], d["trap"], 0.0, d["dt"], k, every=every if which == "cloud1024" else 0)
+        t = time.perf_counter() - t0
+        extra["cpu_baseline"] = {"value": float(n) * n * k / t, "unit": "pairs/s", "cores": len(os.sched_getaffinity(0)),
+                                 "kind": "oracle", "sample": f"oracle md_run (compensated sums), {k} steps, {t:.1f} s"}
+    wl = ("cloud1024: N=1024, Gaussian 20 um, 10 mK, static trap 2pi(1,1,0.2) MHz, dt=1 ns, 100 steps, energies "
+          "every step" if which == "cloud1024" else
+          "rf32768: N=32768 uniform ellipsoid (150,150,1000) um, RF a=0 q=0.3 Omega=2pi 10 MHz, wz=2pi 0.1 MHz, "
+          "dt=5 ns, 1000 steps, energies every 50")
+    return _line("pair interactions/s (FP64 velocity-Verlet run)", float(n) * n * nsteps / (ms * 1e-3), "pairs/s",
+                 reps, args.warmup, ms / nsteps, wl, extra)
+
+
+def bench_kz(args):
+    """kz512: 512 runs, N uniform in [64, 4096], ramp, in one batched
+    launch; FP64 and mixed.  --steps sets the steps per run (10000 in the
+    full workload)."""
+    np, torch, api, inputs, dev = _setup()
+    from paper_2106_11143_amd import drivers
+
+    nsteps = args.steps if args.steps != 50 else 1000
+    d = inputs.kz512(nsteps=nsteps)
+    offs = d["offsets"]
+    ns = np.diff(offs)
+    pairs = float((ns.astype(np.float64) ** 2).sum()) * nsteps
+    st0 = inputs.state9(d)
+    q, m = dev(d["q"]), dev(d["m"])
+    res = {}
+    for prec in ("fp64", "mixed"):
+        ts = [dev(st0[k]) for k in range(9)]
+        torch.cuda.synchronize()
+        e0, e1 = _timer(torch)
+        e0.record()
+        api.md_run(ts, q, m, d["traps"], 0.0, d["dt"], nsteps, offsets=offs, prec=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        got = np.stack([t.cpu().numpy() for t in ts[:3]])
+        defects = [drivers.count_defects(*got[:, offs[r]:offs[r + 1]]) for r in range(d["nrun"])]
+        res[prec] = {"ms": ms, "runs_per_s": d["nrun"] / (ms * 1e-3), "pairs_per_s": pairs / (ms * 1e-3),
+                     "defects_mean": float(np.mean(defects)), "finite": bool(np.isfinite(got).all())}
+    extra = {"mixed": res["mixed"], "fp64": res["fp64"], "nrun": d["nrun"], "nsteps_per_run": nsteps,
+             "sum_N2": float((ns.astype(np.float64) ** 2).sum())}
+    if not args.no_cpu:
+        from oracle import oracle as O
+
+        order = np.argsort(-ns)[:16]
+        k = 2
+        t0 = time.perf_counter()
+        cpairs = 0.0
+        for r in order:
+            sl = slice(offs[r], offs[r + 1])
+            O.md_run(st0[:, sl], d["q"][sl], d["m"][sl], d["trap"], 0.0, d["dt"], k)
+            cpairs += float(ns[r]) ** 2 * k
+        t = time.perf_counter() - t0
+        extra["cpu_baseline"] = {"value": cpairs / t, "unit": "pairs/s", "cores": len(os.sched_getaffinity(0)),
+                                 "kind": "oracle", "sample": f"oracle md_run, 16 largest runs x {k} steps, {t:.1f} s"}
+    return _line("pair interactions/s (FP64 batched ensemble)", res["fp64"]["pairs_per_s"], "pairs/s", 1, 0,
+                 res["fp64"]["ms"] / nsteps,
+                 f"kz512: 512 runs, N~U[64,4096], wx,wy 2pi 1.5->0.6 MHz over 20 us, wz 2pi 0.15 MHz, dt 2 ns, "
+                 f"{nsteps} steps", extra)
+
+
+def bench_crystal(args):
+    """crystal8192: minimised crystal, 32 lowest normal modes by block
+    Lanczos on the HVP kernel, and the 2000-step trajectory gradient with
+    checkpoints every 50 steps, checked against central differences."""
+    np, torch, api, inputs, dev = _setup()
+    from paper_2106_11143_amd import drivers
+
+    d = inputs.crystal8192()
+    n, trap = d["n"], d["trap"]
+    q, m = dev(d["q"]), dev(d["m"])
+    t0 = time.perf_counter()
+    r, info = drivers.minimise(dev(np.stack([d["x"], d["y"], d["z"]])), q, m, trap, ftol_rel=1e-10)
+    torch.cuda.synchronize()
+    t_min = time.perf_counter() - t0
+    # HVP throughput at 8 vectors per pass
+    V = dev(np.random.Generator(np.random.PCG64(1)).normal(size=(8, 3, n)))
+    rows = [r[c].contiguous() for c in range(3)]
+    api.coulomb_hvp(*rows, q, V, m, trap)
+    torch.cuda.synchronize()
+    e0, e1 = _timer(torch)
+    e0.record()
+    for _ in range(10):
+        api.coulomb_hvp(*rows, q, V, m, trap)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_hvp = e0.elapsed_time(e1) / 10
+    t0 = time.perf_counter()
+    lam, vecs, resid = drivers.lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=3200)
+    torch.cuda.synchronize()
+    t_lan = time.perf_counter() - t0
+    wz2 = trap["wz"] ** 2
+    lam = lam.cpu().numpy()
+    st = np.zeros((9, n))
+    st[:3] = r.cpu().numpy()
+    st[3], st[4], st[5] = d["vx"], d["vy"], d["vz"]
+    t0 = time.perf_counter()
+    L, g, _ = drivers.traj_grad(dev(st), q, m, trap, d["dt"], d["nsteps"], checkpoint_every=d["checkpoint_every"])
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    g = g.cpu().numpy()
+
+    def loss(tr):
+        s = [dev(st[k]) for k in range(9)]
+        api.md_run(s, q, m, tr, 0.0, d["dt"], d["nsteps"])
+        return float(sum(((s[c] - dev(st[c])) ** 2).sum() for c in range(3))) / n
+
+    fd = {}
+    for c, key in ((0, "wx"), (2, "wz")):
+        h = 1e-6 * trap[key]
+        tp, tm = dict(trap), dict(trap)
+        tp[key] += h
+        tm[key] -= h
+        fd[key] = {"adjoint": float(g[c]), "central_fd": (loss(tp) - loss(tm)) / (2 * h)}
+    extra = {"minimise_s": t_min, "minimise": info, "hvp_ms_8vec": ms_hvp, "lanczos_s": t_lan,
+             "lowest_over_wz2": [float(v) for v in lam[:6] / wz2],
+             "zero_mode_rel": float(abs(lam[0]) / wz2), "axial_com_rel": float(np.min(np.abs(lam - wz2)) / wz2),
+             "lanczos_max_residual": float(resid.max()), "traj_grad_s": t_grad, "msd": L, "grad_fd": fd}
+    return _line("HVP pair-vector interactions/s (FP64, 8 vectors per pass)", float(n) * n * 8 / (ms_hvp * 1e-3),
+                 "pairs*vectors/s", 10, 1, ms_hvp,
+                 "crystal8192: N=8192 minimised crystal, 2pi(1,1,0.05) MHz; Lanczos 32 lowest; 2000-step adjoint "
+                 "gradient, checkpoints every 50", extra)
+
+
+OTHER_WORKLOADS = {
+    "cloud1024": lambda a: bench_md_single(a, "cloud1024"),
+    "rf32768": lambda a: bench_md_single(a, "rf32768"),
+    "kz512": bench_kz,
+    "crystal8192": bench_crystal,
+}
 
 
 if __name__ == "__main__":

@@ -3,8 +3,8 @@ path; every force, energy, Hessian product and integration step runs in the
 HIP kernels, torch only supplies element-wise glue and the small dense
 algebra of Lanczos).
 
-- minimise: FIRE relaxation (Bitzek et al., PRL 97, 170201 (2006)) to the
-  Coulomb crystal of a trap.
+- minimise: L-BFGS with Hessian-vector Newton step lengths (default) or FIRE
+  (Bitzek et al., PRL 97, 170201 (2006)), to the Coulomb crystal of a trap.
 - lanczos_lowest: block Lanczos with full reorthogonalisation on the
   mass-weighted Hessian M^-1/2 H M^-1/2 (eigenvalues = squared normal-mode
   angular frequencies), several vectors per HVP kernel pass.
@@ -34,42 +34,91 @@ def total_force(r, q, m, trap, t=0.0, eps2=0.0, prec="fp64"):
     return F - m.reshape(1, -1) * k * r
 
 
-def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, max_iter=400000):
-    """Relaxes positions r (3, n) (copied) to a minimum of U_C + U_trap with
-    FIRE.  Stops when max_i |F_i| <= ftol_rel * k_C e^2 / a^2, a being the ion
-    spacing scale (3 k_C e^2 / (m w_max^2))^(1/3).  Returns (r_min, info)."""
-    r = r.clone()
+def _force_scale(m, trap):
     k = trap_k(trap, 0.0)
     wmax = math.sqrt(max(k))
     e2kc = 2.307077552e-28  # k_C e^2 (J m), only for the stopping scale
-    mbar = float(m.mean())
-    a = (3.0 * e2kc / (mbar * wmax * wmax)) ** (1.0 / 3.0)
-    fscale = e2kc / (a * a)
-    v = torch.zeros_like(r)
-    dt_max, dt = 0.2 / wmax, 0.05 / wmax
-    alpha, n_pos = 0.1, 0
-    it = 0
+    a = (3.0 * e2kc / (float(m.mean()) * wmax * wmax)) ** (1.0 / 3.0)
+    return e2kc / (a * a), a, wmax
+
+
+def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, max_iter=100000, method="lbfgs", memory=20):
+    """Relaxes positions r (3, n) (copied) to a minimum of U_C + U_trap.
+
+    method "lbfgs": limited-memory BFGS (two-loop recursion, `memory` pairs)
+    whose step length along each direction p is the Newton step
+    -(g.p)/(p.H p), with H p from the HVP kernel, capped at 0.2 ion spacings
+    per ion.  method "fire": FIRE.  Stops when max_i |F_i| <= ftol_rel *
+    k_C e^2 / a^2, a = (3 k_C e^2 / (m w_max^2))^(1/3).  Returns (r_min, info)."""
+    r = r.clone()
+    fscale, a, wmax = _force_scale(m, trap)
     minv = 1.0 / m.reshape(1, -1)
-    F = total_force(r, q, m, trap, 0.0, eps2)
-    for it in range(max_iter):
-        fmax = float(F.norm(dim=0).max())
-        if fmax <= ftol_rel * fscale:
-            break
-        v = v + dt * F * minv
-        P = float((F * v).sum())
-        if P > 0:
-            v = (1 - alpha) * v + alpha * (v.norm() / F.norm()) * F
-            n_pos += 1
-            if n_pos > 5:
-                dt = min(dt * 1.1, dt_max)
-                alpha *= 0.99
-        else:
-            v.zero_()
-            dt *= 0.5
-            alpha, n_pos = 0.1, 0
-        r = r + dt * v
-        F = total_force(r, q, m, trap, 0.0, eps2)
-    info = {"iters": it, "fmax_rel": float(F.norm(dim=0).max()) / fscale, "force_scale": fscale}
+    tol = ftol_rel * fscale
+    g = -total_force(r, q, m, trap, 0.0, eps2)
+    it = 0
+    if method == "fire":
+        v = torch.zeros_like(r)
+        dt_max, dt = 0.2 / wmax, 0.05 / wmax
+        alpha, n_pos = 0.1, 0
+        for it in range(max_iter):
+            if float(g.norm(dim=0).max()) <= tol:
+                break
+            v = v - dt * g * minv
+            P = -float((g * v).sum())
+            if P > 0:
+                v = (1 - alpha) * v - alpha * (v.norm() / g.norm()) * g
+                n_pos += 1
+                if n_pos > 5:
+                    dt = min(dt * 1.1, dt_max)
+                    alpha *= 0.99
+            else:
+                v.zero_()
+                dt *= 0.5
+                alpha, n_pos = 0.1, 0
+            r = r + dt * v
+            g = -total_force(r, q, m, trap, 0.0, eps2)
+    else:
+        S, Y = [], []
+        h0 = 1.0 / (float(m.mean()) * wmax * wmax)
+        cap = 0.2 * a
+        for it in range(max_iter):
+            if float(g.norm(dim=0).max()) <= tol:
+                break
+            z = g.clone()
+            al = []
+            for s, y in reversed(list(zip(S, Y))):
+                a_ = float((s * z).sum()) / float((y * s).sum())
+                al.append(a_)
+                z = z - a_ * y
+            gamma = float((S[-1] * Y[-1]).sum()) / float((Y[-1] * Y[-1]).sum()) if S else h0
+            z = gamma * z
+            for (s, y), a_ in zip(zip(S, Y), reversed(al)):
+                b = float((y * z).sum()) / float((y * s).sum())
+                z = z + (a_ - b) * s
+            p = -z
+            gp = float((g * p).sum())
+            if gp >= 0:  # not a descent direction: restart from steepest descent
+                S.clear()
+                Y.clear()
+                p = -h0 * g
+                gp = float((g * p).sum())
+            Hp = api.coulomb_hvp(*_rows(r), q, p.contiguous(), m, trap, 0.0, eps2)
+            pHp = float((p * Hp).sum())
+            step = (-gp / pHp if pHp > 0 else 1.0) * p
+            mx = float(step.norm(dim=0).max())
+            if mx > cap:
+                step = step * (cap / mx)
+            r = r + step
+            gn = -total_force(r, q, m, trap, 0.0, eps2)
+            y = gn - g
+            if float((step * y).sum()) > 0:
+                S.append(step)
+                Y.append(y)
+                if len(S) > memory:
+                    S.pop(0)
+                    Y.pop(0)
+            g = gn
+    info = {"method": method, "iters": it, "fmax_rel": float(g.norm(dim=0).max()) / fscale, "force_scale": fscale}
     return r, info
 
 
