@@ -122,70 +122,74 @@ def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, max_iter=100000, method="l
     return r, info
 
 
-def lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=2400, eps2=0.0, seed=0, tol=1e-9):
-    """Lowest k eigenpairs of the mass-weighted Hessian of U_C + U_trap at r.
-    Returns (eigenvalues (k,), eigenvectors (k, 3, n) in mass-weighted
-    coordinates, residual norms (k,))."""
+def lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=12000, eps2=0.0, seed=0, tol=1e-8, check_every=20,
+                   hvp=None):
+    """Lowest k eigenpairs of the mass-weighted Hessian M^-1/2 H M^-1/2 of
+    U_C + U_trap at r (eigenvalues = squared mode angular frequencies).
+
+    Block Lanczos (`block` vectors per HVP kernel pass) with full
+    reorthogonalisation against a preallocated basis.  The projected matrix
+    is block tridiagonal, i.e. banded with bandwidth `block`, so its lowest
+    Ritz pairs come from a banded symmetric eigensolver.  Stops when every
+    wanted Ritz residual |A u - theta u| is below tol * theta_k, or when the
+    basis reaches maxdim.  `hvp(V)` may replace the kernel call
+    (V: (B, 3, n) -> H V).  Returns (eigenvalues (k,), vectors (k, 3, n) in
+    mass-weighted coordinates, residual norms (k,), info)."""
+    from scipy.linalg import eig_banded
+
     n = r.shape[1]
     N3 = 3 * n
-    dev = r.device
+    dev, dt = r.device, r.dtype
     sm = torch.sqrt(m).reshape(1, -1)
+    if hvp is None:
+        hvp = lambda vv: api.coulomb_hvp(*_rows(r), q, vv.contiguous(), m, trap, 0.0, eps2)
 
-    def A(V):  # V: (N3, B) -> (N3, B)
+    def A(V):  # (N3, B) -> (N3, B)
         B = V.shape[1]
-        vv = (V.T.reshape(B, 3, n) / sm).contiguous()
-        hv = api.coulomb_hvp(*_rows(r), q, vv, m, trap, 0.0, eps2)
-        return (hv / sm).reshape(B, N3).T
+        return (hvp((V.T.reshape(B, 3, n) / sm).contiguous()) / sm).reshape(B, N3).T
 
+    maxdim = max(block, min(maxdim, N3) // block * block)
+    nblk = maxdim // block
+    Q = torch.empty(N3, maxdim + block, dtype=dt, device=dev)
     g = torch.Generator(device="cpu").manual_seed(seed)
-    Q0 = torch.randn(N3, block, generator=g, dtype=torch.float64).to(dev)
-    Q0, _ = torch.linalg.qr(Q0)
-    Qs = [Q0]
-    As, Bs = [], []
+    Q[:, :block] = torch.linalg.qr(torch.randn(N3, block, generator=g, dtype=dt))[0].to(dev)
+    band = np.zeros((block + 1, maxdim))  # band[d, c] = T[c + d, c]
     Bprev = None
-    steps = max(1, min(maxdim, N3) // block)
-    theta = None
-    for j in range(steps):
-        Qj = Qs[-1]
+    theta = S = res = None
+    used = 0
+    for j in range(nblk):
+        c0, c1 = j * block, (j + 1) * block
+        Qj = Q[:, c0:c1]
         W = A(Qj)
         if Bprev is not None:
-            W = W - Qs[-2] @ Bprev.T
+            W = W - Q[:, c0 - block:c0] @ Bprev.T
         Aj = Qj.T @ W
         Aj = 0.5 * (Aj + Aj.T)
         W = W - Qj @ Aj
-        Qall = torch.cat(Qs, dim=1)
         for _ in range(2):
-            W = W - Qall @ (Qall.T @ W)
+            W = W - Q[:, :c1] @ (Q[:, :c1].T @ W)
         Qn, Bj = torch.linalg.qr(W)
-        As.append(Aj)
-        Bs.append(Bj)
+        Q[:, c1:c1 + block] = Qn
+        Ah, Bh = Aj.cpu().numpy(), Bj.cpu().numpy()
+        for a_ in range(block):  # diagonal block A_j (lower half)
+            for b_ in range(a_ + 1):
+                band[a_ - b_, c0 + b_] = Ah[a_, b_]
+        if c1 < maxdim:  # coupling block B_j = T[c1:c1+block, c0:c1], upper triangular
+            for a_ in range(block):
+                for b_ in range(a_, block):
+                    band[block + a_ - b_, c0 + b_] = Bh[a_, b_]
         Bprev = Bj
-        Qs.append(Qn)
-        if (j + 1) % 25 == 0 or j == steps - 1:
-            T = _block_tridiag(As, Bs[:-1])
-            theta, S = torch.linalg.eigh(T)
-            res = (Bs[-1] @ S[-block:, :k]).norm(dim=0)
-            scale = float(theta.abs().max())
-            if float(res.max()) <= tol * scale:
+        used = c1
+        if (j + 1) % check_every == 0 or j == nblk - 1:
+            kk = min(k, used)
+            theta, S = eig_banded(band[:, :used], lower=True, select="i", select_range=(0, kk - 1))
+            res = np.linalg.norm(Bh @ S[used - block:used, :], axis=0)
+            if np.all(res <= tol * max(abs(theta[-1]), 1e-300)):
                 break
-    T = _block_tridiag(As, Bs[:-1])
-    theta, S = torch.linalg.eigh(T)
-    res = (Bs[-1] @ S[-block:, :k]).norm(dim=0)
-    Qall = torch.cat(Qs[:-1], dim=1)
-    Y = Qall @ S[:, :k]
-    return theta[:k], Y.T.reshape(k, 3, n), res
-
-
-def _block_tridiag(As, Bs):
-    b = As[0].shape[0]
-    s = len(As)
-    T = torch.zeros(s * b, s * b, dtype=As[0].dtype, device=As[0].device)
-    for i, Ai in enumerate(As):
-        T[i * b:(i + 1) * b, i * b:(i + 1) * b] = Ai
-    for i, Bi in enumerate(Bs):
-        T[(i + 1) * b:(i + 2) * b, i * b:(i + 1) * b] = Bi
-        T[i * b:(i + 1) * b, (i + 1) * b:(i + 2) * b] = Bi.T
-    return 0.5 * (T + T.T)
+    Y = Q[:, :used] @ torch.as_tensor(S, dtype=dt, device=dev)
+    info = {"basis": used, "max_residual": float(res.max()), "theta_k": float(theta[-1])}
+    return (torch.as_tensor(theta, dtype=dt, device=dev), Y.T.reshape(-1, 3, n),
+            torch.as_tensor(res, dtype=dt, device=dev), info)
 
 
 def traj_grad(state0, q, m, trap, dt, nsteps, checkpoint_every=50, eps2=0.0, prec="fp64"):

@@ -28,3 +28,34 @@ def test_domain_walls_are_counted():
 
 def test_tiny_chains():
     assert count_defects([0.0, 1.0], [0.0, 0.0], [0.0, 1.0]) == 0
+
+
+def test_block_lanczos_against_dense_eigensolver(oracle):
+    """The Lanczos driver's algorithm, with the oracle's HVP as the operator,
+    reproduces the lowest eigenvalues of the dense mass-weighted Hessian."""
+    import torch
+    from paper_2106_11143_amd import drivers, inputs
+
+    n = 60
+    g = np.random.Generator(np.random.PCG64(4))
+    trap = inputs.pseudo_trap(1e6, 1e6, 0.3e6)
+    pos = g.normal(size=(3, n)) * inputs.crystal_sigma(n, trap["wx"], trap["wy"], trap["wz"])[:, None]
+    q = np.full(n, inputs.E_CHARGE)
+    m = np.full(n, inputs.MASS_40U) * (1.0 + 0.1 * g.random(n))
+
+    def hvp(V):
+        return torch.as_tensor(oracle.hvp(*pos, q, V.numpy(), m=m, trap=trap))
+
+    cols = [oracle.hvp(*pos, q, e.reshape(3, n), m=m, trap=trap).reshape(-1) for e in np.eye(3 * n)]
+    H = np.array(cols).T
+    sm = np.sqrt(np.tile(m, 3))
+    ref = np.linalg.eigvalsh((H / sm[:, None]) / sm[None, :])
+    r = torch.as_tensor(pos)
+    lam, vecs, res, info = drivers.lanczos_lowest(r, torch.as_tensor(q), torch.as_tensor(m), trap, k=6, block=4,
+                                                  maxdim=3 * n, hvp=hvp, check_every=5)
+    scale = np.abs(ref).max()
+    assert np.abs(lam.numpy() - ref[:6]).max() <= 1e-10 * scale
+    # Ritz vectors are eigenvectors of the mass-weighted operator
+    V = vecs.numpy().reshape(6, -1)
+    Av = np.stack([((H @ (v / sm)) / sm) for v in V])
+    assert np.abs(Av - lam.numpy()[:, None] * V).max() <= 1e-8 * scale

@@ -108,7 +108,7 @@ def test_minimiser_and_lanczos_normal_modes(api):
     r, q, m, trap, info = _crystal(n, 1.0e6, 0.05e6)
     print(f"[minimise n={n}] {info}", flush=True)
     assert info["fmax_rel"] <= 1e-12
-    lam, vecs, res = drivers.lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=1200)
+    lam, vecs, res, info = drivers.lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=1200)
     wz2 = trap["wz"] ** 2
     lam = lam.cpu().numpy()
     print(f"[lanczos] lowest/wz^2: {np.round(lam[:8] / wz2, 6)} max res {float(res.max()):.2e}", flush=True)
