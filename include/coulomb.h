@@ -125,11 +125,13 @@ cb_status coulomb_forces(int64_t n, const double* x, const double* y, const doub
                          double eps2, int32_t prec, double* fx, double* fy, double* fz,
                          void* ws, size_t ws_bytes, void* stream);
 
-/* The first stage of coulomb_forces on its own: the all-pairs kernel writes
- * its j-split partial force sums (before the fixed-order sum over splits and
- * the k_C q_i scaling) into the start of ws, as [splits][3][n] doubles;
- * *splits_out (host) receives the number of splits.  For timing the pair loop
- * and for callers that reduce the partials themselves. */
+/* The first stage of coulomb_forces on its own (everything but the final
+ * element-wise pass), for timing the pair loop and for callers that finish
+ * the sums themselves.  With algorithm 0 (see cb_get_config) the all-pairs
+ * kernel leaves its j-split partial force sums, before the fixed-order sum
+ * over splits and the k_C q_i factor, at the start of ws as [splits][3][n]
+ * doubles and *splits_out (host) is the number of splits; with algorithm 1
+ * the start of ws holds the finished forces [3][n] and *splits_out is 0. */
 cb_status coulomb_pair_stage(int64_t n, const double* x, const double* y, const double* z, const double* q,
                              double eps2, int32_t prec, int32_t* splits_out, void* ws, size_t ws_bytes,
                              void* stream);
@@ -204,14 +206,21 @@ cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_pat
 cb_status cb_load_tuning(const char* cache_path);
 
 /* The launch configuration the next call of `op` at (n, prec) will use:
- * out[0] = i-particles per lane, out[1] = workgroup size, out[2] = j-splits,
- * out[3] = 1 if it came from tuning. */
-cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[4]);
+ * out[0] = algorithm (0: every ordered pair evaluated, j-split partial sums;
+ *          1: each unordered pair evaluated once and applied to both ions by
+ *          Newton's third law, forces only, n <= 2^18),
+ * out[1] = i-particles per lane, out[2] = workgroup size (algorithm 0),
+ * out[3] = j-splits (algorithm 0) or j-segment length (algorithm 1),
+ * out[4] = 1 if it came from tuning or cb_set_config. */
+cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]);
 
-/* Forces the launch configuration for (op, n bucket, prec); p, wg, splits as
- * in cb_get_config.  p = wg = splits = 0 removes a forced or tuned entry (back
- * to the built-in heuristic).  CB_EINVAL if unsupported. */
-cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t p, int32_t wg, int32_t splits);
+/* Forces the launch configuration for (op, n power-of-two bucket, prec), with
+ * the fields of cb_get_config.  Algorithm 0: p in {1,2,4} ({1,2} for the HVP
+ * and adjoint), wg in {64,128,256}, splits in 1..64.  Algorithm 1 (forces,
+ * md_step, md_run): p in {2,3}, splits = segment length in {512,1024,2048},
+ * wg ignored.  algo = p = wg = splits = 0 removes a forced or tuned entry
+ * (back to the built-in heuristic).  CB_EINVAL if unsupported. */
+cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t algo, int32_t p, int32_t wg, int32_t splits);
 
 #ifdef __cplusplus
 }

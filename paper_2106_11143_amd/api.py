@@ -90,7 +90,7 @@ def lib() -> C.CDLL:
                 L.cb_autotune.argtypes = [i32, i64, i32, C.c_char_p]
                 L.cb_load_tuning.argtypes = [C.c_char_p]
                 L.cb_get_config.argtypes = [i32, i64, i32, C.POINTER(C.c_int32)]
-                L.cb_set_config.argtypes = [i32, i64, i32, i32, i32, i32]
+                L.cb_set_config.argtypes = [i32, i64, i32, i32, i32, i32, i32]
                 for name in EXPORTS:
                     if name not in ("cb_workspace_size", "cb_last_error"):
                         getattr(L, name).restype = C.c_int
@@ -164,7 +164,7 @@ def _workspace(op, n, nrun=1, nvec=1, prec="fp64", device=None):
 
 
 def reset_config(op, n: int, prec="fp64") -> None:
-    set_config(op, n, prec, 0, 0, 0)
+    set_config(op, n, prec, 0, 0, 0, 0)
 
 
 def clear_workspace_cache() -> None:
@@ -315,11 +315,14 @@ def load_tuning(cache_path: str) -> None:
 
 
 def get_config(op, n: int, prec="fp64") -> dict:
-    out = (C.c_int32 * 4)()
+    out = (C.c_int32 * 5)()
     _check(lib().cb_get_config(_op(op), int(n), _prec(prec), out), "cb_get_config")
-    return dict(p=out[0], wg=out[1], splits=out[2], tuned=bool(out[3]))
+    return dict(algo=out[0], p=out[1], wg=out[2], splits=out[3], tuned=bool(out[4]))
 
 
-def set_config(op, n: int, prec="fp64", p: int = 1, wg: int = 256, splits: int = 1) -> None:
-    """Force a launch configuration (p = wg = splits = 0: back to the default)."""
-    _check(lib().cb_set_config(_op(op), int(n), _prec(prec), int(p), int(wg), int(splits)), "cb_set_config")
+def set_config(op, n: int, prec="fp64", p: int = 1, wg: int = 256, splits: int = 1, algo: int = 0) -> None:
+    """Force a launch configuration (algo = p = wg = splits = 0: back to the
+    default).  algo 1 = the Newton's-third-law force kernel, with p in {2, 3}
+    and splits = segment length in {512, 1024, 2048}."""
+    _check(lib().cb_set_config(_op(op), int(n), _prec(prec), int(algo), int(p), int(wg), int(splits)),
+           "cb_set_config")

@@ -5,6 +5,7 @@
 // it to a JSON-lines cache that cb_load_tuning reads back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -85,7 +86,7 @@ cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_pat
     const int ps_force[] = {1, 2, 4}, ps_hvp[] = {1, 2};
     const int wgs[] = {64, 128, 256};
     const int splits[] = {1, 2, 4, 8, 16, 24, 32, 48, 64};
-    LaunchCfg best{0, 0, 0, 1};
+    LaunchCfg best{0, 0, 0, 1, ALGO_DIRECT};
     float best_ms = 1e30f;
     cb_status rc = CB_OK;
     const int np = hv ? 2 : 3;
@@ -94,7 +95,7 @@ cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_pat
             for (int sp : splits) {
                 const int p = hv ? ps_hvp[ip] : ps_force[ip];
                 if (sp > 1 && n / sp < 64) continue;
-                LaunchCfg c{p, wg, sp, 1};
+                LaunchCfg c{p, wg, sp, 1, ALGO_DIRECT};
                 const int jlen = split_len(n, sp);
                 auto launch = [&]() -> cb_status {
                     if (hv)
@@ -121,6 +122,41 @@ cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_pat
                     best = c;
                 }
             }
+    // the Newton's-third-law kernel (forces only, n <= kSymMaxN)
+    const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
+    if (rc == CB_OK && force_op && n <= kSymMaxN) {
+        size_t need = 0;
+        for (int p : {2, 3})
+            for (int jl : {512, 1024, 2048}) need = std::max(need, sym_ws_bytes(n, p, jl));
+        DevBuf sws, F;
+        if (hipMalloc(&sws.p, need) != hipSuccess || hipMalloc(&F.p, sizeof(double) * 3 * (size_t)n) != hipSuccess)
+            rc = fail(CB_EHIP, "cb_autotune: allocation failed");
+        for (int p : {2, 3})
+            for (int jl : {512, 1024, 2048}) {
+                if (rc) break;
+                LaunchCfg c{p, 64, jl, 1, ALGO_SYM};
+                auto launch = [&]() {
+                    return launch_pair_sym(prec, c, (int)n, x, y, z, q, 0.0, sws.p, static_cast<double*>(F.p), st);
+                };
+                if ((rc = launch())) break;
+                const int reps = 3;
+                (void)hipEventRecord(e0, st);
+                for (int r = 0; r < reps && rc == CB_OK; ++r) rc = launch();
+                (void)hipEventRecord(e1, st);
+                if (rc || hipEventSynchronize(e1) != hipSuccess) {
+                    if (!rc) rc = fail(CB_EHIP, "cb_autotune: timing failed");
+                    break;
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                ms /= reps;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+        (void)hipStreamSynchronize(st);
+    }
     (void)hipStreamSynchronize(st);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -143,8 +179,8 @@ cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_pat
         if (!f) return fail(CB_EINVAL, "cb_autotune: cannot open %s", cache_path);
         std::fprintf(f,
                      "{\"arch\": \"%s\", \"op\": %d, \"prec\": %d, \"bucket\": %d, \"n\": %lld, \"p\": %d, "
-                     "\"wg\": %d, \"splits\": %d, \"ms\": %.6f}\n",
-                     arch_name().c_str(), op, prec, n_bucket(n), (long long)n, best.p, best.wg, best.splits,
+                     "\"wg\": %d, \"splits\": %d, \"algo\": %d, \"ms\": %.6f}\n",
+                     arch_name().c_str(), op, prec, n_bucket(n), (long long)n, best.p, best.wg, best.splits, best.algo,
                      best_ms);
         std::fclose(f);
     }
@@ -160,15 +196,15 @@ cb_status cb_load_tuning(const char* cache_path) {
 
     while (std::fgets(line, sizeof line, f)) {
         char a[64] = {0};
-        int op, prec, bucket, p, wg, sp;
+        int op, prec, bucket, p, wg, sp, algo = 0;
         long long n;
         if (std::sscanf(line,
                         "{\"arch\": \"%63[^\"]\", \"op\": %d, \"prec\": %d, \"bucket\": %d, \"n\": %lld, \"p\": %d, "
-                        "\"wg\": %d, \"splits\": %d",
-                        a, &op, &prec, &bucket, &n, &p, &wg, &sp) != 8)
+                        "\"wg\": %d, \"splits\": %d, \"algo\": %d",
+                        a, &op, &prec, &bucket, &n, &p, &wg, &sp, &algo) < 8)
             continue;
         if (arch != a || op < 0 || op > CB_OP_ADJOINT || n < 1) continue;
-        LaunchCfg c{p, wg, sp, 1};
+        LaunchCfg c{p, wg, sp, 1, algo};
         if (!valid_cfg(op, c)) continue;
         if (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN) {
             put_cfg(CB_OP_FORCES, n, prec, c);

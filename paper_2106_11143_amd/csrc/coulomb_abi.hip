@@ -77,6 +77,18 @@ static long long cfg_key(int op, int prec, int64_t n) {
 // idle; ILP comes from the independent FMA chains within a pair.
 LaunchCfg default_cfg(int op, int64_t n, int prec) {
     LaunchCfg c;
+    c.tuned = 0;
+    c.algo = ALGO_DIRECT;
+    (void)prec;
+    const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
+    if (force_op && n >= 16384 && n <= kSymMaxN) {
+        // Newton's third law: each pair once (see pair_sym.hpp)
+        c.algo = ALGO_SYM;
+        c.p = 2;
+        c.wg = 64;
+        c.splits = 1024;
+        return c;
+    }
     c.wg = 64;
     c.p = 1;
     const int64_t waves = (n + 64 * c.p - 1) / (64 * c.p);
@@ -84,8 +96,6 @@ LaunchCfg default_cfg(int op, int64_t n, int prec) {
     s = std::max<int64_t>(1, std::min<int64_t>(s, kMaxSplits));
     s = std::min<int64_t>(s, std::max<int64_t>(1, n / 64));
     c.splits = (int)s;
-    c.tuned = 0;
-    (void)prec;
     return c;
 }
 
@@ -107,6 +117,10 @@ void drop_cfg(int op, int64_t n, int prec) {
 }
 
 bool valid_cfg(int op, const LaunchCfg& c) {
+    const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
+    if (c.algo == ALGO_SYM)
+        return force_op && (c.p == 2 || c.p == 3) && (c.splits == 512 || c.splits == 1024 || c.splits == 2048);
+    if (c.algo != ALGO_DIRECT) return false;
     const bool p_ok = (op == CB_OP_HVP || op == CB_OP_ADJOINT) ? (c.p == 1 || c.p == 2)
                                                                  : (c.p == 1 || c.p == 2 || c.p == 4);
     return p_ok && (c.wg == 64 || c.wg == 128 || c.wg == 256) && c.splits >= 1 && c.splits <= kMaxSplits;
@@ -133,7 +147,17 @@ WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec) {
     const bool hv = (op == CB_OP_HVP || op == CB_OP_ADJOINT);
     if (!batched) {
         L.part = off;
-        off += al(sizeof(double) * (size_t)kMaxSplits * 3 * (hv ? nv : 1) * N);
+        size_t part = sizeof(double) * (size_t)kMaxSplits * 3 * (hv ? nv : 1) * N;
+        const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
+        if (force_op && n <= kSymMaxN) {
+            // room for the symmetric path: finished forces [3][n] then its tiles and partials
+            const int jls[] = {512, 1024, 2048};
+            size_t sym = 0;
+            for (int p : {2, 3})
+                for (int jl : jls) sym = std::max(sym, sym_ws_bytes(n, p, jl));
+            part = std::max(part, al(sizeof(double) * 3 * N) + sym);
+        }
+        off += al(part);
         L.ppot = off;
         if (op == CB_OP_ENERGY || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN)
             off += al(sizeof(double) * (size_t)kMaxSplits * N);
@@ -187,24 +211,27 @@ size_t cb_workspace_size(int32_t op, int64_t n, int32_t nrun, int32_t nvec, int3
     return ws_layout(op, n, nrun, nvec).total;
 }
 
-cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[4]) {
+cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]) {
     if (!out || n < 1 || op < 0 || op > CB_OP_ADJOINT) return fail(CB_EINVAL, "cb_get_config: bad argument");
     LaunchCfg c = get_cfg(op, n, prec);
-    out[0] = c.p;
-    out[1] = c.wg;
-    out[2] = c.splits;
-    out[3] = c.tuned;
+    out[0] = c.algo;
+    out[1] = c.p;
+    out[2] = c.wg;
+    out[3] = c.splits;
+    out[4] = c.tuned;
     return ok();
 }
 
-cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t p, int32_t wg, int32_t splits) {
-    LaunchCfg c{p, wg, splits, 1};
-    if (p == 0 && wg == 0 && splits == 0 && n >= 1 && op >= 0 && op <= CB_OP_ADJOINT) {
+cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t algo, int32_t p, int32_t wg, int32_t splits) {
+    if (n < 1 || op < 0 || op > CB_OP_ADJOINT) return fail(CB_EINVAL, "cb_set_config: bad argument");
+    if (algo == 0 && p == 0 && wg == 0 && splits == 0) {
         drop_cfg(op, n, prec);
         return ok();
     }
-    if (n < 1 || op < 0 || op > CB_OP_ADJOINT || !valid_cfg(op, c))
-        return fail(CB_EINVAL, "cb_set_config: unsupported configuration p=%d wg=%d splits=%d", p, wg, splits);
+    LaunchCfg c{p, algo == ALGO_SYM ? 64 : wg, splits, 1, algo};
+    if (!valid_cfg(op, c) || (algo == ALGO_SYM && n > kSymMaxN))
+        return fail(CB_EINVAL, "cb_set_config: unsupported configuration algo=%d p=%d wg=%d splits=%d", algo, p, wg,
+                    splits);
     put_cfg(op, n, prec, c);
     return ok();
 }

@@ -42,9 +42,33 @@ struct PairRun {
 static PairRun plan(int op, int64_t n, int prec) {
     PairRun r;
     r.cfg = get_cfg(op, n, prec);
+    if (r.cfg.algo != ALGO_DIRECT) r.cfg = default_cfg(CB_OP_ENERGY, n, prec);  // direct kernel needed
     r.jlen = split_len(n, r.cfg.splits);
     r.S = n_splits(n, r.jlen);
     return r;
+}
+
+static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+// The force-only pair stage with the configured algorithm.  Direct: partial
+// sums [S][3][n] at ws+L.part (to be scaled by k_C q_i).  Symmetric: the
+// finished forces [3][n] at ws+L.part (S = 1, prescaled), its tiles and
+// partials after them.
+static cb_status force_stage(int op, int prec, int64_t n, const double* x, const double* y, const double* z,
+                             const double* q, double eps2, void* ws, const WsLayout& L, hipStream_t st, int* S_out,
+                             bool* prescaled) {
+    const LaunchCfg cfg = get_cfg(op, n, prec);
+    double* part = at(ws, L.part);
+    if (cfg.algo == ALGO_SYM && n <= kSymMaxN) {
+        *S_out = 1;
+        *prescaled = true;
+        void* scratch = static_cast<char*>(ws) + L.part + al256(sizeof(double) * 3 * (size_t)n);
+        return launch_pair_sym(prec, cfg, (int)n, x, y, z, q, eps2, scratch, part, st);
+    }
+    const PairRun pr = plan(op, n, prec);
+    *S_out = pr.S;
+    *prescaled = false;
+    return launch_pair(prec, pr.cfg, true, false, (int)n, x, y, z, q, eps2, pr.jlen, part, nullptr, st);
 }
 
 // Single-run velocity-Verlet driver shared by md_step and md_run.
@@ -79,13 +103,30 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
     const bool rec0 = energies && every > 0;
     const bool init = (flags & CB_INIT_ACCEL) != 0;
 
+    bool prescaled_now = false;
+    // Force (and potential) pair launch: the potential needs the direct kernel;
+    // forces alone use the configured algorithm.
+    auto pairs = [&](bool force, bool pot) -> cb_status {
+        if (force && !pot) {
+            int S = 0;
+            bool pre = false;
+            cb_status r = force_stage(op, prec, n, s->x, s->y, s->z, q, eps2, ws, L, st, &S, &pre);
+            E.S = S;
+            prescaled_now = pre;
+            return r;
+        }
+        E.S = pr.S;
+        prescaled_now = false;
+        return launch_pair(prec, pr.cfg, force, pot, (int)n, s->x, s->y, s->z, q, eps2, pr.jlen, part, ppot, st);
+    };
+
     // Step 0: initial acceleration and/or energies, then the first drift.
     if (init || rec0) {
-        if ((rc = launch_pair(prec, pr.cfg, init, rec0, (int)n, s->x, s->y, s->z, q, eps2, pr.jlen, part, ppot, st)))
-            return rc;
+        if ((rc = pairs(init, rec0))) return rc;
     }
     E.step = 0;
     E.mode = (init ? EPI_ACCEL : 0u) | (rec0 ? EPI_ENERGY : 0u) | (nsteps > 0 ? EPI_DRIFT : 0u);
+    if (prescaled_now) E.mode |= EPI_PRESCALED;
     if (E.mode) {
         k_epilogue<<<nb, kEpiThreads, 0, st>>>(E);
         if ((rc = check_launch("k_epilogue"))) return rc;
@@ -96,10 +137,9 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
     }
     for (int64_t k = 1; k <= nsteps; ++k) {
         const bool rec = rec0 && (k % every == 0);
-        if ((rc = launch_pair(prec, pr.cfg, true, rec, (int)n, s->x, s->y, s->z, q, eps2, pr.jlen, part, ppot, st)))
-            return rc;
+        if ((rc = pairs(true, rec))) return rc;
         E.step = k;
-        E.mode = EPI_KICK | (rec ? EPI_ENERGY : 0u) | (k < nsteps ? EPI_DRIFT : 0u);
+        E.mode = EPI_KICK | (rec ? EPI_ENERGY : 0u) | (k < nsteps ? EPI_DRIFT : 0u) | (prescaled_now ? EPI_PRESCALED : 0u);
         k_epilogue<<<nb, kEpiThreads, 0, st>>>(E);
         if ((rc = check_launch("k_epilogue"))) return rc;
         if (rec) {
@@ -161,19 +201,18 @@ cb_status coulomb_forces(int64_t n, const double* x, const double* y, const doub
     if (overlaps(fx, fy, n) || overlaps(fx, fz, n) || overlaps(fy, fz, n))
         return fail(CB_EINVAL, "coulomb_forces: outputs overlap");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const PairRun pr = plan(CB_OP_FORCES, n, prec);
-    double* part = at(ws, L.part);
-    if ((rc = launch_pair(prec, pr.cfg, true, false, (int)n, x, y, z, q, eps2, pr.jlen, part, nullptr, st)))
-        return rc;
+    int S = 0;
+    bool prescaled = false;
+    if ((rc = force_stage(CB_OP_FORCES, prec, n, x, y, z, q, eps2, ws, L, st, &S, &prescaled))) return rc;
     EpiParams E{};
     E.n = (int)n;
-    E.S = pr.S;
-    E.part = part;
+    E.S = S;
+    E.part = at(ws, L.part);
     E.q = q;
     E.fx = fx;
     E.fy = fy;
     E.fz = fz;
-    E.mode = EPI_FORCES;
+    E.mode = EPI_FORCES | (prescaled ? EPI_PRESCALED : 0u);
     E.flags = flags_ptr();
     if (!E.flags) return fail(CB_EHIP, "coulomb_forces: device flag symbol not found");
     k_epilogue<<<(int)((n + kEpiThreads - 1) / kEpiThreads), kEpiThreads, 0, st>>>(E);
@@ -188,11 +227,12 @@ cb_status coulomb_pair_stage(int64_t n, const double* x, const double* y, const 
     cb_status rc = check_common("coulomb_pair_stage", n, prec, eps2, ws, ws_bytes, L.total);
     if (rc) return rc;
     if (!x || !y || !z || !q || !splits_out) return fail(CB_EINVAL, "coulomb_pair_stage: NULL argument");
-    const PairRun pr = plan(CB_OP_FORCES, n, prec);
-    if ((rc = launch_pair(prec, pr.cfg, true, false, (int)n, x, y, z, q, eps2, pr.jlen, at(ws, L.part), nullptr,
-                          static_cast<hipStream_t>(stream))))
+    int S = 0;
+    bool prescaled = false;
+    if ((rc = force_stage(CB_OP_FORCES, prec, n, x, y, z, q, eps2, ws, L, static_cast<hipStream_t>(stream), &S,
+                          &prescaled)))
         return rc;
-    *splits_out = pr.S;
+    *splits_out = prescaled ? 0 : S;
     return ok();
 }
 

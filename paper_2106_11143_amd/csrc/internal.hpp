@@ -13,12 +13,16 @@ constexpr int kMaxSplits = 64;       // j-splits per launch
 constexpr int kMaxVec = 8;           // HVP vectors per call
 constexpr int kMaxBatchIons = 4096;  // ions per run in the batched kernel (LDS bound)
 constexpr int kEpiBlock = 256;       // threads per element-wise block
+constexpr int64_t kSymMaxN = int64_t(1) << 18;  // largest n for the symmetric kernel (partials grow as n^2)
+
+enum : int { ALGO_DIRECT = 0, ALGO_SYM = 1 };
 
 struct LaunchCfg {
     int p;       // i-particles per lane
-    int wg;      // threads per workgroup
-    int splits;  // requested j-splits
+    int wg;      // threads per workgroup (direct)
+    int splits;  // direct: requested j-splits; symmetric: segment length JL
     int tuned;   // 1 if set by tuning or cb_set_config
+    int algo;    // ALGO_DIRECT or ALGO_SYM
 };
 
 struct WsLayout {
@@ -41,6 +45,12 @@ int n_splits(int64_t n, int jlen);
 WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec);
 
 bool trap_ok(const cb_trap* t, const char* who, cb_status* st);
+
+// Symmetric (Newton's third law) force path (pair.hip): workspace bytes for
+// (n, p, JL), and the launch sequence ending with finished forces F[3][n].
+size_t sym_ws_bytes(int64_t n, int p, int jl);
+cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, const double* y, const double* z,
+                          const double* q, double eps2, void* ws, double* F, hipStream_t st);
 
 // Launches of the pair kernels (pair.hip).
 cb_status launch_pair(int prec, const LaunchCfg& c, bool force, bool pot, int n, const double* x,

@@ -4,6 +4,7 @@
 
 #include "internal.hpp"
 #include "pair_kernels.hpp"
+#include "pair_sym.hpp"
 
 namespace cb {
 
@@ -53,6 +54,75 @@ cb_status launch_pair(int prec, const LaunchCfg& c, bool force, bool pot, int n,
     }
     if (!okk) return fail(CB_EINVAL, "launch_pair: unsupported precision %d / p %d", prec, c.p);
     return check_launch("k_pair");
+}
+
+// --------------------------------------------------------- symmetric path
+static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+static int64_t sym_tiles(int64_t n, int IB, int JL) {
+    const int nI = (int)((n + IB - 1) / IB);
+    int64_t T = 0;
+    for (int I = 0; I < nI; ++I) T += sym_nseg((int)n, IB, JL, I);
+    return T;
+}
+
+// Workspace carve-up: rowstart[nI+1] | tiles[T] | Pi[T][3][IB] | R[T][3][JL]
+size_t sym_ws_bytes(int64_t n, int p, int jl) {
+    const int IB = 64 * p;
+    const int64_t nI = (n + IB - 1) / IB;
+    const int64_t T = sym_tiles(n, IB, jl);
+    return al256(sizeof(int) * (nI + 1)) + al256(sizeof(int2) * (T + 1)) +
+           al256(sizeof(double) * 3 * IB * (T + 1)) + al256(sizeof(double) * 3 * (size_t)jl * (T + 1));
+}
+
+template <int PREC, int P>
+static void go_sym(int n, int JL, int64_t T, const double* x, const double* y, const double* z, const double* q,
+                   double eps2, const int2* tiles, double* Pi, double* R, hipStream_t st) {
+    k_pair_sym<PREC, P><<<(unsigned)T, 64, 0, st>>>(n, x, y, z, q, eps2, JL, tiles, Pi, R);
+}
+
+cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, const double* y, const double* z,
+                          const double* q, double eps2, void* ws, double* F, hipStream_t st) {
+    const int P = c.p, JL = c.splits, IB = 64 * P;
+    if ((P != 2 && P != 3) || JL < 8 || JL % 8) return fail(CB_EINVAL, "launch_pair_sym: bad configuration");
+    const int nI = (n + IB - 1) / IB;
+    const int64_t T = sym_tiles(n, IB, JL);
+    char* base = static_cast<char*>(ws);
+    int* rowstart = reinterpret_cast<int*>(base);
+    base += al256(sizeof(int) * (nI + 1));
+    int2* tiles = reinterpret_cast<int2*>(base);
+    base += al256(sizeof(int2) * (T + 1));
+    double* Pi = reinterpret_cast<double*>(base);
+    base += al256(sizeof(double) * 3 * IB * (T + 1));
+    double* R = reinterpret_cast<double*>(base);
+    k_sym_rows<<<1, 1, 0, st>>>(n, IB, JL, nI, rowstart);
+    k_sym_fill<<<(nI + 255) / 256, 256, 0, st>>>(n, IB, JL, nI, rowstart, tiles);
+    cb_status rc = check_launch("k_sym_rows/fill");
+    if (rc) return rc;
+    if (T > 0) {
+        bool okk = true;
+        switch (prec * 16 + P) {
+            case PREC_FP64 * 16 + 2: go_sym<PREC_FP64, 2>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_FP64 * 16 + 3: go_sym<PREC_FP64, 3>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_MIXED * 16 + 2: go_sym<PREC_MIXED, 2>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_MIXED * 16 + 3: go_sym<PREC_MIXED, 3>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_IEEE * 16 + 2: go_sym<PREC_IEEE, 2>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_IEEE * 16 + 3: go_sym<PREC_IEEE, 3>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_FP32 * 16 + 2: go_sym<PREC_FP32, 2>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_FP32 * 16 + 3: go_sym<PREC_FP32, 3>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            default: okk = false;
+        }
+        if (!okk) return fail(CB_EINVAL, "launch_pair_sym: unsupported precision %d", prec);
+        if ((rc = check_launch("k_pair_sym"))) return rc;
+    }
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    switch (prec) {
+        case PREC_FP64: k_sym_finish<PREC_FP64><<<nb, 256, 0, st>>>(n, IB, JL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
+        case PREC_MIXED: k_sym_finish<PREC_MIXED><<<nb, 256, 0, st>>>(n, IB, JL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
+        case PREC_IEEE: k_sym_finish<PREC_IEEE><<<nb, 256, 0, st>>>(n, IB, JL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
+        default: k_sym_finish<PREC_FP32><<<nb, 256, 0, st>>>(n, IB, JL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
+    }
+    return check_launch("k_sym_finish");
 }
 
 }  // namespace cb

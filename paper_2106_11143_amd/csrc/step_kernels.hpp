@@ -14,7 +14,8 @@ enum : unsigned {
     EPI_KICK = 4u,     // a_new = F/m + trap; v += dt/2 (a + a_new); a <- a_new
     EPI_DRIFT = 8u,    // r += v dt + a dt^2/2 (after any kick)
     EPI_ENERGY = 16u,  // per-block sums of K, U_C, U_trap of the resulting state
-    EPI_UC_ONLY = 32u  // energy: only U_C (no m, v, trap)
+    EPI_UC_ONLY = 32u,   // energy: only U_C (no m, v, trap)
+    EPI_PRESCALED = 64u  // part holds finished forces [3][n] (S = 1), not sums to scale by k_C q_i
 };
 
 struct EpiParams {
@@ -51,7 +52,8 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
         if (need_p)
             for (int s = 0; s < P.S; ++s) sp += P.ppot[(size_t)s * n + i];
         const double c = kCoulomb * P.q[i];
-        const double Fx = c * sx, Fy = c * sy, Fz = c * sz;
+        const double cf = (mode & EPI_PRESCALED) ? 1.0 : c;
+        const double Fx = cf * sx, Fy = cf * sy, Fz = cf * sz;
         bool ok = true;
         if (mode & EPI_FORCES) {
             P.fx[i] = Fx;

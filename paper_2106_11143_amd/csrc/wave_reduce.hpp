@@ -1,0 +1,76 @@
+// Wave-wide reduce-scatter of 24 doubles per lane on gfx950 (wave64).
+//
+// Input: every lane holds v[jj*3 + c] for jj < 8, c < 3.  Output: every lane
+// of the 8-lane group g = lane >> 3 holds in out[c] the sum over all 64 lanes
+// of v[g*3 + c].  Six halving steps, each exchanging with a partner lane and
+// keeping half of the remaining values:
+//   lanes 0-31 / 32-63   v_permlane32_swap (keep indices 0-11 / 12-23)
+//   rows 0,2 / rows 1,3  v_permlane16_swap (keep 0-5 / 6-11 of those)
+//   lane bit 3           DPP row_ror:8      (keep 0-2 / 3-5 of those)
+// then an all-reduce of the 3 survivors over the 8 lanes of the group (DPP
+// row_half_mirror, quad_perm [2,3,0,1], quad_perm [1,0,3,2]).  The swaps move
+// 32-bit halves, so each 64-bit value takes two swaps.  All lanes of a group
+// end with the same sum up to the order of the last three additions; callers
+// store it from one lane.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace cb {
+
+__device__ __forceinline__ double pack_d(unsigned lo, unsigned hi) {
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+__device__ __forceinline__ unsigned lo_u(double d) {
+    return static_cast<unsigned>(__builtin_bit_cast(unsigned long long, d));
+}
+__device__ __forceinline__ unsigned hi_u(double d) {
+    return static_cast<unsigned>(__builtin_bit_cast(unsigned long long, d) >> 32);
+}
+
+// lanes 0-31 return a(l) + a(l+32); lanes 32-63 return b(l-32) + b(l).
+__device__ __forceinline__ double swap32_add(double a, double b) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(lo_u(a), lo_u(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(hi_u(a), hi_u(b), false, false);
+    return pack_d(lo[0], hi[0]) + pack_d(lo[1], hi[1]);
+}
+
+// rows 0 and 2 return a(l) + a(l+16); rows 1 and 3 return b(l-16) + b(l).
+__device__ __forceinline__ double swap16_add(double a, double b) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(lo_u(a), lo_u(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(hi_u(a), hi_u(b), false, false);
+    return pack_d(lo[0], hi[0]) + pack_d(lo[1], hi[1]);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    const unsigned lo = __builtin_amdgcn_mov_dpp(static_cast<int>(lo_u(x)), CTRL, 0xf, 0xf, false);
+    const unsigned hi = __builtin_amdgcn_mov_dpp(static_cast<int>(hi_u(x)), CTRL, 0xf, 0xf, false);
+    return pack_d(lo, hi);
+}
+
+constexpr int kDppRowRor8 = 0x128;
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
+
+__device__ __forceinline__ void reduce_scatter24(const double (&v)[24], double (&out)[3]) {
+    double u[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) u[k] = swap32_add(v[k], v[k + 12]);
+    double w[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) w[k] = swap16_add(u[k], u[k + 6]);
+    const bool upper8 = (__lane_id() & 8) != 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double own = upper8 ? w[c + 3] : w[c];
+        const double send = upper8 ? w[c] : w[c + 3];
+        double x = own + dpp_d<kDppRowRor8>(send);
+        x += dpp_d<kDppRowHalfMirror>(x);
+        x += dpp_d<kDppQuadXor2>(x);
+        x += dpp_d<kDppQuadXor1>(x);
+        out[c] = x;
+    }
+}
+
+}  // namespace cb

@@ -35,7 +35,7 @@ def test_autotune_roundtrip(api, oracle, tmp_path):
     assert not api.get_config("forces", n, "fp64")["tuned"]
     api.load_tuning(cache)
     c2 = api.get_config("forces", n, "fp64")
-    assert c2["tuned"] and (c2["p"], c2["wg"], c2["splits"]) == (c["p"], c["wg"], c["splits"])
+    assert c2["tuned"] and (c2["algo"], c2["p"], c2["splits"]) == (c["algo"], c["p"], c["splits"])
     api.autotune("hvp", 2000, "fp64")
     assert api.get_config("adjoint", 2000, "fp64")["tuned"]
     for op in ("forces", "md_step", "md_run"):

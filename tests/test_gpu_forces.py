@@ -65,6 +65,34 @@ def test_forces_ragged_sizes_and_launch_shapes(api, oracle, p, wg, splits):
     api.clear_workspace_cache()
 
 
+SYM_SIZES = [1, 2, 3, 65, 127, 128, 129, 191, 192, 193, 385, 1000, 2049, 4001]
+SYM_CONFIGS = [(2, 512), (3, 1024), (2, 2048), (3, 512)]
+
+
+@pytest.mark.parametrize("p,jl", SYM_CONFIGS)
+def test_forces_symmetric_kernel_ragged_sizes(api, oracle, p, jl):
+    """The Newton's-third-law kernel: i-blocks of 64p, j-segments of jl,
+    ragged last blocks and segments, sizes with no off-diagonal tile."""
+    from _gpu_util import per_ion_rel
+    for n in SYM_SIZES:
+        g = np.random.Generator(np.random.PCG64(2000 + n))
+        d = dict(x=g.normal(0, 20e-6, n), y=g.normal(0, 20e-6, n), z=g.normal(0, 20e-6, n),
+                 q=inputs.E_CHARGE * g.choice([1.0, 2.0, -1.0], n))
+        eps2 = (1e-7) ** 2 if n % 3 == 0 else 0.0
+        ref = np.stack(oracle.forces(d["x"], d["y"], d["z"], d["q"], eps2=eps2))
+        for prec in ("fp64", "mixed"):
+            api.set_config("forces", n, prec, p=p, splits=jl, algo=1)
+            F = _forces(api, d, prec, eps2=eps2)
+            api.reset_config("forces", n, prec)
+            if n == 1:
+                assert np.all(F == 0.0)
+                continue
+            err = per_ion_rel(F, ref)
+            assert err.max() <= (1e-12 if prec == "fp64" else 1e-7), (n, prec, p, jl, err.max())
+            # each pair is applied to both ions: Newton's third law holds to rounding
+            assert np.linalg.norm(F.sum(axis=1)) <= 1e-13 * np.linalg.norm(F, axis=0).sum()
+
+
 def test_forces_rf32768_full(api, oracle):
     from _gpu_util import per_ion_rel, report
     d = inputs.rf32768()
