@@ -30,9 +30,15 @@ FLOPS_PER_PAIR = 20  # the paper's double loop with +,-,*,/,sqrt counted once ea
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ("paper_2106_11143_amd/csrc/pair_kernels.hpp", "paper_2106_11143_amd/csrc/rsqrt.hpp",
+KERNEL_SOURCES = ("paper_2106_11143_amd/csrc/pair_kernels.hpp", "paper_2106_11143_amd/csrc/pair_sym.hpp",
+                  "paper_2106_11143_amd/csrc/wave_reduce.hpp", "paper_2106_11143_amd/csrc/rsqrt.hpp",
                   "paper_2106_11143_amd/csrc/pair.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_fp64_cloud100k_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_stage_fp64_cloud100k_traffic.json")
+STAGE_KERNELS = {
+    0: "cb::k_pair<FP64> (all-pairs force, j-split partials)",
+    1: "force stage cb::k_sym_plan + cb::k_pair_sym<FP64> + cb::k_sym_finish<FP64> (each unordered pair "
+       "evaluated once and applied to both ions; tile partials summed in fixed order)",
+}
 
 
 def kernel_hash() -> str:
@@ -44,8 +50,9 @@ def kernel_hash() -> str:
 
 
 def measured_traffic():
-    """HBM bytes per launch of the FP64 all-pairs kernel from the committed
-    rocprofv3 counter summary, or None if absent or taken on other code."""
+    """HBM bytes per FP64 force evaluation (all kernels of the stage) from the
+    committed rocprofv3 counter summary, or None if absent or taken on other
+    code."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -169,7 +176,7 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "cb::k_pair<FP64> (all-pairs force, j-split partials)",
+            "kernel": STAGE_KERNELS.get(cfg["algo"], "?"),
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",

@@ -209,7 +209,8 @@ cb_status cb_load_tuning(const char* cache_path);
  * out[0] = algorithm (0: every ordered pair evaluated, j-split partial sums;
  *          1: each unordered pair evaluated once and applied to both ions by
  *          Newton's third law, forces only, n <= 2^18),
- * out[1] = i-particles per lane, out[2] = workgroup size (algorithm 0),
+ * out[1] = i-particles per lane, out[2] = workgroup size (algorithm 0) or
+ *          j's per reduction group (algorithm 1),
  * out[3] = j-splits (algorithm 0) or j-segment length (algorithm 1),
  * out[4] = 1 if it came from tuning or cb_set_config. */
 cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]);
@@ -217,9 +218,10 @@ cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]);
 /* Forces the launch configuration for (op, n power-of-two bucket, prec), with
  * the fields of cb_get_config.  Algorithm 0: p in {1,2,4} ({1,2} for the HVP
  * and adjoint), wg in {64,128,256}, splits in 1..64.  Algorithm 1 (forces,
- * md_step, md_run): p in {2,3}, splits = segment length in {512,1024,2048},
- * wg ignored.  algo = p = wg = splits = 0 removes a forced or tuned entry
- * (back to the built-in heuristic).  CB_EINVAL if unsupported. */
+ * md_step, md_run; n <= 2^18): p in {2,3,4,5,6,8}, wg = j's per reduction
+ * group = 4, splits = segment length in {256,512,1024,2048}.
+ * algo = p = wg = splits = 0 removes a forced or tuned entry (back to the
+ * built-in heuristic).  CB_EINVAL if unsupported. */
 cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t algo, int32_t p, int32_t wg, int32_t splits);
 
 #ifdef __cplusplus

@@ -126,15 +126,15 @@ cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_pat
     const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
     if (rc == CB_OK && force_op && n <= kSymMaxN) {
         size_t need = 0;
-        for (int p : {2, 3})
-            for (int jl : {512, 1024, 2048}) need = std::max(need, sym_ws_bytes(n, p, jl));
+        for (int p : kSymP)
+            for (int jl : kSymJL) need = std::max(need, sym_ws_bytes(n, p, jl));
         DevBuf sws, F;
         if (hipMalloc(&sws.p, need) != hipSuccess || hipMalloc(&F.p, sizeof(double) * 3 * (size_t)n) != hipSuccess)
             rc = fail(CB_EHIP, "cb_autotune: allocation failed");
-        for (int p : {2, 3})
-            for (int jl : {512, 1024, 2048}) {
+        for (int p : kSymP)
+            for (int jl : kSymJL) {
                 if (rc) break;
-                LaunchCfg c{p, 64, jl, 1, ALGO_SYM};
+                LaunchCfg c{p, kSymGroup, jl, 1, ALGO_SYM};
                 auto launch = [&]() {
                     return launch_pair_sym(prec, c, (int)n, x, y, z, q, 0.0, sws.p, static_cast<double*>(F.p), st);
                 };

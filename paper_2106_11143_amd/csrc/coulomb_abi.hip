@@ -82,11 +82,13 @@ LaunchCfg default_cfg(int op, int64_t n, int prec) {
     (void)prec;
     const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
     if (force_op && n >= 16384 && n <= kSymMaxN) {
-        // Newton's third law: each pair once (see pair_sym.hpp)
+        // Newton's third law: each pair once (see pair_sym.hpp).  Eight ions
+        // per lane amortise the per-j wave reduction best; below 32768 ions
+        // smaller tiles keep about 4096 tiles in flight.
         c.algo = ALGO_SYM;
-        c.p = 2;
-        c.wg = 64;
-        c.splits = 1024;
+        c.wg = kSymGroup;
+        c.p = n >= 32768 ? 8 : 4;
+        c.splits = n >= 32768 ? 512 : 256;
         return c;
     }
     c.wg = 64;
@@ -118,8 +120,7 @@ void drop_cfg(int op, int64_t n, int prec) {
 
 bool valid_cfg(int op, const LaunchCfg& c) {
     const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
-    if (c.algo == ALGO_SYM)
-        return force_op && (c.p == 2 || c.p == 3) && (c.splits == 512 || c.splits == 1024 || c.splits == 2048);
+    if (c.algo == ALGO_SYM) return force_op && sym_cfg_ok(c.p, c.wg, c.splits);
     if (c.algo != ALGO_DIRECT) return false;
     const bool p_ok = (op == CB_OP_HVP || op == CB_OP_ADJOINT) ? (c.p == 1 || c.p == 2)
                                                                  : (c.p == 1 || c.p == 2 || c.p == 4);
@@ -151,10 +152,9 @@ WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec) {
         const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
         if (force_op && n <= kSymMaxN) {
             // room for the symmetric path: finished forces [3][n] then its tiles and partials
-            const int jls[] = {512, 1024, 2048};
             size_t sym = 0;
-            for (int p : {2, 3})
-                for (int jl : jls) sym = std::max(sym, sym_ws_bytes(n, p, jl));
+            for (int p : kSymP)
+                for (int jl : kSymJL) sym = std::max(sym, sym_ws_bytes(n, p, jl));
             part = std::max(part, al(sizeof(double) * 3 * N) + sym);
         }
         off += al(part);
@@ -228,7 +228,7 @@ cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t algo, int32
         drop_cfg(op, n, prec);
         return ok();
     }
-    LaunchCfg c{p, algo == ALGO_SYM ? 64 : wg, splits, 1, algo};
+    LaunchCfg c{p, wg, splits, 1, algo};
     if (!valid_cfg(op, c) || (algo == ALGO_SYM && n > kSymMaxN))
         return fail(CB_EINVAL, "cb_set_config: unsupported configuration algo=%d p=%d wg=%d splits=%d", algo, p, wg,
                     splits);

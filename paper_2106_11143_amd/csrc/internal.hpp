@@ -17,9 +17,22 @@ constexpr int64_t kSymMaxN = int64_t(1) << 18;  // largest n for the symmetric k
 
 enum : int { ALGO_DIRECT = 0, ALGO_SYM = 1 };
 
+// Symmetric path launch parameters: i-particles per lane, j's per reaction
+// group, segment lengths (powers of two).
+constexpr int kSymP[] = {2, 3, 4, 5, 6, 8};
+constexpr int kSymGroup = 4;
+constexpr int kSymJL[] = {256, 512, 1024, 2048};
+
+constexpr bool sym_cfg_ok(int p, int g, int jl) {
+    bool pk = false, jk = false;
+    for (int v : kSymP) pk = pk || v == p;
+    for (int v : kSymJL) jk = jk || v == jl;
+    return pk && jk && g == kSymGroup;
+}
+
 struct LaunchCfg {
     int p;       // i-particles per lane
-    int wg;      // threads per workgroup (direct)
+    int wg;      // direct: threads per workgroup; symmetric: j's per reaction group (4)
     int splits;  // direct: requested j-splits; symmetric: segment length JL
     int tuned;   // 1 if set by tuning or cb_set_config
     int algo;    // ALGO_DIRECT or ALGO_SYM

@@ -81,11 +81,26 @@ static void go_sym(int n, int JL, int64_t T, const double* x, const double* y, c
     k_pair_sym<PREC, P><<<(unsigned)T, 64, 0, st>>>(n, x, y, z, q, eps2, JL, tiles, Pi, R);
 }
 
+template <int PREC>
+static bool go_sym_p(int P, int n, int JL, int64_t T, const double* x, const double* y, const double* z,
+                     const double* q, double eps2, const int2* tiles, double* Pi, double* R, hipStream_t st) {
+    switch (P) {
+        case 2: go_sym<PREC, 2>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
+        case 3: go_sym<PREC, 3>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
+        case 4: go_sym<PREC, 4>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
+        case 5: go_sym<PREC, 5>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
+        case 6: go_sym<PREC, 6>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
+        case 8: go_sym<PREC, 8>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
+        default: return false;
+    }
+}
+
 cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, const double* y, const double* z,
                           const double* q, double eps2, void* ws, double* F, hipStream_t st) {
     const int P = c.p, JL = c.splits, IB = 64 * P;
-    if ((P != 2 && P != 3) || JL < 8 || JL % 8) return fail(CB_EINVAL, "launch_pair_sym: bad configuration");
+    if (!sym_cfg_ok(P, c.wg, JL)) return fail(CB_EINVAL, "launch_pair_sym: bad configuration");
     const int nI = (n + IB - 1) / IB;
+    if (nI > kPlanMaxRows) return fail(CB_EINVAL, "launch_pair_sym: n = %d is too large for the symmetric kernel", n);
     const int64_t T = sym_tiles(n, IB, JL);
     char* base = static_cast<char*>(ws);
     int* rowstart = reinterpret_cast<int*>(base);
@@ -95,32 +110,29 @@ cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, 
     double* Pi = reinterpret_cast<double*>(base);
     base += al256(sizeof(double) * 3 * IB * (T + 1));
     double* R = reinterpret_cast<double*>(base);
-    k_sym_rows<<<1, 1, 0, st>>>(n, IB, JL, nI, rowstart);
-    k_sym_fill<<<(nI + 255) / 256, 256, 0, st>>>(n, IB, JL, nI, rowstart, tiles);
-    cb_status rc = check_launch("k_sym_rows/fill");
+    k_sym_plan<<<1, kPlanThreads, 0, st>>>(n, IB, JL, nI, rowstart, tiles);
+    cb_status rc = check_launch("k_sym_plan");
     if (rc) return rc;
     if (T > 0) {
-        bool okk = true;
-        switch (prec * 16 + P) {
-            case PREC_FP64 * 16 + 2: go_sym<PREC_FP64, 2>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_FP64 * 16 + 3: go_sym<PREC_FP64, 3>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_MIXED * 16 + 2: go_sym<PREC_MIXED, 2>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_MIXED * 16 + 3: go_sym<PREC_MIXED, 3>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_IEEE * 16 + 2: go_sym<PREC_IEEE, 2>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_IEEE * 16 + 3: go_sym<PREC_IEEE, 3>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_FP32 * 16 + 2: go_sym<PREC_FP32, 2>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_FP32 * 16 + 3: go_sym<PREC_FP32, 3>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            default: okk = false;
+        bool okk = false;
+        switch (prec) {
+            case PREC_FP64: okk = go_sym_p<PREC_FP64>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_MIXED: okk = go_sym_p<PREC_MIXED>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_IEEE: okk = go_sym_p<PREC_IEEE>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_FP32: okk = go_sym_p<PREC_FP32>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            default: break;
         }
-        if (!okk) return fail(CB_EINVAL, "launch_pair_sym: unsupported precision %d", prec);
+        if (!okk) return fail(CB_EINVAL, "launch_pair_sym: unsupported precision %d / p %d", prec, P);
         if ((rc = check_launch("k_pair_sym"))) return rc;
     }
-    const unsigned nb = (unsigned)((n + 255) / 256);
+    const unsigned nb = (unsigned)((n + 63) / 64);
+    int lgJL = 0;
+    while ((1 << lgJL) < JL) ++lgJL;
     switch (prec) {
-        case PREC_FP64: k_sym_finish<PREC_FP64><<<nb, 256, 0, st>>>(n, IB, JL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
-        case PREC_MIXED: k_sym_finish<PREC_MIXED><<<nb, 256, 0, st>>>(n, IB, JL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
-        case PREC_IEEE: k_sym_finish<PREC_IEEE><<<nb, 256, 0, st>>>(n, IB, JL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
-        default: k_sym_finish<PREC_FP32><<<nb, 256, 0, st>>>(n, IB, JL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
+        case PREC_FP64: k_sym_finish<PREC_FP64><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
+        case PREC_MIXED: k_sym_finish<PREC_MIXED><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
+        case PREC_IEEE: k_sym_finish<PREC_IEEE><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
+        default: k_sym_finish<PREC_FP32><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
     }
     return check_launch("k_sym_finish");
 }

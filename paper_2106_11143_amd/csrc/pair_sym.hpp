@@ -8,10 +8,10 @@
 // one wave.  Per j (uniform across the wave, fetched by scalar loads into
 // SGPRs) each lane evaluates its P pairs once and
 //   - adds q_i q_j d y^3 to its own i accumulators (force on i, up to k_C);
-//   - adds q_i d y^3 over its P ions into a per-j value; after 8 j's the 24
-//     per-j values (8 j x 3 components) are summed over the wave by a
-//     reduce-scatter (wave_reduce.hpp), giving the reaction on those 8 j
-//     (up to -k_C q_j), which one lane per value stores.
+//   - adds q_i d y^3 over its P ions into a per-j value; after a group of
+//     4 j's the 12 per-j values are summed over the wave by a reduce-scatter
+//     (wave_reduce.hpp), giving the reaction on those j (up to -k_C q_j),
+//     which one lane per value stores.
 // The tile writes its i sums to Pi[tile][3][IB] and its reactions to
 // R[tile][3][JL]; nothing is accumulated across workgroups, so results are
 // deterministic.  The diagonal i-block (pairs inside one block) is evaluated
@@ -29,27 +29,52 @@ namespace cb {
 
 // Segments of row I: ceil((n - (I+1) IB) / JL), or 0.
 __host__ __device__ __forceinline__ int sym_nseg(int n, int IB, int JL, int I) {
-    const long long a = (long long)n - (long long)(I + 1) * IB;
-    return a > 0 ? (int)((a + JL - 1) / JL) : 0;
+    const int a = n - (I + 1) * IB;  // n <= 2^18: no overflow
+    return a > 0 ? (a + JL - 1) / JL : 0;
 }
 
-// rowstart[I] = first tile of row I (exclusive prefix sum), rowstart[nI] = tiles.
-__global__ void k_sym_rows(int n, int IB, int JL, int nI, int* __restrict__ rowstart) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        int acc = 0;
-        for (int I = 0; I < nI; ++I) {
-            rowstart[I] = acc;
-            acc += sym_nseg(n, IB, JL, I);
-        }
-        rowstart[nI] = acc;
+// Tile table, one workgroup.  rowstart[I] = first tile of row I (exclusive
+// prefix sum over rows of their segment counts), rowstart[nI] = tiles T;
+// tiles[t] = (row, segment) of tile t.  Each thread sums the segments of a
+// contiguous share of rows, the shares are scanned in LDS (Hillis-Steele),
+// the row starts are kept in LDS, and each wave then writes whole rows of
+// the table, its lanes taking consecutive segments.
+constexpr int kPlanThreads = 1024;
+constexpr int kPlanMaxRows = 2048;  // n <= 2^18 ions in blocks of >= 128
+
+__global__ void __launch_bounds__(kPlanThreads) k_sym_plan(int n, int IB, int JL, int nI, int* __restrict__ rowstart,
+                                                           int2* __restrict__ tiles) {
+    __shared__ int sh[kPlanThreads];
+    __shared__ int rs[kPlanMaxRows + 1];
+    const int t = threadIdx.x;
+    const int per = (nI + kPlanThreads - 1) / kPlanThreads;
+    const int r0 = min(nI, t * per), r1 = min(nI, r0 + per);
+    int mine = 0;
+    for (int I = r0; I < r1; ++I) mine += sym_nseg(n, IB, JL, I);
+    sh[t] = mine;
+    __syncthreads();
+    for (int w = 1; w < kPlanThreads; w <<= 1) {
+        const int add = t >= w ? sh[t - w] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
     }
-}
-
-__global__ void k_sym_fill(int n, int IB, int JL, int nI, const int* __restrict__ rowstart, int2* __restrict__ tiles) {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= nI) return;
-    const int s0 = rowstart[I], ns = sym_nseg(n, IB, JL, I);
-    for (int s = 0; s < ns; ++s) tiles[s0 + s] = make_int2(I, s);
+    int acc = sh[t] - mine;  // exclusive prefix of this thread's rows
+    for (int I = r0; I < r1; ++I) {
+        rs[I] = acc;
+        rowstart[I] = acc;
+        acc += sym_nseg(n, IB, JL, I);
+    }
+    if (t == kPlanThreads - 1) {
+        rs[nI] = sh[t];
+        rowstart[nI] = sh[t];
+    }
+    __syncthreads();
+    const int lane = t & 63;
+    for (int I = t >> 6; I < nI; I += kPlanThreads / 64) {
+        const int s0 = rs[I], ns = rs[I + 1] - s0;
+        for (int sg = lane; sg < ns; sg += 64) tiles[s0 + sg] = make_int2(I, sg);
+    }
 }
 
 // s = q r^{-3} refined as in the direct kernel (the series on r^-3).
@@ -60,26 +85,50 @@ __device__ __forceinline__ double sym_s(double r2, double q, const SeriesK& K) {
     return s;
 }
 
-// One group of 8 j's (jg .. jg+7; only the first cnt are live when TAIL):
-// i sums into ia, the 8 reactions reduced over the wave and stored.
-template <int PREC, int P, bool TAIL>
-__device__ __forceinline__ void sym_group(int jg, int cnt, int j0, int JL, const double* __restrict__ x,
-                                          const double* __restrict__ y, const double* __restrict__ z,
-                                          const double* __restrict__ q, double eps2, const double (&xi)[P],
-                                          const double (&yi)[P], const double (&zi)[P], const double (&qi)[P],
-                                          double (&ia)[P][3], const SeriesK& K, double* __restrict__ Rt) {
-    double jv[24];
+// Coordinates and charges of a group of 4 j's.  The j index is uniform over
+// the wave, so these are scalar loads into SGPRs (32 of them; two groups fit
+// beside the rest of the kernel's scalar registers, eight j's do not).
+constexpr int kGroupJ = 4;
+
+struct JGroup {
+    double x[kGroupJ], y[kGroupJ], z[kGroupJ], q[kGroupJ];
+};
+
+// Loads j = jg + u for u < 4, with u clamped to last (last >= 0) so that a
+// partial group stays in bounds.
+template <bool CLAMP>
+__device__ __forceinline__ void load_group(JGroup& g, int jg, int last, const double* __restrict__ x,
+                                           const double* __restrict__ y, const double* __restrict__ z,
+                                           const double* __restrict__ q) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int j = TAIL ? jg + min(u, cnt - 1) : jg + u;
-        const double xj = x[j], yj = y[j], zj = z[j], qj = q[j];
+    for (int u = 0; u < kGroupJ; ++u) {
+        const int j = CLAMP ? jg + min(u, last) : jg + u;
+        g.x[u] = x[j];
+        g.y[u] = y[j];
+        g.z[u] = z[j];
+        g.q[u] = q[j];
+    }
+}
+
+// The pairs of one group (only its first `live` j's when TAIL): i sums into
+// ia; the reactions on the 4 j's summed over the wave and stored by one lane
+// per value to Rt[c][jg - j0 + u].
+template <int PREC, int P, bool TAIL>
+__device__ __forceinline__ void sym_group(const JGroup& jd, int jg, int live, int j0, int JL, double eps2,
+                                          const double (&xi)[P], const double (&yi)[P], const double (&zi)[P],
+                                          const double (&qi)[P], double (&ia)[P][3], const SeriesK& K,
+                                          double* __restrict__ Rt) {
+    double jv[3 * kGroupJ];  // this lane's share of each reaction: sum over its P ions of q_i d r^-3
+#pragma unroll
+    for (int u = 0; u < kGroupJ; ++u) {
+        const double xj = jd.x[u], yj = jd.y[u], zj = jd.z[u], qj = jd.q[u];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const double dx = xi[p] - xj, dy = yi[p] - yj, dz = zi[p] - zj;
             const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
             double s = sym_s<PREC>(r2, qi[p], K);  // q_i r^-3
-            if (TAIL && u >= cnt) s = 0.0;
+            if (TAIL && u >= live) s = 0.0;
             const double sq = s * qj;  // q_i q_j r^-3
             ia[p][0] = __builtin_fma(dx, sq, ia[p][0]);
             ia[p][1] = __builtin_fma(dy, sq, ia[p][1]);
@@ -88,22 +137,37 @@ __device__ __forceinline__ void sym_group(int jg, int cnt, int j0, int JL, const
             a1 = __builtin_fma(dy, s, a1);
             a2 = __builtin_fma(dz, s, a2);
         }
-        jv[u * 3 + 0] = a0;
-        jv[u * 3 + 1] = a1;
-        jv[u * 3 + 2] = a2;
+        jv[3 * u + 0] = a0;
+        jv[3 * u + 1] = a1;
+        jv[3 * u + 2] = a2;
     }
+    // The empty asm ties the i sums to this point: without it the compiler
+    // defers their updates past the reduction and the conditional store,
+    // keeping every pair's dx, dy, dz and s alive through them (about 100
+    // more VGPRs, half the occupancy).
+#pragma unroll
+    for (int p = 0; p < P; ++p) asm volatile("" : "+v"(ia[p][0]), "+v"(ia[p][1]), "+v"(ia[p][2]));
     double o[3];
-    reduce_scatter24(jv, o);
+    reduce_scatter12(jv, o);
     const int lane = threadIdx.x;
-    const int g = lane >> 3, c = lane & 7;
-    if ((!TAIL || g < cnt) && c < 3) Rt[(size_t)c * JL + (jg - j0) + g] = (c == 0) ? o[0] : ((c == 1) ? o[1] : o[2]);
+    const int g = lane >> 4, c = lane & 15;
+    if ((!TAIL || g < live) && c < 3) Rt[(size_t)c * JL + (jg - j0) + g] = (c == 0) ? o[0] : ((c == 1) ? o[1] : o[2]);
+}
+
+// Waves per SIMD the register budget is sized for (no spills at these; the
+// IEEE square root and division need more registers).
+template <int PREC, int P>
+constexpr int sym_waves() {
+    return PREC == PREC_IEEE ? (P <= 4 ? 4 : (P <= 6 ? 3 : 2)) : (P <= 5 ? 4 : 3);
 }
 
 template <int PREC, int P>
-__global__ void __launch_bounds__(64, (P <= 2 ? 3 : 2)) k_pair_sym(int n, const double* __restrict__ x, const double* __restrict__ y,
-                                                 const double* __restrict__ z, const double* __restrict__ q,
-                                                 double eps2, int JL, const int2* __restrict__ tiles,
-                                                 double* __restrict__ Pi, double* __restrict__ R) {
+__global__ void __launch_bounds__(64, (sym_waves<PREC, P>())) k_pair_sym(int n, const double* __restrict__ x,
+                                                                 const double* __restrict__ y,
+                                                                 const double* __restrict__ z,
+                                                                 const double* __restrict__ q, double eps2, int JL,
+                                                                 const int2* __restrict__ tiles,
+                                                                 double* __restrict__ Pi, double* __restrict__ R) {
     constexpr int IB = 64 * P;
     const int t = blockIdx.x;
     const int2 tl = tiles[t];
@@ -122,11 +186,29 @@ __global__ void __launch_bounds__(64, (P <= 2 ? 3 : 2)) k_pair_sym(int n, const 
     const SeriesK K;
     const int j0 = (I + 1) * IB + sg * JL;
     const int j1 = min(n, j0 + JL);
+    const int jfull = j0 + (j1 - j0) / kGroupJ * kGroupJ;
     double* Rt = R + (size_t)t * 3 * JL;
+    // Full groups, software-pipelined: the next group's j data is requested
+    // before the current group is evaluated, so its load latency overlaps the
+    // arithmetic (the last group re-requests itself).
     int jg = j0;
-    for (; jg + 8 <= j1; jg += 8)
-        sym_group<PREC, P, false>(jg, 8, j0, JL, x, y, z, q, eps2, xi, yi, zi, qi, ia, K, Rt);
-    if (jg < j1) sym_group<PREC, P, true>(jg, j1 - jg, j0, JL, x, y, z, q, eps2, xi, yi, zi, qi, ia, K, Rt);
+    if (jg < jfull) {
+        JGroup cur;
+        load_group<false>(cur, jg, 0, x, y, z, q);
+        for (; jg < jfull; jg += kGroupJ) {
+            JGroup nxt;
+            const int jn = jg + kGroupJ;
+            load_group<false>(nxt, jn < jfull ? jn : jg, 0, x, y, z, q);
+            __builtin_amdgcn_sched_barrier(0);  // keep the requests ahead of the arithmetic
+            sym_group<PREC, P, false>(cur, jg, kGroupJ, j0, JL, eps2, xi, yi, zi, qi, ia, K, Rt);
+            cur = nxt;
+        }
+    }
+    if (jg < j1) {  // the last, partial group: j's from j1 on are masked
+        JGroup tail;
+        load_group<true>(tail, jg, j1 - jg - 1, x, y, z, q);
+        sym_group<PREC, P, true>(tail, jg, j1 - jg, j0, JL, eps2, xi, yi, zi, qi, ia, K, Rt);
+    }
     double* Pt = Pi + (size_t)t * 3 * IB;
 #pragma unroll
     for (int p = 0; p < P; ++p)
@@ -136,25 +218,43 @@ __global__ void __launch_bounds__(64, (P <= 2 ? 3 : 2)) k_pair_sym(int n, const 
 
 // Per ion k: direct pairs inside its own i-block, plus its i sums over the
 // segments of its row, minus q_k times its reactions from the rows above;
-// writes the finished force F = k_C (...) to F[3][n].  A wave's 64 ions lie
-// in one i-block (IB is a multiple of 64), so the block's j loop is uniform.
+// writes the finished force F = k_C (...) to F[3][n].  One workgroup = 64
+// consecutive ions (one i-block holds them all, IB being a multiple of 64)
+// and kFinishParts waves; wave w takes the w-th contiguous share of each of
+// the three sums, and the shares are added in wave order through LDS, so the
+// result does not depend on timing.  All j and row loops are uniform.
+constexpr int kFinishParts = 4;
+
+__host__ __device__ __forceinline__ void share(int a, int b, int w, int& lo, int& hi) {
+    const int len = (b - a + kFinishParts - 1) / kFinishParts;
+    lo = min(b, a + w * len);
+    hi = min(b, lo + len);
+}
+
 template <int PREC>
-__global__ void __launch_bounds__(256) k_sym_finish(int n, int IB, int JL, const double* __restrict__ x,
-                                                    const double* __restrict__ y, const double* __restrict__ z,
-                                                    const double* __restrict__ q, double eps2,
-                                                    const int* __restrict__ rowstart,
-                                                    const double* __restrict__ Pi, const double* __restrict__ R,
-                                                    double* __restrict__ F) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int wbase = __builtin_amdgcn_readfirstlane(blockIdx.x * blockDim.x + (threadIdx.x & ~63));
-    if (wbase >= n) return;
+__global__ void __launch_bounds__(64 * kFinishParts) k_sym_finish(int n, int IB, int JL, int lgJL,
+                                                                  const double* __restrict__ x,
+                                                                  const double* __restrict__ y,
+                                                                  const double* __restrict__ z,
+                                                                  const double* __restrict__ q, double eps2,
+                                                                  const int* __restrict__ rowstart,
+                                                                  const double* __restrict__ Pi,
+                                                                  const double* __restrict__ R,
+                                                                  double* __restrict__ F) {
+    __shared__ double red[kFinishParts][9][64];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int k0 = blockIdx.x * 64;
+    const int k = k0 + lane;
     const int kc = min(k, n - 1);
-    const int Ik = wbase / IB;
+    const int Ik = k0 / IB;
     const int b0 = Ik * IB, b1 = min(n, b0 + IB);
     const double xk = x[kc], yk = y[kc], zk = z[kc];
     const SeriesK K;
+    int lo, hi;
     double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-    for (int j = b0; j < b1; ++j) {
+    share(b0, b1, w, lo, hi);
+    for (int j = lo; j < hi; ++j) {
         const double dx = xk - x[j], dy = yk - y[j], dz = zk - z[j];
         const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
         double s = sym_s<PREC>(r2, q[j], K);
@@ -163,29 +263,44 @@ __global__ void __launch_bounds__(256) k_sym_finish(int n, int IB, int JL, const
         d1 = __builtin_fma(dy, s, d1);
         d2 = __builtin_fma(dz, s, d2);
     }
-    if (k >= n) return;
-    const int off = k - b0;
+    const int off = kc - b0;
     double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-    const int r0 = rowstart[Ik], r1 = rowstart[Ik + 1];
-    for (int t = r0; t < r1; ++t) {
+    share(rowstart[Ik], rowstart[Ik + 1], w, lo, hi);
+#pragma unroll 4
+    for (int t = lo; t < hi; ++t) {
         const double* Pt = Pi + (size_t)t * 3 * IB + off;
         p0 += Pt[0];
         p1 += Pt[IB];
         p2 += Pt[2 * IB];
     }
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-    for (int I = 0; I < Ik; ++I) {
-        const int rel = k - (I + 1) * IB;
-        const int sI = rel / JL;
-        const double* Rt = R + (size_t)(rowstart[I] + sI) * 3 * JL + (rel - sI * JL);
+    share(0, Ik, w, lo, hi);
+#pragma unroll 4
+    for (int I = lo; I < hi; ++I) {
+        const int rel = kc - (I + 1) * IB;
+        const int sI = rel >> lgJL;
+        const double* Rt = R + (size_t)(rowstart[I] + sI) * 3 * JL + (rel - (sI << lgJL));
         e0 += Rt[0];
         e1 += Rt[JL];
         e2 += Rt[2 * JL];
     }
+    const double v[9] = {d0, d1, d2, p0, p1, p2, e0, e1, e2};
+#pragma unroll
+    for (int c = 0; c < 9; ++c) red[w][c][lane] = v[c];
+    __syncthreads();
+    if (w != 0 || k >= n) return;
+    double tot[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        double a = red[0][c][lane];
+#pragma unroll
+        for (int u = 1; u < kFinishParts; ++u) a += red[u][c][lane];
+        tot[c] = a;
+    }
     const double qk = q[k];
-    F[k] = kCoulomb * (p0 + qk * (d0 - e0));
-    F[(size_t)n + k] = kCoulomb * (p1 + qk * (d1 - e1));
-    F[2 * (size_t)n + k] = kCoulomb * (p2 + qk * (d2 - e2));
+    F[k] = kCoulomb * (tot[3] + qk * (tot[0] - tot[6]));
+    F[(size_t)n + k] = kCoulomb * (tot[4] + qk * (tot[1] - tot[7]));
+    F[2 * (size_t)n + k] = kCoulomb * (tot[5] + qk * (tot[2] - tot[8]));
 }
 
 }  // namespace cb

@@ -1,17 +1,4 @@
-// Wave-wide reduce-scatter of 24 doubles per lane on gfx950 (wave64).
-//
-// Input: every lane holds v[jj*3 + c] for jj < 8, c < 3.  Output: every lane
-// of the 8-lane group g = lane >> 3 holds in out[c] the sum over all 64 lanes
-// of v[g*3 + c].  Six halving steps, each exchanging with a partner lane and
-// keeping half of the remaining values:
-//   lanes 0-31 / 32-63   v_permlane32_swap (keep indices 0-11 / 12-23)
-//   rows 0,2 / rows 1,3  v_permlane16_swap (keep 0-5 / 6-11 of those)
-//   lane bit 3           DPP row_ror:8      (keep 0-2 / 3-5 of those)
-// then an all-reduce of the 3 survivors over the 8 lanes of the group (DPP
-// row_half_mirror, quad_perm [2,3,0,1], quad_perm [1,0,3,2]).  The swaps move
-// 32-bit halves, so each 64-bit value takes two swaps.  All lanes of a group
-// end with the same sum up to the order of the last three additions; callers
-// store it from one lane.
+// Wave-wide reduce-scatter of 12 doubles per lane on gfx950 (wave64).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -53,19 +40,25 @@ constexpr int kDppRowHalfMirror = 0x141;
 constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
 constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
 
-__device__ __forceinline__ void reduce_scatter24(const double (&v)[24], double (&out)[3]) {
-    double u[12];
+// Input: every lane holds v[jj*3 + c] for jj < 4, c < 3.  Output: every lane
+// of the 16-lane group g = lane >> 4 holds in out[c] the sum over all 64
+// lanes of v[g*3 + c].  Two halving steps, each exchanging with a partner
+// lane and keeping half of the remaining values:
+//   lanes 0-31 / 32-63   v_permlane32_swap (keep indices 0-5 / 6-11)
+//   rows 0,2 / rows 1,3  v_permlane16_swap (keep 0-2 / 3-5 of those)
+// then an all-reduce of the 3 survivors over the 16 lanes of the group (DPP
+// row_ror:8, row_half_mirror, quad_perm [2,3,0,1], quad_perm [1,0,3,2]).
+// The swaps move 32-bit halves, so each 64-bit value takes two swaps.  All
+// lanes of a group end with the same sum up to the order of the last
+// additions; callers store it from one lane.
+__device__ __forceinline__ void reduce_scatter12(const double (&v)[12], double (&out)[3]) {
+    double u[6];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) u[k] = swap32_add(v[k], v[k + 12]);
-    double w[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) w[k] = swap16_add(u[k], u[k + 6]);
-    const bool upper8 = (__lane_id() & 8) != 0;
+    for (int k = 0; k < 6; ++k) u[k] = swap32_add(v[k], v[k + 6]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double own = upper8 ? w[c + 3] : w[c];
-        const double send = upper8 ? w[c] : w[c + 3];
-        double x = own + dpp_d<kDppRowRor8>(send);
+        double x = swap16_add(u[c], u[c + 3]);
+        x += dpp_d<kDppRowRor8>(x);
         x += dpp_d<kDppRowHalfMirror>(x);
         x += dpp_d<kDppQuadXor2>(x);
         x += dpp_d<kDppQuadXor1>(x);

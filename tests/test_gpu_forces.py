@@ -65,12 +65,12 @@ def test_forces_ragged_sizes_and_launch_shapes(api, oracle, p, wg, splits):
     api.clear_workspace_cache()
 
 
-SYM_SIZES = [1, 2, 3, 65, 127, 128, 129, 191, 192, 193, 385, 1000, 2049, 4001]
-SYM_CONFIGS = [(2, 512), (3, 1024), (2, 2048), (3, 512)]
+SYM_SIZES = [1, 2, 3, 65, 127, 128, 129, 191, 192, 193, 320, 385, 511, 512, 513, 1000, 1537, 2049, 4001]
+SYM_CONFIGS = [(2, 4, 256), (3, 4, 1024), (4, 4, 512), (5, 4, 2048), (6, 4, 256), (8, 4, 512)]
 
 
-@pytest.mark.parametrize("p,jl", SYM_CONFIGS)
-def test_forces_symmetric_kernel_ragged_sizes(api, oracle, p, jl):
+@pytest.mark.parametrize("p,group,jl", SYM_CONFIGS)
+def test_forces_symmetric_kernel_ragged_sizes(api, oracle, p, group, jl):
     """The Newton's-third-law kernel: i-blocks of 64p, j-segments of jl,
     ragged last blocks and segments, sizes with no off-diagonal tile."""
     from _gpu_util import per_ion_rel
@@ -81,7 +81,7 @@ def test_forces_symmetric_kernel_ragged_sizes(api, oracle, p, jl):
         eps2 = (1e-7) ** 2 if n % 3 == 0 else 0.0
         ref = np.stack(oracle.forces(d["x"], d["y"], d["z"], d["q"], eps2=eps2))
         for prec in ("fp64", "mixed"):
-            api.set_config("forces", n, prec, p=p, splits=jl, algo=1)
+            api.set_config("forces", n, prec, p=p, wg=group, splits=jl, algo=1)
             F = _forces(api, d, prec, eps2=eps2)
             api.reset_config("forces", n, prec)
             if n == 1:
