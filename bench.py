@@ -49,10 +49,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per FP64 force evaluation (all kernels of the stage) from the
-    committed rocprofv3 counter summary, or None if absent or taken on other
-    code."""
+def stage_counters():
+    """The committed rocprofv3 counter summary of one FP64 force evaluation
+    (all kernels of the stage): HBM bytes and executed FP64 FLOPs, or None if
+    absent or taken on other code."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -60,14 +60,14 @@ def measured_traffic():
         return None
     if t.get("kernel_hash") != kernel_hash():
         return None
-    return t.get("bytes_per_launch")
+    return t
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -76,6 +76,9 @@ def main():
     ap.add_argument("--workload", default="cloud100k",
                     choices=["cloud100k", "cloud1024", "rf32768", "kz512", "crystal8192"],
                     help="cloud100k is the headline; the others time the remaining workloads")
+    ap.add_argument("--direct", action="store_true",
+                    help="force the direct kernel (every ordered pair, j-split partials) instead of the "
+                         "default Newton's-third-law stage, at the direct kernel's default launch")
     args = ap.parse_args()
     if args.workload != "cloud100k":
         if args.gpus != 1:
@@ -85,7 +88,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+              "not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -102,6 +105,12 @@ def main():
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
     q, m = dev(d["q"]), dev(d["m"])
     trap, dt = d["trap"], d["dt"]
+    if args.direct:
+        waves = -(-n // 64)
+        splits = max(1, min(64, -(-65536 // waves), max(1, n // 64)))
+        for op in ("md_run", "forces"):
+            for prec in ("fp64", "mixed"):
+                api.set_config(op, n, prec, p=1, wg=64, splits=splits, algo=0)
 
     if args.calib_copy_mib:
         src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda").fill_(1)
@@ -148,7 +157,9 @@ def main():
     ms_per_step = ms_fp64 / args.steps
     value = pairs_step * args.steps / (ms_fp64 * 1e-3)
     achieved = FLOPS_PER_PAIR * pairs_step / (kt64 * 1e-3) / 1e12
-    traffic = measured_traffic()
+    counters = stage_counters()
+    traffic = counters.get("bytes_per_launch") if counters else None
+    executed = counters.get("executed_fp64_flops_per_launch") if counters else None
 
     # force error of the mixed path against the FP64 path, all ions
     x, y, z = (dev(d[k]) for k in ("x", "y", "z"))
@@ -185,6 +196,9 @@ def main():
             "traffic": traffic,
             "kernel_ms": kt64,
             "algorithmic_flops_per_launch": FLOPS_PER_PAIR * pairs_step,
+            "flop_convention": "algorithmic: 20 FLOP per ordered pair, N^2 ordered pairs per force evaluation; "
+                               "the Newton's-third-law stage evaluates each unordered pair once",
+            "executed_fp64_tflops": executed / (kt64 * 1e-3) / 1e12 if executed else None,
         },
         "mixed": {
             "pairs_per_s": pairs_step * args.steps / (ms_mixed * 1e-3),

@@ -21,7 +21,7 @@
  * component accumulated with Neumaier compensation so the oracle's own
  * summation error is about one rounding of the result.
  *
- * Readings of the paper taken here (each one also listed in the design doc):
+ * Readings of the paper taken here:
  *  - softening is added to r^2 (as the double loop does), not inside the norm;
  *  - the trap term acts on ion i (eq. (1) prints x_j, y_j);
  *  - the RF drive is cos(Omega t + phi) with Omega in rad/s, and its amplitude

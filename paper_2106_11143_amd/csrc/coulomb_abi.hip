@@ -84,10 +84,10 @@ LaunchCfg default_cfg(int op, int64_t n, int prec) {
     if (force_op && n >= 16384 && n <= kSymMaxN) {
         // Newton's third law: each pair once (see pair_sym.hpp).  Eight ions
         // per lane amortise the per-j wave reduction best; below 32768 ions
-        // smaller tiles keep about 4096 tiles in flight.
+        // smaller tiles keep enough of them in flight (measured on MI355X).
         c.algo = ALGO_SYM;
         c.wg = kSymGroup;
-        c.p = n >= 32768 ? 8 : 4;
+        c.p = n >= 32768 ? 8 : (n >= 24576 ? 6 : 4);
         c.splits = n >= 32768 ? 512 : 256;
         return c;
     }
