@@ -208,7 +208,8 @@ cb_status cb_load_tuning(const char* cache_path);
 /* The launch configuration the next call of `op` at (n, prec) will use:
  * out[0] = algorithm (0: every ordered pair evaluated, j-split partial sums;
  *          1: each unordered pair evaluated once and applied to both ions by
- *          Newton's third law, forces only, n <= 2^18),
+ *          Newton's third law, forces only, n <= 2^18, the reactions summed
+ *          over the wave by cross-lane permutes; 2: as 1, summed through LDS),
  * out[1] = i-particles per lane, out[2] = workgroup size (algorithm 0) or
  *          j's per reduction group (algorithm 1),
  * out[3] = j-splits (algorithm 0) or j-segment length (algorithm 1),
@@ -217,7 +218,7 @@ cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]);
 
 /* Forces the launch configuration for (op, n power-of-two bucket, prec), with
  * the fields of cb_get_config.  Algorithm 0: p in {1,2,4} ({1,2} for the HVP
- * and adjoint), wg in {64,128,256}, splits in 1..64.  Algorithm 1 (forces,
+ * and adjoint), wg in {64,128,256}, splits in 1..64.  Algorithms 1 and 2 (forces,
  * md_step, md_run; n <= 2^18): p in {2,3,4,5,6,8}, wg = j's per reduction
  * group = 4, splits = segment length in {256,512,1024,2048}.
  * algo = p = wg = splits = 0 removes a forced or tuned entry (back to the

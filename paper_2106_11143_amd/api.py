@@ -324,6 +324,7 @@ def set_config(op, n: int, prec="fp64", p: int = 1, wg: int = 256, splits: int =
     """Force a launch configuration (algo = p = wg = splits = 0: back to the
     default).  algo 1 = the Newton's-third-law force kernel (n <= 2^18), with
     p in {2, 3, 4, 5, 6, 8}, wg = j's per reduction group = 4 and splits =
-    segment length in {256, 512, 1024, 2048}."""
+    segment length in {256, 512, 1024, 2048}; algo 2 = the same kernel with
+    the per-j reactions summed through LDS."""
     _check(lib().cb_set_config(_op(op), int(n), _prec(prec), int(algo), int(p), int(wg), int(splits)),
            "cb_set_config")

@@ -131,10 +131,11 @@ cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_pat
         DevBuf sws, F;
         if (hipMalloc(&sws.p, need) != hipSuccess || hipMalloc(&F.p, sizeof(double) * 3 * (size_t)n) != hipSuccess)
             rc = fail(CB_EHIP, "cb_autotune: allocation failed");
+        for (int algo : {ALGO_SYM, ALGO_SYM_LDS})
         for (int p : kSymP)
             for (int jl : kSymJL) {
                 if (rc) break;
-                LaunchCfg c{p, kSymGroup, jl, 1, ALGO_SYM};
+                LaunchCfg c{p, kSymGroup, jl, 1, algo};
                 auto launch = [&]() {
                     return launch_pair_sym(prec, c, (int)n, x, y, z, q, 0.0, sws.p, static_cast<double*>(F.p), st);
                 };

@@ -120,7 +120,7 @@ void drop_cfg(int op, int64_t n, int prec) {
 
 bool valid_cfg(int op, const LaunchCfg& c) {
     const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
-    if (c.algo == ALGO_SYM) return force_op && sym_cfg_ok(c.p, c.wg, c.splits);
+    if (is_sym(c.algo)) return force_op && sym_cfg_ok(c.p, c.wg, c.splits);
     if (c.algo != ALGO_DIRECT) return false;
     const bool p_ok = (op == CB_OP_HVP || op == CB_OP_ADJOINT) ? (c.p == 1 || c.p == 2)
                                                                  : (c.p == 1 || c.p == 2 || c.p == 4);
@@ -229,7 +229,7 @@ cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t algo, int32
         return ok();
     }
     LaunchCfg c{p, wg, splits, 1, algo};
-    if (!valid_cfg(op, c) || (algo == ALGO_SYM && n > kSymMaxN))
+    if (!valid_cfg(op, c) || (is_sym(algo) && n > kSymMaxN))
         return fail(CB_EINVAL, "cb_set_config: unsupported configuration algo=%d p=%d wg=%d splits=%d", algo, p, wg,
                     splits);
     put_cfg(op, n, prec, c);

@@ -59,7 +59,7 @@ static cb_status force_stage(int op, int prec, int64_t n, const double* x, const
                              bool* prescaled) {
     const LaunchCfg cfg = get_cfg(op, n, prec);
     double* part = at(ws, L.part);
-    if (cfg.algo == ALGO_SYM && n <= kSymMaxN) {
+    if (is_sym(cfg.algo) && n <= kSymMaxN) {
         *S_out = 1;
         *prescaled = true;
         void* scratch = static_cast<char*>(ws) + L.part + al256(sizeof(double) * 3 * (size_t)n);

@@ -15,7 +15,11 @@ constexpr int kMaxBatchIons = 4096;  // ions per run in the batched kernel (LDS 
 constexpr int kEpiBlock = 256;       // threads per element-wise block
 constexpr int64_t kSymMaxN = int64_t(1) << 18;  // largest n for the symmetric kernel (partials grow as n^2)
 
-enum : int { ALGO_DIRECT = 0, ALGO_SYM = 1 };
+// ALGO_SYM and ALGO_SYM_LDS differ only in how the per-j reactions are summed
+// over the wave (cross-lane permutes and DPP, or LDS).
+enum : int { ALGO_DIRECT = 0, ALGO_SYM = 1, ALGO_SYM_LDS = 2 };
+
+constexpr bool is_sym(int algo) { return algo == ALGO_SYM || algo == ALGO_SYM_LDS; }
 
 // Symmetric path launch parameters: i-particles per lane, j's per reaction
 // group, segment lengths (powers of two).
@@ -35,7 +39,7 @@ struct LaunchCfg {
     int wg;      // direct: threads per workgroup; symmetric: j's per reaction group (4)
     int splits;  // direct: requested j-splits; symmetric: segment length JL
     int tuned;   // 1 if set by tuning or cb_set_config
-    int algo;    // ALGO_DIRECT or ALGO_SYM
+    int algo;    // ALGO_DIRECT, ALGO_SYM or ALGO_SYM_LDS
 };
 
 struct WsLayout {

@@ -75,30 +75,38 @@ size_t sym_ws_bytes(int64_t n, int p, int jl) {
            al256(sizeof(double) * 3 * IB * (T + 1)) + al256(sizeof(double) * 3 * (size_t)jl * (T + 1));
 }
 
-template <int PREC, int P>
+template <int PREC, int P, int RED>
 static void go_sym(int n, int JL, int64_t T, const double* x, const double* y, const double* z, const double* q,
                    double eps2, const int2* tiles, double* Pi, double* R, hipStream_t st) {
-    k_pair_sym<PREC, P><<<(unsigned)T, 64, 0, st>>>(n, x, y, z, q, eps2, JL, tiles, Pi, R);
+    k_pair_sym<PREC, P, RED><<<(unsigned)T, 64, 0, st>>>(n, x, y, z, q, eps2, JL, tiles, Pi, R);
 }
 
-template <int PREC>
+template <int PREC, int RED>
 static bool go_sym_p(int P, int n, int JL, int64_t T, const double* x, const double* y, const double* z,
                      const double* q, double eps2, const int2* tiles, double* Pi, double* R, hipStream_t st) {
     switch (P) {
-        case 2: go_sym<PREC, 2>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 3: go_sym<PREC, 3>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 4: go_sym<PREC, 4>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 5: go_sym<PREC, 5>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 6: go_sym<PREC, 6>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 8: go_sym<PREC, 8>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
+        case 2: go_sym<PREC, 2, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
+        case 3: go_sym<PREC, 3, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
+        case 4: go_sym<PREC, 4, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
+        case 5: go_sym<PREC, 5, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
+        case 6: go_sym<PREC, 6, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
+        case 8: go_sym<PREC, 8, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
         default: return false;
     }
+}
+
+template <int PREC>
+static bool go_sym_pr(int P, int red, int n, int JL, int64_t T, const double* x, const double* y, const double* z,
+                      const double* q, double eps2, const int2* tiles, double* Pi, double* R, hipStream_t st) {
+    return red ? go_sym_p<PREC, 1>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st)
+               : go_sym_p<PREC, 0>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st);
 }
 
 cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, const double* y, const double* z,
                           const double* q, double eps2, void* ws, double* F, hipStream_t st) {
     const int P = c.p, JL = c.splits, IB = 64 * P;
-    if (!sym_cfg_ok(P, c.wg, JL)) return fail(CB_EINVAL, "launch_pair_sym: bad configuration");
+    if (!is_sym(c.algo) || !sym_cfg_ok(P, c.wg, JL)) return fail(CB_EINVAL, "launch_pair_sym: bad configuration");
+    const int red = c.algo == ALGO_SYM_LDS ? 1 : 0;
     const int nI = (n + IB - 1) / IB;
     if (nI > kPlanMaxRows) return fail(CB_EINVAL, "launch_pair_sym: n = %d is too large for the symmetric kernel", n);
     const int64_t T = sym_tiles(n, IB, JL);
@@ -116,10 +124,10 @@ cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, 
     if (T > 0) {
         bool okk = false;
         switch (prec) {
-            case PREC_FP64: okk = go_sym_p<PREC_FP64>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_MIXED: okk = go_sym_p<PREC_MIXED>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_IEEE: okk = go_sym_p<PREC_IEEE>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_FP32: okk = go_sym_p<PREC_FP32>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_FP64: okk = go_sym_pr<PREC_FP64>(P, red, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_MIXED: okk = go_sym_pr<PREC_MIXED>(P, red, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_IEEE: okk = go_sym_pr<PREC_IEEE>(P, red, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_FP32: okk = go_sym_pr<PREC_FP32>(P, red, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
             default: break;
         }
         if (!okk) return fail(CB_EINVAL, "launch_pair_sym: unsupported precision %d / p %d", prec, P);

@@ -113,11 +113,13 @@ __device__ __forceinline__ void load_group(JGroup& g, int jg, int last, const do
 // The pairs of one group (only its first `live` j's when TAIL): i sums into
 // ia; the reactions on the 4 j's summed over the wave and stored by one lane
 // per value to Rt[c][jg - j0 + u].
-template <int PREC, int P, bool TAIL>
+// RED selects the wave reduction: 0 = cross-lane permutes and DPP, 1 = LDS
+// (red, one wave's buffer).
+template <int PREC, int P, int RED, bool TAIL>
 __device__ __forceinline__ void sym_group(const JGroup& jd, int jg, int live, int j0, int JL, double eps2,
                                           const double (&xi)[P], const double (&yi)[P], const double (&zi)[P],
                                           const double (&qi)[P], double (&ia)[P][3], const SeriesK& K,
-                                          double* __restrict__ Rt) {
+                                          double* __restrict__ Rt, double* __restrict__ red) {
     double jv[3 * kGroupJ];  // this lane's share of each reaction: sum over its P ions of q_i d r^-3
 #pragma unroll
     for (int u = 0; u < kGroupJ; ++u) {
@@ -147,11 +149,19 @@ __device__ __forceinline__ void sym_group(const JGroup& jd, int jg, int live, in
     // more VGPRs, half the occupancy).
 #pragma unroll
     for (int p = 0; p < P; ++p) asm volatile("" : "+v"(ia[p][0]), "+v"(ia[p][1]), "+v"(ia[p][2]));
-    double o[3];
-    reduce_scatter12(jv, o);
     const int lane = threadIdx.x;
-    const int g = lane >> 4, c = lane & 15;
-    if ((!TAIL || g < live) && c < 3) Rt[(size_t)c * JL + (jg - j0) + g] = (c == 0) ? o[0] : ((c == 1) ? o[1] : o[2]);
+    if constexpr (RED == 0) {
+        double o[3];
+        reduce_scatter12(jv, o);
+        const int g = lane >> 4, c = lane & 15;
+        if ((!TAIL || g < live) && c < 3)
+            Rt[(size_t)c * JL + (jg - j0) + g] = (c == 0) ? o[0] : ((c == 1) ? o[1] : o[2]);
+    } else {
+        const double o = lds_reduce12(jv, red);
+        const int v = lane >> 2;           // value 3 u + c of quad v (v < 12 stores)
+        const int u = (v * 11) >> 5, c = v - 3 * u;  // v / 3 and v % 3 for v < 16
+        if ((lane & 3) == 0 && v < 12 && (!TAIL || u < live)) Rt[(size_t)c * JL + (jg - j0) + u] = o;
+    }
 }
 
 // Waves per SIMD the register budget is sized for (no spills at these; the
@@ -161,7 +171,7 @@ constexpr int sym_waves() {
     return PREC == PREC_IEEE ? (P <= 4 ? 4 : (P <= 6 ? 3 : 2)) : (P <= 5 ? 4 : 3);
 }
 
-template <int PREC, int P>
+template <int PREC, int P, int RED>
 __global__ void __launch_bounds__(64, (sym_waves<PREC, P>())) k_pair_sym(int n, const double* __restrict__ x,
                                                                  const double* __restrict__ y,
                                                                  const double* __restrict__ z,
@@ -184,6 +194,8 @@ __global__ void __launch_bounds__(64, (sym_waves<PREC, P>())) k_pair_sym(int n, 
         ia[p][0] = ia[p][1] = ia[p][2] = 0.0;
     }
     const SeriesK K;
+    __shared__ __align__(16) double red_buf[RED == 1 ? 12 * kRedStride : 2];
+    double* red = red_buf;
     const int j0 = (I + 1) * IB + sg * JL;
     const int j1 = min(n, j0 + JL);
     const int jfull = j0 + (j1 - j0) / kGroupJ * kGroupJ;
@@ -200,14 +212,14 @@ __global__ void __launch_bounds__(64, (sym_waves<PREC, P>())) k_pair_sym(int n, 
             const int jn = jg + kGroupJ;
             load_group<false>(nxt, jn < jfull ? jn : jg, 0, x, y, z, q);
             __builtin_amdgcn_sched_barrier(0);  // keep the requests ahead of the arithmetic
-            sym_group<PREC, P, false>(cur, jg, kGroupJ, j0, JL, eps2, xi, yi, zi, qi, ia, K, Rt);
+            sym_group<PREC, P, RED, false>(cur, jg, kGroupJ, j0, JL, eps2, xi, yi, zi, qi, ia, K, Rt, red);
             cur = nxt;
         }
     }
     if (jg < j1) {  // the last, partial group: j's from j1 on are masked
         JGroup tail;
         load_group<true>(tail, jg, j1 - jg - 1, x, y, z, q);
-        sym_group<PREC, P, true>(tail, jg, j1 - jg, j0, JL, eps2, xi, yi, zi, qi, ia, K, Rt);
+        sym_group<PREC, P, RED, true>(tail, jg, j1 - jg, j0, JL, eps2, xi, yi, zi, qi, ia, K, Rt, red);
     }
     double* Pt = Pi + (size_t)t * 3 * IB;
 #pragma unroll

@@ -1,4 +1,6 @@
-// Wave-wide reduce-scatter of 12 doubles per lane on gfx950 (wave64).
+// Wave-wide reduce-scatter of 12 doubles per lane on gfx950 (wave64), two
+// ways: through cross-lane permutes and DPP (reduce_scatter12), or through LDS
+// (lds_reduce12).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -64,6 +66,36 @@ __device__ __forceinline__ void reduce_scatter12(const double (&v)[12], double (
         x += dpp_d<kDppQuadXor1>(x);
         out[c] = x;
     }
+}
+
+// The same sums through LDS, for a workgroup of one wave.  Every lane writes
+// its 12 values value-major into red (row v of kRedStride doubles holds value
+// v of lanes 0-63); then lane L reads value v = min(L / 4, 11) of lanes
+// 16 (L % 4) .. 16 (L % 4) + 15 as eight 16-byte loads, adds them in a fixed
+// tree, and the four lanes of each quad add their partial sums by DPP.  The
+// result, the sum over all 64 lanes of value v, is returned in every lane of
+// quad v (lanes 48-63 repeat value 11).  red holds 12 kRedStride doubles,
+// 16-byte aligned; the row stride puts the 12 rows in different banks.
+constexpr int kRedStride = 66;
+
+__device__ __forceinline__ double lds_reduce12(const double (&v)[12], double* __restrict__ red) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int k = 0; k < 12; ++k) red[k * kRedStride + lane] = v[k];
+    __syncthreads();
+    const int vi = min(lane >> 2, 11);
+    const double2* src = reinterpret_cast<const double2*>(red + vi * kRedStride + (lane & 3) * 16);
+    double2 a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = src[k];
+    double s4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s4[k] = (a[2 * k].x + a[2 * k].y) + (a[2 * k + 1].x + a[2 * k + 1].y);
+    double x = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    x += dpp_d<kDppQuadXor1>(x);
+    x += dpp_d<kDppQuadXor2>(x);
+    __syncthreads();  // every lane has read before the next group overwrites red
+    return x;
 }
 
 }  // namespace cb

@@ -155,11 +155,15 @@ def test_symmetric_config_validation(api):
     assert api.get_config("md_run", 50000, "fp64")["algo"] == 1  # the default at this size
     assert api.get_config("md_run", 1000, "fp64")["algo"] == 0
     assert api.get_config("energy", 50000, "fp64")["algo"] == 0  # the potential needs every ordered pair
-    for p in (2, 3, 4, 5, 6, 8):
-        for jl in (256, 512, 1024, 2048):
-            api.set_config("forces", 5000, "fp64", p=p, wg=4, splits=jl, algo=1)
-            assert api.get_config("forces", 5000, "fp64")["p"] == p
+    for algo in (1, 2):
+        for p in (2, 3, 4, 5, 6, 8):
+            for jl in (256, 512, 1024, 2048):
+                api.set_config("forces", 5000, "fp64", p=p, wg=4, splits=jl, algo=algo)
+                c = api.get_config("forces", 5000, "fp64")
+                assert (c["algo"], c["p"], c["splits"]) == (algo, p, jl)
     api.reset_config("forces", 5000, "fp64")
+    with pytest.raises(api.CoulombError):
+        api.set_config("forces", 5000, "fp64", p=4, wg=4, splits=512, algo=3)
     for bad in (dict(op="forces", n=1 << 19, p=2, wg=4, splits=1024),  # beyond the symmetric size limit
                 dict(op="hvp", n=5000, p=2, wg=4, splits=1024),  # forces only
                 dict(op="energy", n=5000, p=2, wg=4, splits=1024),
@@ -168,5 +172,7 @@ def test_symmetric_config_validation(api):
                 dict(op="forces", n=5000, p=1, wg=4, splits=1024),
                 dict(op="forces", n=5000, p=2, wg=4, splits=128),
                 dict(op="forces", n=5000, p=2, wg=4, splits=1000)):
+        with pytest.raises(api.CoulombError):
+            api.set_config(bad["op"], bad["n"], "fp64", p=bad["p"], wg=bad["wg"], splits=bad["splits"], algo=2)
         with pytest.raises(api.CoulombError):
             api.set_config(bad["op"], bad["n"], "fp64", p=bad["p"], wg=bad["wg"], splits=bad["splits"], algo=1)

@@ -66,13 +66,16 @@ def test_forces_ragged_sizes_and_launch_shapes(api, oracle, p, wg, splits):
 
 
 SYM_SIZES = [1, 2, 3, 65, 127, 128, 129, 191, 192, 193, 320, 385, 511, 512, 513, 1000, 1537, 2049, 4001]
-SYM_CONFIGS = [(2, 4, 256), (3, 4, 1024), (4, 4, 512), (5, 4, 2048), (6, 4, 256), (8, 4, 512)]
+SYM_CONFIGS = [(1, 2, 256), (1, 3, 1024), (1, 4, 512), (1, 5, 2048), (1, 6, 256), (1, 8, 512),
+               (2, 2, 512), (2, 4, 256), (2, 6, 1024), (2, 8, 512)]
 
 
-@pytest.mark.parametrize("p,group,jl", SYM_CONFIGS)
-def test_forces_symmetric_kernel_ragged_sizes(api, oracle, p, group, jl):
-    """The Newton's-third-law kernel: i-blocks of 64p, j-segments of jl,
+@pytest.mark.parametrize("algo,p,jl", SYM_CONFIGS)
+def test_forces_symmetric_kernel_ragged_sizes(api, oracle, algo, p, jl):
+    """The Newton's-third-law kernel (algo 1: reactions summed over the wave by
+    permutes and DPP; algo 2: through LDS): i-blocks of 64p, j-segments of jl,
     ragged last blocks and segments, sizes with no off-diagonal tile."""
+    group = 4
     from _gpu_util import per_ion_rel
     for n in SYM_SIZES:
         g = np.random.Generator(np.random.PCG64(2000 + n))
@@ -81,7 +84,7 @@ def test_forces_symmetric_kernel_ragged_sizes(api, oracle, p, group, jl):
         eps2 = (1e-7) ** 2 if n % 3 == 0 else 0.0
         ref = np.stack(oracle.forces(d["x"], d["y"], d["z"], d["q"], eps2=eps2))
         for prec in ("fp64", "mixed"):
-            api.set_config("forces", n, prec, p=p, wg=group, splits=jl, algo=1)
+            api.set_config("forces", n, prec, p=p, wg=group, splits=jl, algo=algo)
             F = _forces(api, d, prec, eps2=eps2)
             api.reset_config("forces", n, prec)
             if n == 1:
