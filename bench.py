@@ -37,7 +37,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_stage_fp64_cloud100k_traffi
 STAGE_KERNELS = {
     0: "cb::k_pair<FP64> (all-pairs force, j-split partials)",
     1: "force stage cb::k_sym_plan + cb::k_pair_sym<FP64> + cb::k_sym_finish<FP64> (each unordered pair "
-       "evaluated once and applied to both ions; tile partials summed in fixed order)",
+       "evaluated once and applied to both ions, reactions summed by cross-lane permutes; tile partials summed "
+       "in fixed order)",
+    2: "force stage cb::k_sym_plan + cb::k_pair_sym<FP64> + cb::k_sym_finish<FP64> (each unordered pair "
+       "evaluated once and applied to both ions, reactions summed through LDS; tile partials summed in fixed "
+       "order)",
 }
 
 
@@ -281,6 +285,17 @@ def _line(metric, value, unit, steps, warmup, ms_per_step, workload, extra, high
     return out
 
 
+def _roof(flops, seconds, what):
+    """Roofline object for a secondary workload: the whole timed region's
+    algorithmic FLOP rate against the FP64 vector peak (a lower bound on the
+    dominant kernel's own rate, since it includes the other kernels and the
+    launch gaps)."""
+    achieved = flops / seconds / 1e12
+    return {"bound": "alu", "kernel": what, "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+            "flop_convention": "algorithmic, per ordered pair: 20 (force), 38 + 12 per extra vector (HVP)"}
+
+
 def bench_md_single(args, which):
     """cloud1024 (100 steps, energies every step) or rf32768 (explicit RF,
     energies every 50 steps): time of whole runs, pairs/s = N^2 per step."""
@@ -308,7 +323,9 @@ def bench_md_single(args, which):
     ms = e0.elapsed_time(e1) / reps
     E = en[0, :, 3].cpu().numpy()
     extra = {"energy_rel_range": float((E.max() - E.min()) / abs(E[0])), "nsteps_per_run": nsteps,
-             "launch": api.get_config("md_run", n, "fp64")}
+             "launch": api.get_config("md_run", n, "fp64"),
+             "roofline": _roof(FLOPS_PER_PAIR * float(n) * n * nsteps, ms * 1e-3,
+                               "whole md_run (force stage + fused epilogue per step, energies as recorded)")}
     if not args.no_cpu:
         from oracle import oracle as O
 
@@ -355,7 +372,9 @@ def bench_kz(args):
         res[prec] = {"ms": ms, "runs_per_s": d["nrun"] / (ms * 1e-3), "pairs_per_s": pairs / (ms * 1e-3),
                      "defects_mean": float(np.mean(defects)), "finite": bool(np.isfinite(got).all())}
     extra = {"mixed": res["mixed"], "fp64": res["fp64"], "nrun": d["nrun"], "nsteps_per_run": nsteps,
-             "sum_N2": float((ns.astype(np.float64) ** 2).sum())}
+             "sum_N2": float((ns.astype(np.float64) ** 2).sum()),
+             "roofline": _roof(FLOPS_PER_PAIR * pairs, res["fp64"]["ms"] * 1e-3,
+                               "cb::k_batched<FP64> (one persistent launch for all runs)")}
     if not args.no_cpu:
         from oracle import oracle as O
 
@@ -433,10 +452,23 @@ def bench_crystal(args):
         tp[key] += h
         tm[key] -= h
         fd[key] = {"adjoint": float(g[c]), "central_fd": (loss(tp) - loss(tm)) / (2 * h)}
-    extra = {"minimise_s": t_min, "minimise": info, "hvp_ms_8vec": ms_hvp, "lanczos_s": t_lan,
+    hvp_flops = (38 + 12 * 7) * float(n) * n
+    extra = {"roofline": _roof(hvp_flops, ms_hvp * 1e-3, "cb::k_hvp<FP64> + epilogue, 8 vectors per pass"),
+             "minimise_s": t_min, "minimise": info, "hvp_ms_8vec": ms_hvp, "lanczos_s": t_lan,
              "lowest_over_wz2": [float(v) for v in lam[:6] / wz2],
              "zero_mode_rel": float(abs(lam[0]) / wz2), "kohn_axial_rel": kohn,
              "lanczos_max_residual": float(resid.max()), "lanczos": lan_info, "traj_grad_s": t_grad, "msd": L, "grad_fd": fd}
+    if not args.no_cpu:
+        from oracle import oracle as O
+
+        rc = r.cpu().numpy()
+        v1 = np.random.Generator(np.random.PCG64(2)).normal(size=(3, n))
+        t0 = time.perf_counter()
+        O.hvp(rc[0], rc[1], rc[2], d["q"], v1, m=d["m"], trap=trap)
+        t = time.perf_counter() - t0
+        extra["cpu_baseline"] = {"value": float(n) * n / t, "unit": "pairs*vectors/s",
+                                 "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+                                 "sample": f"oracle exact HVP (compensated), 1 vector at N={n}, {t:.1f} s"}
     return _line("HVP pair-vector interactions/s (FP64, 8 vectors per pass)", float(n) * n * 8 / (ms_hvp * 1e-3),
                  "pairs*vectors/s", 10, 1, ms_hvp,
                  "crystal8192: N=8192 minimised crystal, 2pi(1,1,0.05) MHz; Lanczos 32 lowest; 2000-step adjoint "

@@ -82,10 +82,12 @@ LaunchCfg default_cfg(int op, int64_t n, int prec) {
     (void)prec;
     const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
     if (force_op && n >= 16384 && n <= kSymMaxN) {
-        // Newton's third law: each pair once (see pair_sym.hpp).  Eight ions
-        // per lane amortise the per-j wave reduction best; below 32768 ions
-        // smaller tiles keep enough of them in flight (measured on MI355X).
-        c.algo = ALGO_SYM;
+        // Newton's third law: each pair once (see pair_sym.hpp), reactions
+        // summed through LDS.  Eight ions per lane amortise the per-j wave
+        // reduction best; below 32768 ions smaller tiles keep enough of them
+        // in flight; below 16384 the direct kernel is faster (measured on
+        // MI355X).
+        c.algo = ALGO_SYM_LDS;
         c.wg = kSymGroup;
         c.p = n >= 32768 ? 8 : (n >= 24576 ? 6 : 4);
         c.splits = n >= 32768 ? 512 : 256;

@@ -152,7 +152,7 @@ def test_symmetric_config_validation(api):
     c = api.get_config("md_run", 50000, "fp64")
     assert (c["algo"], c["p"], c["wg"], c["splits"], c["tuned"]) == (1, 3, 4, 2048, True)
     api.reset_config("md_run", 50000, "fp64")
-    assert api.get_config("md_run", 50000, "fp64")["algo"] == 1  # the default at this size
+    assert api.get_config("md_run", 50000, "fp64")["algo"] == 2  # the default at this size
     assert api.get_config("md_run", 1000, "fp64")["algo"] == 0
     assert api.get_config("energy", 50000, "fp64")["algo"] == 0  # the potential needs every ordered pair
     for algo in (1, 2):
