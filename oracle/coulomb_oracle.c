@@ -226,6 +226,13 @@ static void or_energies(int64_t n, const double* s, const double* q, const doubl
  *   r_{n+1} = r_n + v_n dt + dt^2/2 a_n
  *   a_{n+1} = a(r_{n+1}, t0 + (n+1) dt)
  *   v_{n+1} = v_n + dt/2 (a_n + a_{n+1})
+ * With the friction term of eq. (1), -Gamma v / m (tr->gamma = Gamma > 0),
+ * the velocity-dependent part is taken by the trapezoidal rule, with
+ * g_i = Gamma / m_i and a the conservative (Coulomb + trap) acceleration:
+ *   r_{n+1} = r_n + v_n dt + dt^2/2 (a_n - g_i v_n)
+ *   v_{n+1} = (v_n (1 - g_i dt/2) + dt/2 (a_n + a_{n+1})) / (1 + g_i dt/2)
+ * (the paper states the friction term but not how the integrator treats it;
+ * this is the reading taken).  state's a is the conservative acceleration.
  * state holds 9 arrays of n doubles: x y z vx vy vz ax ay az, updated in
  * place.  When init_accel is set, a_0 = a(r_0, t0) is computed first;
  * otherwise the given a is a_0.  When energies is non-NULL, energies[4*k ..]
@@ -244,18 +251,40 @@ void or_md_run(int64_t n, double* state, const double* q, const double* m, const
     int64_t rec = 0;
     if (energies && every > 0) or_energies(n, state, q, m, tr, t0, eps2, energies + 4 * rec++, nthreads);
     const double hdt2 = 0.5 * dt * dt, hdt = 0.5 * dt;
+    const double Gam = tr->gamma;
     for (int64_t s = 0; s < nsteps; ++s) {
-        for (int64_t i = 0; i < n; ++i) {
-            x[i] = x[i] + vx[i] * dt + hdt2 * ax[i];
-            y[i] = y[i] + vy[i] * dt + hdt2 * ay[i];
-            z[i] = z[i] + vz[i] * dt + hdt2 * az[i];
+        if (Gam == 0.0) {
+            for (int64_t i = 0; i < n; ++i) {
+                x[i] = x[i] + vx[i] * dt + hdt2 * ax[i];
+                y[i] = y[i] + vy[i] * dt + hdt2 * ay[i];
+                z[i] = z[i] + vz[i] * dt + hdt2 * az[i];
+            }
+        } else {
+            for (int64_t i = 0; i < n; ++i) {
+                double g = Gam / m[i];
+                x[i] = x[i] + vx[i] * dt + hdt2 * (ax[i] - g * vx[i]);
+                y[i] = y[i] + vy[i] * dt + hdt2 * (ay[i] - g * vy[i]);
+                z[i] = z[i] + vz[i] * dt + hdt2 * (az[i] - g * vz[i]);
+            }
         }
         double t1 = t0 + (double)(s + 1) * dt;
         or_accel(n, x, y, z, q, m, tr, t1, eps2, anx, any, anz, nthreads);
+        if (Gam == 0.0) {
+            for (int64_t i = 0; i < n; ++i) {
+                vx[i] = vx[i] + hdt * (ax[i] + anx[i]);
+                vy[i] = vy[i] + hdt * (ay[i] + any[i]);
+                vz[i] = vz[i] + hdt * (az[i] + anz[i]);
+            }
+        } else {
+            for (int64_t i = 0; i < n; ++i) {
+                double g = Gam / m[i];
+                double lo = 1.0 - g * hdt, hi = 1.0 + g * hdt;
+                vx[i] = (vx[i] * lo + hdt * (ax[i] + anx[i])) / hi;
+                vy[i] = (vy[i] * lo + hdt * (ay[i] + any[i])) / hi;
+                vz[i] = (vz[i] * lo + hdt * (az[i] + anz[i])) / hi;
+            }
+        }
         for (int64_t i = 0; i < n; ++i) {
-            vx[i] = vx[i] + hdt * (ax[i] + anx[i]);
-            vy[i] = vy[i] + hdt * (ay[i] + any[i]);
-            vz[i] = vz[i] + hdt * (az[i] + anz[i]);
             ax[i] = anx[i];
             ay[i] = any[i];
             az[i] = anz[i];
@@ -328,9 +357,14 @@ void or_hvp(int64_t n, const double* x, const double* y, const double* z, const 
  *   dL/dw_c += sum_i (-2 w_c r'_ic) la*_ic
  *   lr = lr*,  lv = lv' + dt lr*,  la = dt/2 lv' + dt^2/2 lr*
  * and finally a_0 = a(r_0) adds dL/dw_c += sum_i (-2 w_c r_0ic) la_0ic.
- * state0 holds x y z vx vy vz (6n doubles).  out[0] = L, out[1..3] = dL/dw. */
+ * state0 holds x y z vx vy vz (6n doubles).  out[0] = L, out[1..3] = dL/dw.
+ * Without friction only (tr->gamma != 0 gives NaN in every output). */
 void or_msd_grad(int64_t n, const double* state0, const double* q, const double* m, const or_trap* tr,
                  double dt, int64_t nsteps, double eps2, double* out, int nthreads) {
+    if (tr->gamma != 0.0) {
+        out[0] = out[1] = out[2] = out[3] = NAN;
+        return;
+    }
     const size_t N9 = 9 * (size_t)n;
     double* tr_all = (double*)malloc(sizeof(double) * N9 * (size_t)(nsteps + 1));
     memcpy(tr_all, state0, sizeof(double) * 6 * (size_t)n);

@@ -381,3 +381,64 @@ def test_plain_double_loop_agrees_with_compensated_oracle(oracle):
     err = np.linalg.norm(np.stack([px, py, pz]) - ref, axis=0) / np.linalg.norm(ref, axis=0)
     assert used >= 1
     assert np.all(err <= 64 * U * math.sqrt(d["n"]) * kappa)
+
+
+# ---------------------------------------------------------------- friction
+# eq. (1)'s friction term -Gamma v / m, taken by the trapezoidal rule inside
+# velocity-Verlet (the integrator's treatment is not stated in the paper).
+
+def _damped_exact(x0, v0, w, g, t):
+    """x(t) of x'' + g x' + w^2 x = 0 (underdamped), x(0) = x0, x'(0) = v0."""
+    wd = np.sqrt(w * w - 0.25 * g * g)
+    return np.exp(-0.5 * g * t) * (x0 * np.cos(wd * t) + (v0 + 0.5 * g * x0) / wd * np.sin(wd * t))
+
+
+def test_friction_single_ion_converges_to_damped_oscillator(oracle):
+    # one ion (no Coulomb force) in a static trap with friction: the scheme
+    # must converge to the exact damped solution at second order in dt
+    f = np.array([1.0e6, 0.7e6, 0.2e6])
+    w = TWO_PI * f
+    g = 0.2 * w[2]  # gamma = Gamma / m, light damping on every axis
+    trap = inputs.trap_dict(kind=0, wx=w[0], wy=w[1], wz=w[2], gamma=g * M40)
+    r0 = np.array([1e-6, -2e-6, 3e-6])
+    v0 = np.array([0.3, 0.1, -0.05]) * w * 1e-6
+    T = 3.0 / f[2]
+    errs = []
+    for steps in (6000, 12000):
+        dt = T / steps
+        st = np.zeros((9, 1))
+        st[:3, 0], st[3:6, 0] = r0, v0
+        out, _, _ = oracle.md_run(st, [E], [M40], trap, 0.0, dt, steps)
+        exact = np.array([_damped_exact(r0[c], v0[c], w[c], g, T) for c in range(3)])
+        errs.append(np.max(np.abs(out[:3, 0] - exact)) / np.max(np.abs(r0)))
+    assert errs[1] < 2e-4
+    assert 3.6 < errs[0] / errs[1] < 4.4, errs
+
+
+def test_friction_zero_gamma_is_plain_velocity_verlet(oracle):
+    d = inputs.cloud1024(n=48, seed=4)
+    st = inputs.state9(d)
+    t0 = inputs.pseudo_trap(1e6, 1e6, 0.2e6)
+    t1 = dict(t0, gamma=0.0)
+    a, _, _ = oracle.md_run(st, d["q"], d["m"], t0, 0.0, 1e-9, 50)
+    b, _, _ = oracle.md_run(st, d["q"], d["m"], t1, 0.0, 1e-9, 50)
+    assert np.array_equal(a, b)
+
+
+def test_friction_relaxes_two_ions_to_closed_form_spacing(oracle):
+    # two ions released away from equilibrium come to rest at the spacing
+    # d = (q^2 / (2 pi eps0 m wz^2))^(1/3) on the trap axis
+    wz = TWO_PI * 0.2e6
+    d = (2.0 * KC_CODATA * E * E / (M40 * wz * wz)) ** (1.0 / 3.0)
+    g = 0.5 * wz
+    trap = inputs.trap_dict(kind=0, wx=TWO_PI * 1e6, wy=TWO_PI * 1e6, wz=wz, gamma=g * M40)
+    st = np.zeros((9, 2))
+    st[2] = [0.8 * d, -0.5 * d]
+    st[0] = [0.1 * d, -0.05 * d]
+    st[5] = [3.0, -1.0]
+    out, en, _ = oracle.md_run(st, [E, E], [M40, M40], trap, 0.0, 2e-9, 60000, every=1000)
+    assert abs((out[2, 0] - out[2, 1]) - d) <= 1e-8 * d
+    assert abs(out[2, 0] + out[2, 1]) <= 1e-8 * d and np.max(np.abs(out[0])) <= 1e-8 * d
+    E_tot = en[:, 3]
+    assert np.all(np.diff(E_tot) <= 1e-14 * abs(E_tot[-1]))  # friction only removes energy
+    assert E_tot[0] - E_tot[-1] > 0.1 * abs(E_tot[-1])  # the released pair had energy to lose
