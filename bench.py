@@ -30,9 +30,10 @@ FLOPS_PER_PAIR = 20  # the paper's double loop with +,-,*,/,sqrt counted once ea
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ("paper_2106_11143_amd/csrc/pair_kernels.hpp", "paper_2106_11143_amd/csrc/pair_sym.hpp",
+# sources of the default force stage (the counter summary is valid only for these as committed)
+KERNEL_SOURCES = ("paper_2106_11143_amd/csrc/pair_sym.hpp", "paper_2106_11143_amd/csrc/pair_sym.hip",
                   "paper_2106_11143_amd/csrc/wave_reduce.hpp", "paper_2106_11143_amd/csrc/rsqrt.hpp",
-                  "paper_2106_11143_amd/csrc/pair.hip")
+                  "paper_2106_11143_amd/csrc/step_common.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_stage_fp64_cloud100k_traffic.json")
 STAGE_KERNELS = {
     0: "cb::k_pair<FP64> (all-pairs force, j-split partials)",
@@ -78,7 +79,7 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (rocprofv3 counter calibration)")
     ap.add_argument("--workload", default="cloud100k",
-                    choices=["cloud100k", "cloud1024", "rf32768", "kz512", "crystal8192"],
+                    choices=["cloud100k", "cloud1024", "rf32768", "kz512", "crystal8192", "rsqrt_sweep"],
                     help="cloud100k is the headline; the others time the remaining workloads")
     ap.add_argument("--direct", action="store_true",
                     help="force the direct kernel (every ordered pair, j-split partials) instead of the "
@@ -165,6 +166,22 @@ def main():
     traffic = counters.get("bytes_per_launch") if counters else None
     executed = counters.get("executed_fp64_flops_per_launch") if counters else None
 
+    # one GPU's share of an 8-way split by ion index: forces on N/8 ions from all N
+    xs, ys, zs = (dev(d[k]) for k in ("x", "y", "z"))
+    i0, i1 = 3 * n // 8, 4 * n // 8
+    api.coulomb_forces_range(xs, ys, zs, q, i0, i1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        api.coulomb_forces_range(xs, ys, zs, q, i0, i1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_share = e0.elapsed_time(e1) / reps
+    share = {"i_range": [i0, i1], "ms": ms_share, "pairs_per_s": float(i1 - i0) * n / (ms_share * 1e-3),
+             "note": "coulomb_forces_range (direct kernel, every ordered pair of the range) on one GPU; the "
+                     "position all-gather of a multi-GPU run is not included"}
+
     # force error of the mixed path against the FP64 path, all ions
     x, y, z = (dev(d[k]) for k in ("x", "y", "z"))
     F64 = torch.stack(api.coulomb_forces(x, y, z, q, prec="fp64")).cpu().numpy()
@@ -204,6 +221,7 @@ def main():
                                "the Newton's-third-law stage evaluates each unordered pair once",
             "executed_fp64_tflops": executed / (kt64 * 1e-3) / 1e12 if executed else None,
         },
+        "one_gpu_share_of_8": share,
         "mixed": {
             "pairs_per_s": pairs_step * args.steps / (ms_mixed * 1e-3),
             "ms_per_step": ms_mixed / args.steps,
@@ -475,11 +493,58 @@ def bench_crystal(args):
                  "gradient, checkpoints every 50", extra)
 
 
+def bench_rsqrt_sweep(args):
+    """Speed and accuracy of the four 1/sqrt variants against N (the paper's
+    comparison of SQRT+DIV with the approximate inverse square root plus 0, 1
+    or 2 Newton-Raphson steps, sections 4 and 6): time per force evaluation
+    in the default launch of each size, and the per-ion relative force error
+    against the oracle on a sample of ions."""
+    np, torch, api, inputs, dev = _setup()
+    from oracle import oracle as O
+
+    variants = {"ieee": "SQRT+DIV (IEEE sqrt, division)", "fp64": "FP32 seed + 2nd-order refinement",
+                "mixed": "FP32 seed + one Newton step", "fp32": "FP32 seed only"}
+    sizes = [1024, 4096, 16384, 32768, 65536, 100000]
+    rows = []
+    for n in sizes:
+        d = inputs.cloud100k(n=n)
+        x, y, z, q = (dev(d[k]) for k in ("x", "y", "z", "q"))
+        g = np.random.Generator(np.random.PCG64(11))
+        idx = np.sort(g.choice(n, min(n, 256), replace=False))
+        ref = np.stack(O.forces(d["x"], d["y"], d["z"], d["q"], idx=idx))
+        for prec in variants:
+            F = api.coulomb_forces(x, y, z, q, prec=prec)
+            torch.cuda.synchronize()
+            reps = max(3, int(0.05 / (n * n * 2e-13)))
+            e0, e1 = _timer(torch)
+            e0.record()
+            for _ in range(reps):
+                api.coulomb_forces(x, y, z, q, prec=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            Fh = np.stack([t.cpu().numpy() for t in F])[:, idx]
+            err = np.linalg.norm(Fh - ref, axis=0) / np.linalg.norm(ref, axis=0)
+            cfg = api.get_config("forces", n, prec)
+            rows.append({"n": n, "variant": prec, "ms": ms, "pairs_per_s": float(n) * n / (ms * 1e-3),
+                         "max_rel_err": float(err.max()), "rms_rel_err": float(np.sqrt(np.mean(err ** 2))),
+                         "algo": cfg["algo"]})
+            print(f"n={n:6d} {prec:5s} {ms:9.4f} ms {float(n) * n / (ms * 1e-3):.3e} pairs/s "
+                  f"max_err {err.max():.2e}", file=sys.stderr, flush=True)
+    top = [r for r in rows if r["n"] == sizes[-1]]
+    best = {r["variant"]: r["pairs_per_s"] for r in top}
+    return _line("pair interactions/s per 1/sqrt variant (cloud100k-shaped clouds, coulomb_forces)",
+                 best["fp64"], "pairs/s", 1, 1, [r["ms"] for r in top if r["variant"] == "fp64"][0],
+                 f"rsqrt sweep: Gaussian clouds N in {sizes}, 1% at +2e, four 1/sqrt variants", 
+                 {"variants": variants, "table": rows})
+
+
 OTHER_WORKLOADS = {
     "cloud1024": lambda a: bench_md_single(a, "cloud1024"),
     "rf32768": lambda a: bench_md_single(a, "rf32768"),
     "kz512": bench_kz,
     "crystal8192": bench_crystal,
+    "rsqrt_sweep": bench_rsqrt_sweep,
 }
 
 

@@ -97,7 +97,12 @@ typedef enum { CB_OP_FORCES = 0, CB_OP_ENERGY = 1, CB_OP_MD_STEP = 2, CB_OP_MD_R
  *  kind 1: explicit RF drive in Mathieu form plus a static axial well:
  *          kx = rf_a rf_omega^2/4 + rf_q rf_omega^2/2 cos(rf_omega t + rf_phase),
  *          ky = -kx, kz = wz^2.
- *  gamma (friction, kg/s) must be 0 in this build (CB_EUNSUPPORTED otherwise).
+ *  gamma: the friction coefficient Gamma >= 0 (kg/s) of eq. (1)'s -Gamma v / m
+ *          term (0 = none).  md_step / md_run integrate it by the trapezoidal
+ *          rule inside velocity-Verlet (g = Gamma / m_i): the drift uses
+ *          a - g v, and v_{n+1} = (v_n (1 - g dt/2) + dt/2 (a_n + a_{n+1})) /
+ *          (1 + g dt/2); the state's a stays the conservative acceleration.
+ *          md_adjoint_step needs gamma = 0; coulomb_hvp ignores it.
  *  All frequencies in rad/s. */
 typedef struct {
     int32_t kind;
@@ -125,13 +130,26 @@ cb_status coulomb_forces(int64_t n, const double* x, const double* y, const doub
                          double eps2, int32_t prec, double* fx, double* fy, double* fz,
                          void* ws, size_t ws_bytes, void* stream);
 
+/* Forces (N) on the ions i0 .. i1-1 only, from all n ions (the same sum as
+ * coulomb_forces, eq. (1) and the section 3 double loop, restricted to a
+ * contiguous range of i): the share of one GPU when a force evaluation is
+ * split across GPUs by ion index, each GPU holding every position.  x, y, z,
+ * q: n doubles each.  fx, fy, fz: outputs of i1 - i0 doubles, indexed by
+ * i - i0; they must not alias the inputs.  0 <= i0 < i1 <= n, else
+ * CB_EINVAL.  Every ordered pair with i in the range is evaluated (no
+ * Newton's third law); the sums are deterministic.  Workspace:
+ * cb_workspace_size(CB_OP_FORCES, n, 1, 1, prec) suffices. */
+cb_status coulomb_forces_range(int64_t n, int64_t i0, int64_t i1, const double* x, const double* y, const double* z,
+                               const double* q, double eps2, int32_t prec, double* fx, double* fy, double* fz,
+                               void* ws, size_t ws_bytes, void* stream);
+
 /* The first stage of coulomb_forces on its own (everything but the final
  * element-wise pass), for timing the pair loop and for callers that finish
  * the sums themselves.  With algorithm 0 (see cb_get_config) the all-pairs
  * kernel leaves its j-split partial force sums, before the fixed-order sum
  * over splits and the k_C q_i factor, at the start of ws as [splits][3][n]
- * doubles and *splits_out (host) is the number of splits; with algorithm 1
- * the start of ws holds the finished forces [3][n] and *splits_out is 0. */
+ * doubles and *splits_out (host) is the number of splits; with algorithms 1
+ * and 2 the start of ws holds the finished forces [3][n] and *splits_out is 0. */
 cb_status coulomb_pair_stage(int64_t n, const double* x, const double* y, const double* z, const double* q,
                              double eps2, int32_t prec, int32_t* splits_out, void* ws, size_t ws_bytes,
                              void* stream);

@@ -27,7 +27,7 @@ OPS = {"forces": 0, "energy": 1, "md_step": 2, "md_run": 3, "hvp": 4, "adjoint":
 CB_INIT_ACCEL = 1
 CB_ADJ_FINAL = 1
 
-EXPORTS = ("cb_workspace_size", "coulomb_forces", "coulomb_pair_stage", "coulomb_energy", "md_step", "md_run", "coulomb_hvp",
+EXPORTS = ("cb_workspace_size", "coulomb_forces", "coulomb_forces_range", "coulomb_pair_stage", "coulomb_energy", "md_step", "md_run", "coulomb_hvp",
            "md_adjoint_step", "cb_poll_flags", "cb_last_error", "cb_autotune", "cb_load_tuning", "cb_get_config",
            "cb_set_config")
 
@@ -76,6 +76,7 @@ def lib() -> C.CDLL:
                 L.cb_workspace_size.argtypes = [i32, i64, i32, i32, i32]
                 L.cb_workspace_size.restype = sz
                 L.coulomb_forces.argtypes = [i64, _P, _P, _P, _P, d, i32, _P, _P, _P, _P, sz, _P]
+                L.coulomb_forces_range.argtypes = [i64, i64, i64, _P, _P, _P, _P, d, i32, _P, _P, _P, _P, sz, _P]
                 L.coulomb_energy.argtypes = [i64, _P, _P, _P, _P, d, i32, _P, _P, sz, _P]
                 L.coulomb_pair_stage.argtypes = [i64, _P, _P, _P, _P, d, i32, C.POINTER(C.c_int32), _P, sz, _P]
                 L.md_step.argtypes = [i64, C.POINTER(State), _P, _P, C.POINTER(Trap), d, d, d, i32, _P, sz, _P]
@@ -181,6 +182,24 @@ def coulomb_forces(x, y, z, q, eps2: float = 0.0, prec="fp64", out=None):
     _check(lib().coulomb_forces(n, x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(), float(eps2), _prec(prec),
                                 fx.data_ptr(), fy.data_ptr(), fz.data_ptr(), ws.data_ptr(), ws.numel(), _stream()),
            "coulomb_forces")
+    return fx, fy, fz
+
+
+def coulomb_forces_range(x, y, z, q, i0: int, i1: int, eps2: float = 0.0, prec="fp64", out=None):
+    """Forces (N) on the ions i0 .. i1-1 from all ions; returns (fx, fy, fz)
+    of length i1 - i0."""
+    dev = _dev_f64(x, y, z, q)
+    n = x.numel()
+    ni = int(i1) - int(i0)
+    if out is not None:
+        fx, fy, fz = out
+    else:
+        fx, fy, fz = (torch.empty(max(ni, 0), dtype=torch.float64, device=dev) for _ in range(3))
+    ws = _workspace("forces", n, prec=prec, device=dev)
+    _check(lib().coulomb_forces_range(n, int(i0), int(i1), x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(),
+                                      float(eps2), _prec(prec), fx.data_ptr(), fy.data_ptr(), fz.data_ptr(),
+                                      ws.data_ptr(), ws.numel(), _stream()),
+           "coulomb_forces_range")
     return fx, fy, fz
 
 

@@ -156,6 +156,7 @@ __global__ void __launch_bounds__(kBatchWG) k_batched(BatchParams B) {
         for (int i = tid; i < n; i += kBatchWG) sh[i] = make_double4(X[i], Y[i], Z[i], Q[i]);
         __syncthreads();
         const double dt = B.dt, hdt = 0.5 * dt, hdt2 = 0.5 * dt * dt, eps2 = B.eps2;
+        const double Gam = tr.gamma;  // friction coefficient Gamma (kg/s), uniform over the run
         bool bad = false;
         const long long nrec = B.energies ? B.nsteps / B.every + 1 : 0;
         double* Erun = B.energies ? B.energies + (size_t)run * nrec * 4 : nullptr;
@@ -198,9 +199,16 @@ __global__ void __launch_bounds__(kBatchWG) k_batched(BatchParams B) {
             // drift of the owned ions
             for (int i = tid; i < n; i += kBatchWG) {
                 double4 r = sh[i];
-                r.x = r.x + VX[i] * dt + hdt2 * AX[i];
-                r.y = r.y + VY[i] * dt + hdt2 * AY[i];
-                r.z = r.z + VZ[i] * dt + hdt2 * AZ[i];
+                if (Gam == 0.0) {
+                    r.x = r.x + VX[i] * dt + hdt2 * AX[i];
+                    r.y = r.y + VY[i] * dt + hdt2 * AY[i];
+                    r.z = r.z + VZ[i] * dt + hdt2 * AZ[i];
+                } else {  // the drift sees the friction acceleration -g v too
+                    const double g = Gam / M[i];
+                    r.x = r.x + VX[i] * dt + hdt2 * (AX[i] - g * VX[i]);
+                    r.y = r.y + VY[i] * dt + hdt2 * (AY[i] - g * VY[i]);
+                    r.z = r.z + VZ[i] * dt + hdt2 * (AZ[i] - g * VZ[i]);
+                }
                 sh[i] = r;
             }
             __syncthreads();
@@ -214,9 +222,17 @@ __global__ void __launch_bounds__(kBatchWG) k_batched(BatchParams B) {
                 const double anx = c * fx / mi - k.kx * r.x;
                 const double any = c * fy / mi - k.ky * r.y;
                 const double anz = c * fz / mi - k.kz * r.z;
-                const double vx = VX[i] + hdt * (AX[i] + anx);
-                const double vy = VY[i] + hdt * (AY[i] + any);
-                const double vz = VZ[i] + hdt * (AZ[i] + anz);
+                double vx, vy, vz;
+                if (Gam == 0.0) {
+                    vx = VX[i] + hdt * (AX[i] + anx);
+                    vy = VY[i] + hdt * (AY[i] + any);
+                    vz = VZ[i] + hdt * (AZ[i] + anz);
+                } else {  // friction -g v by the trapezoidal rule, g = Gamma / m_i
+                    const double g = Gam / mi, lo = 1.0 - g * hdt, hi = 1.0 + g * hdt;
+                    vx = (VX[i] * lo + hdt * (AX[i] + anx)) / hi;
+                    vy = (VY[i] * lo + hdt * (AY[i] + any)) / hi;
+                    vz = (VZ[i] * lo + hdt * (AZ[i] + anz)) / hi;
+                }
                 VX[i] = vx;
                 VY[i] = vy;
                 VZ[i] = vz;

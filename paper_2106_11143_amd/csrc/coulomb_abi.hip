@@ -191,8 +191,8 @@ bool trap_ok(const cb_trap* t, const char* who, cb_status* st) {
         *st = fail(CB_EINVAL, "%s: trap kind must be 0 or 1", who);
         return false;
     }
-    if (t->gamma != 0.0) {
-        *st = fail(CB_EUNSUPPORTED, "%s: friction (gamma != 0) is not supported", who);
+    if (t->gamma < 0.0) {
+        *st = fail(CB_EINVAL, "%s: friction gamma must be >= 0", who);
         return false;
     }
     return true;

@@ -32,6 +32,14 @@ static cb_status check_common(const char* who, int64_t n, int32_t prec, double e
     return CB_OK;
 }
 
+// [a, a + na) and [b, b + nb) doubles intersect.
+static bool overlaps2(const void* a, int64_t na, const void* b, int64_t nb) {
+    if (!a || !b) return false;
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + nb * (int64_t)sizeof(double) && pb < pa + na * (int64_t)sizeof(double);
+}
+
 static double* at(void* ws, size_t off) { return reinterpret_cast<double*>(static_cast<char*>(ws) + off); }
 
 struct PairRun {
@@ -216,6 +224,50 @@ cb_status coulomb_forces(int64_t n, const double* x, const double* y, const doub
     E.flags = flags_ptr();
     if (!E.flags) return fail(CB_EHIP, "coulomb_forces: device flag symbol not found");
     k_epilogue<<<(int)((n + kEpiThreads - 1) / kEpiThreads), kEpiThreads, 0, st>>>(E);
+    if ((rc = check_launch("k_epilogue"))) return rc;
+    return ok();
+}
+
+cb_status coulomb_forces_range(int64_t n, int64_t i0, int64_t i1, const double* x, const double* y, const double* z,
+                               const double* q, double eps2, int32_t prec, double* fx, double* fy, double* fz,
+                               void* ws, size_t ws_bytes, void* stream) {
+    const WsLayout L = ws_layout(CB_OP_FORCES, n > 0 ? n : 1, 1, 1);
+    cb_status rc = check_common("coulomb_forces_range", n, prec, eps2, ws, ws_bytes, L.total);
+    if (rc) return rc;
+    if (i0 < 0 || i1 <= i0 || i1 > n)
+        return fail(CB_EINVAL, "coulomb_forces_range: need 0 <= i0 < i1 <= n (i0 = %lld, i1 = %lld, n = %lld)",
+                    (long long)i0, (long long)i1, (long long)n);
+    if (!x || !y || !z || !q || !fx || !fy || !fz) return fail(CB_EINVAL, "coulomb_forces_range: NULL array");
+    const int64_t ni = i1 - i0;
+    const void* in[4] = {x, y, z, q};
+    const void* out[3] = {fx, fy, fz};
+    for (auto o : out)
+        for (auto i : in)
+            if (overlaps2(o, ni, i, n)) return fail(CB_EINVAL, "coulomb_forces_range: output aliases an input");
+    if (overlaps2(fx, ni, fy, ni) || overlaps2(fx, ni, fz, ni) || overlaps2(fy, ni, fz, ni))
+        return fail(CB_EINVAL, "coulomb_forces_range: outputs overlap");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // the direct kernel over the i-range; j-splits sized for the range's waves
+    LaunchCfg cfg = get_cfg(CB_OP_FORCES, n, prec);
+    if (cfg.algo != ALGO_DIRECT) cfg = default_cfg(CB_OP_ENERGY, ni, prec);
+    const int jlen = split_len(n, cfg.splits);
+    const int S = n_splits(n, jlen);
+    double* part = at(ws, L.part);
+    if ((rc = launch_pair_range(prec, cfg, true, false, (int)n, (int)i0, (int)ni, x, y, z, q, eps2, jlen, part,
+                                nullptr, st)))
+        return rc;
+    EpiParams E{};
+    E.n = (int)ni;
+    E.S = S;
+    E.part = part;
+    E.q = q + i0;
+    E.fx = fx;
+    E.fy = fy;
+    E.fz = fz;
+    E.mode = EPI_FORCES;
+    E.flags = flags_ptr();
+    if (!E.flags) return fail(CB_EHIP, "coulomb_forces_range: device flag symbol not found");
+    k_epilogue<<<(int)((ni + kEpiThreads - 1) / kEpiThreads), kEpiThreads, 0, st>>>(E);
     if ((rc = check_launch("k_epilogue"))) return rc;
     return ok();
 }

@@ -251,8 +251,9 @@ cb_status md_adjoint_step(int64_t n, const double* x, const double* y, const dou
     if (rc) return rc;
     if (!x || !y || !z || !q || !m || !lam || !dldw) return fail(CB_EINVAL, "md_adjoint_step: NULL argument");
     if (!trap_ok(trap, "md_adjoint_step", &rc)) return rc;
-    if (trap->kind != 0 || trap->t_ramp1 > trap->t_ramp0)
-        return fail(CB_EUNSUPPORTED, "md_adjoint_step: needs a static pseudo-potential trap (kind 0, no ramp)");
+    if (trap->kind != 0 || trap->t_ramp1 > trap->t_ramp0 || trap->gamma != 0.0)
+        return fail(CB_EUNSUPPORTED,
+                    "md_adjoint_step: needs a static pseudo-potential trap (kind 0, no ramp, no friction)");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CB_EINVAL, "md_adjoint_step: dt must be > 0");
     if (flags & ~CB_ADJ_FINAL) return fail(CB_EINVAL, "md_adjoint_step: unknown flags 0x%x", flags);
     const size_t lb = sizeof(double) * 9 * (size_t)n, ab = sizeof(double) * (size_t)n;

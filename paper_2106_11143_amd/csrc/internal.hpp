@@ -69,7 +69,12 @@ size_t sym_ws_bytes(int64_t n, int p, int jl);
 cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, const double* y, const double* z,
                           const double* q, double eps2, void* ws, double* F, hipStream_t st);
 
-// Launches of the pair kernels (pair.hip).
+// Launches of the pair kernels (pair.hip).  The _range form evaluates the
+// forces / potentials of the ions i0 .. i0 + ni - 1 only (partials indexed by
+// i - i0); launch_pair is the whole range.
+cb_status launch_pair_range(int prec, const LaunchCfg& c, bool force, bool pot, int n, int i0, int ni,
+                            const double* x, const double* y, const double* z, const double* q, double eps2,
+                            int jlen, double* part, double* ppot, hipStream_t st);
 cb_status launch_pair(int prec, const LaunchCfg& c, bool force, bool pot, int n, const double* x,
                       const double* y, const double* z, const double* q, double eps2, int jlen, double* part,
                       double* ppot, hipStream_t st);

@@ -1,148 +1,70 @@
-// Instantiation and launch of the all-pairs kernels for every precision,
-// i-particles-per-lane count and output kind.
+// Instantiation and launch of the direct all-pairs kernel for every
+// precision, i-particles-per-lane count and output kind.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
 #include "pair_kernels.hpp"
-#include "pair_sym.hpp"
 
 namespace cb {
 
+struct PairArgs {
+    int n, i0, ni;
+    const double *x, *y, *z, *q;
+    double eps2;
+    int jlen;
+    double *part, *ppot;
+};
+
 template <int PREC, int P, bool FORCE, bool POT>
-static void go(dim3 grid, dim3 block, hipStream_t st, int n, const double* x, const double* y, const double* z,
-               const double* q, double eps2, int jlen, double* part, double* ppot) {
-    k_pair<PREC, P, FORCE, POT><<<grid, block, 0, st>>>(n, x, y, z, q, eps2, jlen, part, ppot);
+static void go(dim3 grid, dim3 block, hipStream_t st, const PairArgs& a) {
+    k_pair<PREC, P, FORCE, POT><<<grid, block, 0, st>>>(a.n, a.i0, a.ni, a.x, a.y, a.z, a.q, a.eps2, a.jlen, a.part,
+                                                        a.ppot);
 }
 
 template <int PREC, int P>
-static bool go_kind(bool force, bool pot, dim3 g, dim3 b, hipStream_t st, int n, const double* x,
-                    const double* y, const double* z, const double* q, double eps2, int jlen, double* part,
-                    double* ppot) {
-    if (force && pot) go<PREC, P, true, true>(g, b, st, n, x, y, z, q, eps2, jlen, part, ppot);
-    else if (force) go<PREC, P, true, false>(g, b, st, n, x, y, z, q, eps2, jlen, part, ppot);
-    else if (pot) go<PREC, P, false, true>(g, b, st, n, x, y, z, q, eps2, jlen, part, ppot);
+static bool go_kind(bool force, bool pot, dim3 g, dim3 b, hipStream_t st, const PairArgs& a) {
+    if (force && pot) go<PREC, P, true, true>(g, b, st, a);
+    else if (force) go<PREC, P, true, false>(g, b, st, a);
+    else if (pot) go<PREC, P, false, true>(g, b, st, a);
     else return false;
     return true;
 }
 
 template <int PREC>
-static bool go_p(int p, bool force, bool pot, dim3 g, dim3 b, hipStream_t st, int n, const double* x,
-                 const double* y, const double* z, const double* q, double eps2, int jlen, double* part,
-                 double* ppot) {
+static bool go_p(int p, bool force, bool pot, dim3 g, dim3 b, hipStream_t st, const PairArgs& a) {
     switch (p) {
-        case 1: return go_kind<PREC, 1>(force, pot, g, b, st, n, x, y, z, q, eps2, jlen, part, ppot);
-        case 2: return go_kind<PREC, 2>(force, pot, g, b, st, n, x, y, z, q, eps2, jlen, part, ppot);
-        case 4: return go_kind<PREC, 4>(force, pot, g, b, st, n, x, y, z, q, eps2, jlen, part, ppot);
+        case 1: return go_kind<PREC, 1>(force, pot, g, b, st, a);
+        case 2: return go_kind<PREC, 2>(force, pot, g, b, st, a);
+        case 4: return go_kind<PREC, 4>(force, pot, g, b, st, a);
         default: return false;
     }
 }
 
-cb_status launch_pair(int prec, const LaunchCfg& c, bool force, bool pot, int n, const double* x,
-                      const double* y, const double* z, const double* q, double eps2, int jlen, double* part,
-                      double* ppot, hipStream_t st) {
+cb_status launch_pair_range(int prec, const LaunchCfg& c, bool force, bool pot, int n, int i0, int ni,
+                            const double* x, const double* y, const double* z, const double* q, double eps2,
+                            int jlen, double* part, double* ppot, hipStream_t st) {
+    if (i0 < 0 || ni < 1 || i0 + ni > n) return fail(CB_EINVAL, "launch_pair: bad i-range");
     const int S = n_splits(n, jlen);
     const int ipb = 64 * c.p * (c.wg / 64);  // i-particles per workgroup
-    dim3 grid((n + ipb - 1) / ipb, S);
+    dim3 grid((ni + ipb - 1) / ipb, S);
     dim3 block(c.wg);
+    const PairArgs a{n, i0, ni, x, y, z, q, eps2, jlen, part, ppot};
     bool okk = false;
     switch (prec) {
-        case PREC_FP64: okk = go_p<PREC_FP64>(c.p, force, pot, grid, block, st, n, x, y, z, q, eps2, jlen, part, ppot); break;
-        case PREC_MIXED: okk = go_p<PREC_MIXED>(c.p, force, pot, grid, block, st, n, x, y, z, q, eps2, jlen, part, ppot); break;
-        case PREC_IEEE: okk = go_p<PREC_IEEE>(c.p, force, pot, grid, block, st, n, x, y, z, q, eps2, jlen, part, ppot); break;
-        case PREC_FP32: okk = go_p<PREC_FP32>(c.p, force, pot, grid, block, st, n, x, y, z, q, eps2, jlen, part, ppot); break;
+        case PREC_FP64: okk = go_p<PREC_FP64>(c.p, force, pot, grid, block, st, a); break;
+        case PREC_MIXED: okk = go_p<PREC_MIXED>(c.p, force, pot, grid, block, st, a); break;
+        case PREC_IEEE: okk = go_p<PREC_IEEE>(c.p, force, pot, grid, block, st, a); break;
+        case PREC_FP32: okk = go_p<PREC_FP32>(c.p, force, pot, grid, block, st, a); break;
         default: break;
     }
     if (!okk) return fail(CB_EINVAL, "launch_pair: unsupported precision %d / p %d", prec, c.p);
     return check_launch("k_pair");
 }
 
-// --------------------------------------------------------- symmetric path
-static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
-
-static int64_t sym_tiles(int64_t n, int IB, int JL) {
-    const int nI = (int)((n + IB - 1) / IB);
-    int64_t T = 0;
-    for (int I = 0; I < nI; ++I) T += sym_nseg((int)n, IB, JL, I);
-    return T;
-}
-
-// Workspace carve-up: rowstart[nI+1] | tiles[T] | Pi[T][3][IB] | R[T][3][JL]
-size_t sym_ws_bytes(int64_t n, int p, int jl) {
-    const int IB = 64 * p;
-    const int64_t nI = (n + IB - 1) / IB;
-    const int64_t T = sym_tiles(n, IB, jl);
-    return al256(sizeof(int) * (nI + 1)) + al256(sizeof(int2) * (T + 1)) +
-           al256(sizeof(double) * 3 * IB * (T + 1)) + al256(sizeof(double) * 3 * (size_t)jl * (T + 1));
-}
-
-template <int PREC, int P, int RED>
-static void go_sym(int n, int JL, int64_t T, const double* x, const double* y, const double* z, const double* q,
-                   double eps2, const int2* tiles, double* Pi, double* R, hipStream_t st) {
-    k_pair_sym<PREC, P, RED><<<(unsigned)T, 64, 0, st>>>(n, x, y, z, q, eps2, JL, tiles, Pi, R);
-}
-
-template <int PREC, int RED>
-static bool go_sym_p(int P, int n, int JL, int64_t T, const double* x, const double* y, const double* z,
-                     const double* q, double eps2, const int2* tiles, double* Pi, double* R, hipStream_t st) {
-    switch (P) {
-        case 2: go_sym<PREC, 2, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 3: go_sym<PREC, 3, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 4: go_sym<PREC, 4, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 5: go_sym<PREC, 5, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 6: go_sym<PREC, 6, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 8: go_sym<PREC, 8, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        default: return false;
-    }
-}
-
-template <int PREC>
-static bool go_sym_pr(int P, int red, int n, int JL, int64_t T, const double* x, const double* y, const double* z,
-                      const double* q, double eps2, const int2* tiles, double* Pi, double* R, hipStream_t st) {
-    return red ? go_sym_p<PREC, 1>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st)
-               : go_sym_p<PREC, 0>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st);
-}
-
-cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, const double* y, const double* z,
-                          const double* q, double eps2, void* ws, double* F, hipStream_t st) {
-    const int P = c.p, JL = c.splits, IB = 64 * P;
-    if (!is_sym(c.algo) || !sym_cfg_ok(P, c.wg, JL)) return fail(CB_EINVAL, "launch_pair_sym: bad configuration");
-    const int red = c.algo == ALGO_SYM_LDS ? 1 : 0;
-    const int nI = (n + IB - 1) / IB;
-    if (nI > kPlanMaxRows) return fail(CB_EINVAL, "launch_pair_sym: n = %d is too large for the symmetric kernel", n);
-    const int64_t T = sym_tiles(n, IB, JL);
-    char* base = static_cast<char*>(ws);
-    int* rowstart = reinterpret_cast<int*>(base);
-    base += al256(sizeof(int) * (nI + 1));
-    int2* tiles = reinterpret_cast<int2*>(base);
-    base += al256(sizeof(int2) * (T + 1));
-    double* Pi = reinterpret_cast<double*>(base);
-    base += al256(sizeof(double) * 3 * IB * (T + 1));
-    double* R = reinterpret_cast<double*>(base);
-    k_sym_plan<<<1, kPlanThreads, 0, st>>>(n, IB, JL, nI, rowstart, tiles);
-    cb_status rc = check_launch("k_sym_plan");
-    if (rc) return rc;
-    if (T > 0) {
-        bool okk = false;
-        switch (prec) {
-            case PREC_FP64: okk = go_sym_pr<PREC_FP64>(P, red, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_MIXED: okk = go_sym_pr<PREC_MIXED>(P, red, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_IEEE: okk = go_sym_pr<PREC_IEEE>(P, red, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_FP32: okk = go_sym_pr<PREC_FP32>(P, red, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            default: break;
-        }
-        if (!okk) return fail(CB_EINVAL, "launch_pair_sym: unsupported precision %d / p %d", prec, P);
-        if ((rc = check_launch("k_pair_sym"))) return rc;
-    }
-    const unsigned nb = (unsigned)((n + 63) / 64);
-    int lgJL = 0;
-    while ((1 << lgJL) < JL) ++lgJL;
-    switch (prec) {
-        case PREC_FP64: k_sym_finish<PREC_FP64><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
-        case PREC_MIXED: k_sym_finish<PREC_MIXED><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
-        case PREC_IEEE: k_sym_finish<PREC_IEEE><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
-        default: k_sym_finish<PREC_FP32><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
-    }
-    return check_launch("k_sym_finish");
+cb_status launch_pair(int prec, const LaunchCfg& c, bool force, bool pot, int n, const double* x,
+                      const double* y, const double* z, const double* q, double eps2, int jlen, double* part,
+                      double* ppot, hipStream_t st) {
+    return launch_pair_range(prec, c, force, pot, n, 0, n, x, y, z, q, eps2, jlen, part, ppot, st);
 }
 
 }  // namespace cb

@@ -103,15 +103,19 @@ __device__ __forceinline__ void pair_range(const IBlock<P>& ib, Acc<P, FORCE, PO
 
 // part: [S][3][n] force partials (FORCE), ppot: [S][n] potential partials
 // (POT); S = gridDim.y.  Workgroup = blockDim.x threads = blockDim.x/64 waves.
+// The i's are i0 .. i0 + ni - 1 (all n for a whole force evaluation); the
+// partial sums are indexed by i - i0: part[s][c][ni], ppot[s][ni].
 template <int PREC, int P, bool FORCE, bool POT>
-__global__ void __launch_bounds__(256) k_pair(int n, const double* __restrict__ x, const double* __restrict__ y,
-                                              const double* __restrict__ z, const double* __restrict__ q,
-                                              double eps2, int jlen, double* __restrict__ part,
-                                              double* __restrict__ ppot) {
+__global__ void __launch_bounds__(256) k_pair(int n, int i0, int ni, const double* __restrict__ x,
+                                              const double* __restrict__ y, const double* __restrict__ z,
+                                              const double* __restrict__ q, double eps2, int jlen,
+                                              double* __restrict__ part, double* __restrict__ ppot) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ibase = (blockIdx.x * (blockDim.x >> 6) + wave) * (64 * P);
-    if (ibase >= n) return;
+    const int rbase = (blockIdx.x * (blockDim.x >> 6) + wave) * (64 * P);  // relative to i0
+    if (rbase >= ni) return;
+    const int ibase = i0 + rbase;
+    const int iend = i0 + ni;
     const int s = blockIdx.y;
     const int j0 = s * jlen;
     const int j1 = min(n, j0 + jlen);
@@ -120,7 +124,7 @@ __global__ void __launch_bounds__(256) k_pair(int n, const double* __restrict__ 
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const int i = ibase + p * 64 + lane;
-        const int ic = min(i, n - 1);
+        const int ic = min(i, iend - 1);
         ib.i[p] = i;
         ib.x[p] = x[ic];
         ib.y[p] = y[ic];
@@ -137,13 +141,14 @@ __global__ void __launch_bounds__(256) k_pair(int n, const double* __restrict__ 
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const int i = ib.i[p];
-        if (i < n) {
+        if (i < iend) {
+            const int r = i - i0;
             if (FORCE) {
-                part[(size_t)(s * 3 + 0) * n + i] = tot.fx[p];
-                part[(size_t)(s * 3 + 1) * n + i] = tot.fy[p];
-                part[(size_t)(s * 3 + 2) * n + i] = tot.fz[p];
+                part[(size_t)(s * 3 + 0) * ni + r] = tot.fx[p];
+                part[(size_t)(s * 3 + 1) * ni + r] = tot.fy[p];
+                part[(size_t)(s * 3 + 2) * ni + r] = tot.fz[p];
             }
-            if (POT) ppot[(size_t)s * n + i] = tot.ph[p];
+            if (POT) ppot[(size_t)s * ni + r] = tot.ph[p];
         }
     }
 }

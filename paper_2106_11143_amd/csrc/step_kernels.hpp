@@ -77,9 +77,16 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
                 const double anz = Fz / mi - k.kz * z;
                 if (mode & EPI_KICK) {
                     const double h = 0.5 * P.dt;
-                    vx = vx + h * (ax + anx);
-                    vy = vy + h * (ay + any);
-                    vz = vz + h * (az + anz);
+                    if (P.trap.gamma == 0.0) {
+                        vx = vx + h * (ax + anx);
+                        vy = vy + h * (ay + any);
+                        vz = vz + h * (az + anz);
+                    } else {  // friction -g v by the trapezoidal rule, g = Gamma / m_i
+                        const double g = P.trap.gamma / mi, lo = 1.0 - g * h, hi = 1.0 + g * h;
+                        vx = (vx * lo + h * (ax + anx)) / hi;
+                        vy = (vy * lo + h * (ay + any)) / hi;
+                        vz = (vz * lo + h * (az + anz)) / hi;
+                    }
                     P.vx[i] = vx;
                     P.vy[i] = vy;
                     P.vz[i] = vz;
@@ -100,9 +107,16 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
             }
             if (mode & EPI_DRIFT) {
                 const double dt = P.dt, h2 = 0.5 * dt * dt;
-                x = x + vx * dt + h2 * ax;
-                y = y + vy * dt + h2 * ay;
-                z = z + vz * dt + h2 * az;
+                if (P.trap.gamma == 0.0) {
+                    x = x + vx * dt + h2 * ax;
+                    y = y + vy * dt + h2 * ay;
+                    z = z + vz * dt + h2 * az;
+                } else {  // the drift sees the friction acceleration -g v too
+                    const double g = P.trap.gamma / mi;
+                    x = x + vx * dt + h2 * (ax - g * vx);
+                    y = y + vy * dt + h2 * (ay - g * vy);
+                    z = z + vz * dt + h2 * (az - g * vz);
+                }
                 P.x[i] = x;
                 P.y[i] = y;
                 P.z[i] = z;

@@ -3,8 +3,9 @@ path; every force, energy, Hessian product and integration step runs in the
 HIP kernels, torch only supplies element-wise glue and the small dense
 algebra of Lanczos).
 
-- minimise: L-BFGS with Hessian-vector Newton step lengths (default) or FIRE
-  (Bitzek et al., PRL 97, 170201 (2006)), to the Coulomb crystal of a trap.
+- minimise: L-BFGS with Hessian-vector Newton step lengths (default), FIRE
+  (Bitzek et al., PRL 97, 170201 (2006)) or damped molecular dynamics (the
+  friction term), to the Coulomb crystal of a trap.
 - lanczos_lowest: block Lanczos with full reorthogonalisation on the
   mass-weighted Hessian M^-1/2 H M^-1/2 (eigenvalues = squared normal-mode
   angular frequencies), several vectors per HVP kernel pass.
@@ -48,15 +49,34 @@ def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, max_iter=100000, method="l
     method "lbfgs": limited-memory BFGS (two-loop recursion, `memory` pairs)
     whose step length along each direction p is the Newton step
     -(g.p)/(p.H p), with H p from the HVP kernel, capped at 0.2 ion spacings
-    per ion.  method "fire": FIRE.  Stops when max_i |F_i| <= ftol_rel *
-    k_C e^2 / a^2, a = (3 k_C e^2 / (m w_max^2))^(1/3).  Returns (r_min, info)."""
+    per ion.  method "fire": FIRE.  method "damped": damped molecular
+    dynamics, i.e. md_run with eq. (1)'s friction term, Gamma = 2 m w_min
+    (critical damping of the slowest trap axis), in chunks of steps (max_iter
+    counts steps).  Stops when max_i |F_i| <= ftol_rel * k_C e^2 / a^2,
+    a = (3 k_C e^2 / (m w_max^2))^(1/3).  Returns (r_min, info)."""
     r = r.clone()
     fscale, a, wmax = _force_scale(m, trap)
     minv = 1.0 / m.reshape(1, -1)
     tol = ftol_rel * fscale
     g = -total_force(r, q, m, trap, 0.0, eps2)
     it = 0
-    if method == "fire":
+    if method == "damped":
+        k = trap_k(trap, 0.0)
+        wmin = math.sqrt(min(k))
+        damped = dict(trap, gamma=2.0 * wmin * float(m.mean()))
+        dt = 0.05 / wmax
+        chunk = max(20, int(0.5 / (wmin * dt)))
+        st = [r[c].contiguous() for c in range(3)] + [torch.zeros_like(r[0]) for _ in range(6)]
+        first = True
+        while it < max_iter:
+            if float(g.norm(dim=0).max()) <= tol:
+                break
+            api.md_run(st, q, m, damped, 0.0, dt, chunk, eps2=eps2, init_accel=first)
+            first = False
+            it += chunk
+            r = torch.stack(st[:3])
+            g = -total_force(r, q, m, trap, 0.0, eps2)
+    elif method == "fire":
         v = torch.zeros_like(r)
         dt_max, dt = 0.2 / wmax, 0.05 / wmax
         alpha, n_pos = 0.1, 0

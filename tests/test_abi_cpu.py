@@ -90,6 +90,23 @@ def test_forces_argument_errors(api):
     assert "alias" in api.last_error()
 
 
+def test_forces_range_argument_errors(api):
+    L = api.lib()
+    P = C.c_void_p(1 << 21)
+    big = 1 << 40
+    for i0, i1 in ((-1, 5), (5, 5), (6, 5), (0, 11)):
+        assert L.coulomb_forces_range(10, i0, i1, P, P, P, P, 0.0, 0, P, P, P, _ws(), big, None) == api.CB_EINVAL
+        assert "i0" in api.last_error()
+    assert L.coulomb_forces_range(10, 0, 5, P, P, P, P, 0.0, 0, None, P, P, _ws(), big, None) == api.CB_EINVAL
+    assert L.coulomb_forces_range(10, 0, 5, P, P, P, P, 0.0, 0, P, P, P, _ws(), 100, None) == api.CB_ENOWS
+    # an output of i1 - i0 doubles inside an input array is rejected
+    x = C.c_void_p(1 << 22)
+    o = C.c_void_p((1 << 22) + 8 * 9)
+    o2, o3 = C.c_void_p(1 << 23), C.c_void_p(1 << 24)
+    assert L.coulomb_forces_range(10, 0, 2, x, P, P, P, 0.0, 0, o, o2, o3, _ws(), big, None) == api.CB_EINVAL
+    assert "alias" in api.last_error()
+
+
 def test_md_argument_errors(api):
     L = api.lib()
     big = 1 << 40
@@ -99,9 +116,16 @@ def test_md_argument_errors(api):
     tr = api.make_trap(dict(kind=0, wx=1e6, wy=1e6, wz=1e5))
     # dt <= 0
     assert L.md_step(10, C.byref(s), q, m, C.byref(tr), 0.0, 0.0, 0.0, 0, _ws(), big, None) == api.CB_EINVAL
-    # friction is not supported
-    tg = api.make_trap(dict(kind=0, wx=1e6, wy=1e6, wz=1e5, gamma=1e-20))
-    assert L.md_step(10, C.byref(s), q, m, C.byref(tg), 0.0, 1e-9, 0.0, 0, _ws(), big, None) == api.CB_EUNSUPPORTED
+    # negative friction
+    tg = api.make_trap(dict(kind=0, wx=1e6, wy=1e6, wz=1e5, gamma=-1e-20))
+    assert L.md_step(10, C.byref(s), q, m, C.byref(tg), 0.0, 1e-9, 0.0, 0, _ws(), big, None) == api.CB_EINVAL
+    assert "gamma" in api.last_error()
+    # the adjoint step is friction-free only
+    tf = api.make_trap(dict(kind=0, wx=1e6, wy=1e6, wz=1e5, gamma=1e-20))
+    lam, dl = C.c_void_p(1 << 31), C.c_void_p(1 << 32)
+    assert L.md_adjoint_step(10, arrs[0], arrs[1], arrs[2], q, m, C.byref(tf), 1e-9, 0.0, 0, 0, lam, dl, _ws(), big,
+                             None) == api.CB_EUNSUPPORTED
+    assert "friction" in api.last_error()
     # non-finite trap, bad kind
     tn = api.make_trap(dict(kind=0, wx=float("inf")))
     assert L.md_step(10, C.byref(s), q, m, C.byref(tn), 0.0, 1e-9, 0.0, 0, _ws(), big, None) == api.CB_EINVAL

@@ -124,3 +124,21 @@ def test_kz_ensemble_small(api):
     counts = [drivers.count_defects(got[0, offs[r]:offs[r + 1]], got[1, offs[r]:offs[r + 1]],
                                     got[2, offs[r]:offs[r + 1]]) for r in range(24)]
     print(f"[kz small] defect counts {counts}", flush=True)
+
+
+def test_batched_with_friction_matches_oracle_run_by_run(api, oracle):
+    """Runs with different friction coefficients (one of them zero) in one
+    batched launch, each against the oracle."""
+    from _gpu_util import dev
+    base = inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6)
+    traps = [dict(base, gamma=g * inputs.MASS_40U) for g in (0.0, 2e5, 1e6)]
+    sizes = [130, 64, 257]
+    parts, offs, q, m = _ensemble(sizes, 17, base)
+    st = np.concatenate(parts, axis=1)
+    ts = [dev(st[k]) for k in range(9)]
+    nsteps, every = 40, 10
+    en = api.md_run(ts, dev(q), dev(m), traps, 0.0, 2e-9, nsteps, offsets=offs, every=every).cpu().numpy()
+    got = np.stack([t.cpu().numpy() for t in ts])
+    for r in range(3):
+        sl = slice(offs[r], offs[r + 1])
+        _check_run(oracle, parts[r], q[sl], m[sl], traps[r], 2e-9, nsteps, got[:, sl], en[r], every, f"run {r}")

@@ -129,6 +129,46 @@ def test_forces_cloud100k_sampled(api, oracle):
         assert tot <= 1e-12 * np.linalg.norm(F, axis=0).sum()
 
 
+@pytest.mark.parametrize("n,i0,i1", [(1, 0, 1), (2, 1, 2), (4001, 0, 1), (4001, 37, 1000), (4001, 3900, 4001),
+                                     (4001, 0, 4001), (300, 64, 129)])
+def test_forces_range_ragged(api, oracle, n, i0, i1):
+    """coulomb_forces_range: the forces on ions i0 .. i1-1 from all n ions,
+    against the oracle on the same ions; ragged ranges, ranges that start
+    inside a wave, the whole range."""
+    from _gpu_util import dev, host, per_ion_rel
+    g = np.random.Generator(np.random.PCG64(3000 + n + i0))
+    d = dict(x=g.normal(0, 20e-6, n), y=g.normal(0, 20e-6, n), z=g.normal(0, 20e-6, n),
+             q=inputs.E_CHARGE * g.choice([1.0, 2.0, -1.0], n))
+    eps2 = (1e-7) ** 2 if i0 % 2 else 0.0
+    idx = np.arange(i0, i1)
+    ref = np.stack(oracle.forces(d["x"], d["y"], d["z"], d["q"], eps2=eps2, idx=idx))
+    for prec in ("fp64", "mixed"):
+        F = np.stack([host(t) for t in api.coulomb_forces_range(*(dev(d[k]) for k in "xyzq"), i0, i1, eps2=eps2,
+                                                                 prec=prec)])
+        assert F.shape == (3, i1 - i0)
+        if n == 1:
+            assert np.all(F == 0.0)
+            continue
+        err = per_ion_rel(F, ref)
+        assert err.max() <= (1e-12 if prec == "fp64" else 1e-7), (n, i0, i1, prec, err.max())
+
+
+def test_forces_range_one_gpu_share_of_cloud100k(api, oracle):
+    """One GPU's share when N = 1e5 is split by ion index over 8 GPUs: ions
+    37500 .. 49999 against all 1e5, sampled against the oracle."""
+    from _gpu_util import dev, host, per_ion_rel, report
+    d = inputs.cloud100k()
+    n = d["n"]
+    i0, i1 = 3 * n // 8, 4 * n // 8
+    F = np.stack([host(t) for t in api.coulomb_forces_range(*(dev(d[k]) for k in "xyzq"), i0, i1)])
+    g = np.random.Generator(np.random.PCG64(78))
+    rel = np.unique(np.concatenate([[0, 1, i1 - i0 - 1], g.choice(i1 - i0, 400, replace=False)]))
+    fx, fy, fz, kappa = oracle.forces(d["x"], d["y"], d["z"], d["q"], idx=i0 + rel, kappa=True)
+    err = per_ion_rel(F[:, rel], np.stack([fx, fy, fz]))
+    report("cloud100k share 3/8 (sampled)", err, kappa)
+    assert err.max() <= 1e-12
+
+
 def test_forces_are_deterministic(api):
     from _gpu_util import dev
     d = inputs.cloud1024(n=5000, seed=5)

@@ -148,3 +148,23 @@ def test_trajectory_gradient_matches_oracle_and_fd(api, oracle):
         fd = (loss(tp) - loss(tm)) / (2 * h)
         gc = g[0] if key == "wx" else g[2]
         assert gc == pytest.approx(fd, rel=1e-5)
+
+
+def test_damped_md_minimiser_reaches_the_lbfgs_chain(api):
+    """Damped molecular dynamics (md_run with the friction term) and L-BFGS
+    relax the same start to the same linear chain (a unique minimum)."""
+    from paper_2106_11143_amd import drivers
+    from _gpu_util import dev
+    n = 10
+    trap = inputs.pseudo_trap(5.0e6, 5.0e6, 0.2e6)
+    g = np.random.Generator(np.random.PCG64(4))
+    r0 = dev(g.normal(size=(3, n)) * np.array([1e-7, 1e-7, 20e-6])[:, None])
+    q, m = dev(np.full(n, E)), dev(np.full(n, M40))
+    ra, ia = drivers.minimise(r0, q, m, trap, ftol_rel=1e-10)
+    rb, ib = drivers.minimise(r0, q, m, trap, ftol_rel=1e-9, method="damped", max_iter=400000)
+    print(f"[minimise lbfgs] {ia}\n[minimise damped] {ib}", flush=True)
+    assert ib["fmax_rel"] <= 1e-9
+    za = np.sort(ra[2].cpu().numpy())
+    zb = np.sort(rb[2].cpu().numpy())
+    assert np.max(np.abs(za - zb)) <= 1e-7 * np.max(np.abs(za))
+    assert np.max(np.abs(rb[:2].cpu().numpy())) <= 1e-9 * np.max(np.abs(za))

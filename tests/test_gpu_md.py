@@ -150,3 +150,32 @@ def test_cloud100k_centre_of_mass_follows_harmonic_solution(api, prec):
         spread = np.abs(out[c]).max()
         assert abs(out[c].mean() - com) <= 1e-11 * spread, (c, out[c].mean(), com)
     assert api.poll_flags() == 0
+
+
+@pytest.mark.parametrize("n,every", [(1024, 1), (20000, 10)])
+def test_md_run_with_friction_matches_oracle(api, oracle, n, every):
+    """eq. (1)'s friction term (trapezoidal velocity-Verlet): the GPU run
+    against the oracle's, within the oracle's round-off envelope; n = 20000
+    takes the Newton's-third-law force stage."""
+    from _gpu_util import dev, state_host, state_tensors
+    d = inputs.cloud1024(n=n, seed=9)
+    st = inputs.state9(d)
+    w = inputs.TWO_PI * 0.2e6
+    trap = dict(d["trap"], gamma=0.05 * w * inputs.MASS_40U)
+    nsteps = 60 if n <= 1024 else 8
+    ref, en_ref, alt, en_alt = _oracle_envelope(oracle, st, d["q"], d["m"], trap, d["dt"], nsteps, every)
+    ts = state_tensors(st)
+    en = api.md_run(ts, dev(d["q"]), dev(d["m"]), trap, 0.0, d["dt"], nsteps, every=every)
+    got = state_host(ts)
+    for blk in (slice(0, 3), slice(3, 6), slice(6, 9)):
+        D = np.abs(alt[blk] - ref[blk]).max()
+        err = np.abs(got[blk] - ref[blk]).max()
+        assert err <= 10 * D + 1e-13 * np.abs(ref[blk]).max(), (n, blk, err, D)
+    en = en.cpu().numpy()[0]
+    assert np.all(np.abs(en - en_ref) <= 10 * np.abs(en_alt - en_ref) + 1e-12 * np.abs(en_ref).max(axis=0))
+    # the friction run loses kinetic energy against the friction-free one
+    ts0 = state_tensors(st)
+    api.md_run(ts0, dev(d["q"]), dev(d["m"]), d["trap"], 0.0, d["dt"], nsteps)
+    v_f = np.linalg.norm(got[3:6])
+    v_0 = np.linalg.norm(state_host(ts0)[3:6])
+    assert v_f < v_0
