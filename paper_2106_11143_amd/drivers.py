@@ -142,6 +142,39 @@ def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, max_iter=100000, method="l
     return r, info
 
 
+def _band_ritz(band, k):
+    """Lowest k eigenpairs of the symmetric banded matrix T given in lower
+    form, band[d, c] = T[c + d, c]: eigenvalues by the banded eigenvalue
+    solver, eigenvectors by inverse iteration with banded LU solves, each
+    re-orthogonalised against the earlier vectors of its cluster of equal
+    eigenvalues (exactly degenerate modes are common in symmetric traps).
+    Forming the banded solver's own eigenvectors would build the full
+    orthogonal matrix of its band reduction, which costs O(n^3)."""
+    from scipy.linalg import eigvals_banded, solve_banded
+
+    b, n = band.shape[0] - 1, band.shape[1]
+    theta = eigvals_banded(band, lower=True, select="i", select_range=(0, k - 1))
+    ab = np.zeros((2 * b + 1, n))  # the general banded form solve_banded takes: ab[b + i - j, j] = T[i, j]
+    for d in range(b + 1):
+        ab[b + d, :n - d] = band[d, :n - d]
+        ab[b - d, d:] = band[d, :n - d]
+    scale = float(np.abs(band).sum(axis=0).max())  # bound on |T|
+    rng = np.random.default_rng(0)
+    S = np.empty((n, k))
+    for i, th in enumerate(theta):
+        shifted = ab.copy()
+        shifted[b] -= th + 1e-14 * scale
+        cluster = [c for c in range(i) if abs(theta[c] - th) <= 1e-10 * scale]
+        x = rng.standard_normal(n)
+        for _ in range(3):
+            x = solve_banded((b, b), shifted, x)
+            for c in cluster:
+                x -= (S[:, c] @ x) * S[:, c]
+            x /= np.linalg.norm(x)
+        S[:, i] = x
+    return theta, S
+
+
 def lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=12000, eps2=0.0, seed=0, tol=1e-8, check_every=20,
                    hvp=None):
     """Lowest k eigenpairs of the mass-weighted Hessian M^-1/2 H M^-1/2 of
@@ -150,12 +183,11 @@ def lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=12000, eps2=0.0, seed=0,
     Block Lanczos (`block` vectors per HVP kernel pass) with full
     reorthogonalisation against a preallocated basis.  The projected matrix
     is block tridiagonal, i.e. banded with bandwidth `block`, so its lowest
-    Ritz pairs come from a banded symmetric eigensolver.  Stops when every
+    Ritz pairs come from banded solves (_band_ritz).  Stops when every
     wanted Ritz residual |A u - theta u| is below tol * theta_k, or when the
     basis reaches maxdim.  `hvp(V)` may replace the kernel call
     (V: (B, 3, n) -> H V).  Returns (eigenvalues (k,), vectors (k, 3, n) in
     mass-weighted coordinates, residual norms (k,), info)."""
-    from scipy.linalg import eig_banded
 
     n = r.shape[1]
     N3 = 3 * n
@@ -202,7 +234,7 @@ def lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=12000, eps2=0.0, seed=0,
         used = c1
         if (j + 1) % check_every == 0 or j == nblk - 1:
             kk = min(k, used)
-            theta, S = eig_banded(band[:, :used], lower=True, select="i", select_range=(0, kk - 1))
+            theta, S = _band_ritz(band[:, :used], kk)
             res = np.linalg.norm(Bh @ S[used - block:used, :], axis=0)
             if np.all(res <= tol * max(abs(theta[-1]), 1e-300)):
                 break

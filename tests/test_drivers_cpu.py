@@ -59,3 +59,38 @@ def test_block_lanczos_against_dense_eigensolver(oracle):
     V = vecs.numpy().reshape(6, -1)
     Av = np.stack([((H @ (v / sm)) / sm) for v in V])
     assert np.abs(Av - lam.numpy()[:, None] * V).max() <= 1e-8 * scale
+
+
+def test_block_lanczos_resolves_exactly_degenerate_modes():
+    """An operator whose every eigenvalue is doubly degenerate (two identical
+    decoupled copies, as the x/y modes of a cylindrically symmetric trap):
+    the Ritz values come in equal pairs and the Ritz vectors stay orthonormal
+    eigenvectors."""
+    import torch
+    from paper_2106_11143_amd import drivers
+
+    n = 20  # 3n = 60 = two copies of a 30-dimensional operator
+    g = np.random.Generator(np.random.PCG64(8))
+    lam0 = np.sort(g.uniform(1.0, 50.0, 30))
+    Q0 = np.linalg.qr(g.normal(size=(30, 30)))[0]
+    D = (Q0 * lam0) @ Q0.T
+    H = np.zeros((60, 60))
+    H[:30, :30] = D
+    H[30:, 30:] = D
+    P = np.linalg.qr(g.normal(size=(60, 60)))[0]  # hide the block structure
+    H = P @ H @ P.T
+
+    def hvp(V):
+        B = V.shape[0]
+        return torch.as_tensor((V.numpy().reshape(B, 60) @ H).reshape(B, 3, n))
+
+    r = torch.zeros(3, n, dtype=torch.float64)
+    ones = torch.ones(n, dtype=torch.float64)
+    lam, vecs, res, info = drivers.lanczos_lowest(r, ones, ones, {"kind": 0}, k=6, block=4, maxdim=60, hvp=hvp,
+                                                  check_every=3)
+    lam = lam.numpy()
+    ref = np.repeat(lam0[:3], 2)
+    assert np.abs(lam - ref).max() <= 1e-10 * lam0.max()
+    V = vecs.numpy().reshape(6, -1)
+    assert np.abs(V @ V.T - np.eye(6)).max() <= 1e-9
+    assert np.abs(V @ H - lam[:, None] * V).max() <= 1e-8 * lam0.max()

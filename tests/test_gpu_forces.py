@@ -169,6 +169,25 @@ def test_forces_range_one_gpu_share_of_cloud100k(api, oracle):
     assert err.max() <= 1e-12
 
 
+@pytest.mark.parametrize("n", [1 << 18, (1 << 18) + 1])
+def test_forces_at_the_symmetric_size_limit(api, oracle, n):
+    """The largest size the Newton's-third-law stage takes (2^18 ions, its
+    most tiles) and one more ion (the direct kernel takes over): sampled ions
+    against the oracle."""
+    from _gpu_util import dev, host, per_ion_rel, report
+    d = inputs.cloud100k(n=n, seed=31)
+    cfg = api.get_config("forces", n, "fp64")
+    assert cfg["algo"] == (2 if n <= (1 << 18) else 0)
+    F = np.stack([host(t) for t in api.coulomb_forces(*(dev(d[k]) for k in "xyzq"))])
+    g = np.random.Generator(np.random.PCG64(79))
+    idx = np.unique(np.concatenate([[0, 1, n - 2, n - 1], g.choice(n, 300, replace=False)]))
+    fx, fy, fz, kappa = oracle.forces(d["x"], d["y"], d["z"], d["q"], idx=idx, kappa=True)
+    err = per_ion_rel(F[:, idx], np.stack([fx, fy, fz]))
+    report(f"n={n} algo={cfg['algo']} (sampled)", err, kappa)
+    assert err.max() <= 1e-12
+    api.clear_workspace_cache()
+
+
 def test_forces_are_deterministic(api):
     from _gpu_util import dev
     d = inputs.cloud1024(n=5000, seed=5)
