@@ -480,13 +480,17 @@ def bench_crystal(args):
         from oracle import oracle as O
 
         rc = r.cpu().numpy()
-        v1 = np.random.Generator(np.random.PCG64(2)).normal(size=(3, n))
+        v8 = np.random.Generator(np.random.PCG64(2)).normal(size=(8, 3, n))
         t0 = time.perf_counter()
-        O.hvp(rc[0], rc[1], rc[2], d["q"], v1, m=d["m"], trap=trap)
+        passes = 0
+        while passes == 0 or time.perf_counter() - t0 < 3.0:
+            O.hvp(rc[0], rc[1], rc[2], d["q"], v8, m=d["m"], trap=trap)
+            passes += 1
         t = time.perf_counter() - t0
-        extra["cpu_baseline"] = {"value": float(n) * n / t, "unit": "pairs*vectors/s",
+        extra["cpu_baseline"] = {"value": float(n) * n * 8 * passes / t, "unit": "pairs*vectors/s",
                                  "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
-                                 "sample": f"oracle exact HVP (compensated), 1 vector at N={n}, {t:.1f} s"}
+                                 "sample": f"oracle exact HVP (compensated), 8 vectors at N={n}, {passes} pass(es), "
+                                           f"{t:.1f} s"}
     return _line("HVP pair-vector interactions/s (FP64, 8 vectors per pass)", float(n) * n * 8 / (ms_hvp * 1e-3),
                  "pairs*vectors/s", 10, 1, ms_hvp,
                  "crystal8192: N=8192 minimised crystal, 2pi(1,1,0.05) MHz; Lanczos 32 lowest; 2000-step adjoint "

@@ -110,6 +110,13 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
     cb_status rc;
     const bool rec0 = energies && every > 0;
     const bool init = (flags & CB_INIT_ACCEL) != 0;
+    // arrival counter of the epilogue's final energy sum: after the block
+    // partials (whose region has room for it), zeroed once here
+    E.ecount = reinterpret_cast<unsigned*>(eblk + 3 * ((size_t)n / kEpiBlock + 1));
+    if (rec0) {
+        k_zero_u32<<<1, 1, 0, st>>>(E.ecount);
+        if ((rc = check_launch("k_zero_u32"))) return rc;
+    }
 
     bool prescaled_now = false;
     // Force (and potential) pair launch: the potential needs the direct kernel;
@@ -135,25 +142,19 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
     E.step = 0;
     E.mode = (init ? EPI_ACCEL : 0u) | (rec0 ? EPI_ENERGY : 0u) | (nsteps > 0 ? EPI_DRIFT : 0u);
     if (prescaled_now) E.mode |= EPI_PRESCALED;
+    E.efinal = rec0 ? energies : nullptr;
     if (E.mode) {
         k_epilogue<<<nb, kEpiThreads, 0, st>>>(E);
         if ((rc = check_launch("k_epilogue"))) return rc;
-    }
-    if (rec0) {
-        k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, eblk, energies, 0);
-        if ((rc = check_launch("k_energy_final"))) return rc;
     }
     for (int64_t k = 1; k <= nsteps; ++k) {
         const bool rec = rec0 && (k % every == 0);
         if ((rc = pairs(true, rec))) return rc;
         E.step = k;
         E.mode = EPI_KICK | (rec ? EPI_ENERGY : 0u) | (k < nsteps ? EPI_DRIFT : 0u) | (prescaled_now ? EPI_PRESCALED : 0u);
+        E.efinal = rec ? energies + 4 * (k / every) : nullptr;
         k_epilogue<<<nb, kEpiThreads, 0, st>>>(E);
         if ((rc = check_launch("k_epilogue"))) return rc;
-        if (rec) {
-            k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, eblk, energies + 4 * (k / every), 0);
-            if ((rc = check_launch("k_energy_final"))) return rc;
-        }
     }
     return ok();
 }

@@ -26,7 +26,6 @@ static bool go_hvp_nv(int nv, dim3 g, dim3 b, hipStream_t st, int n, const doubl
         case 1: go_hvp<PREC, P, 1>(g, b, st, n, x, y, z, q, v, eps2, jlen, part); return true;
         case 2: go_hvp<PREC, P, 2>(g, b, st, n, x, y, z, q, v, eps2, jlen, part); return true;
         case 4: go_hvp<PREC, P, 4>(g, b, st, n, x, y, z, q, v, eps2, jlen, part); return true;
-        case 8: go_hvp<PREC, P, 8>(g, b, st, n, x, y, z, q, v, eps2, jlen, part); return true;
         default: return false;
     }
 }
@@ -229,10 +228,10 @@ cb_status coulomb_hvp(int64_t n, const double* x, const double* y, const double*
     const int S = n_splits(n, jlen);
     const TrapK k = m ? host_trap_k(*trap, t) : TrapK{0.0, 0.0, 0.0};
     double* part = at(ws, L.part);
-    // vectors in chunks of 8, 4, 2, 1
+    // vectors in passes of 4, 2, 1 (eight per pass need too many registers)
     for (int b0 = 0; b0 < nvec;) {
         const int left = nvec - b0;
-        const int nv = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+        const int nv = left >= 4 ? 4 : left >= 2 ? 2 : 1;
         const double* vb0 = v + (size_t)b0 * 3 * n;
         if ((rc = launch_hvp(prec, cfg, nv, (int)n, x, y, z, q, vb0, eps2, jlen, part, st))) return rc;
         k_hvp_epi<<<(int)((n + kEpiThreads - 1) / kEpiThreads), kEpiThreads, 0, st>>>(

@@ -32,7 +32,15 @@ struct EpiParams {
     unsigned mode;
     double* eblk;  // [gridDim.x][3]
     unsigned* flags;
+    // With EPI_ENERGY and efinal set, the last block to finish sums the block
+    // partials (in block order, so the result does not depend on timing)
+    // into efinal: K, U_C, U_trap, E (U_C alone with EPI_UC_ONLY).  ecount
+    // is zero at launch and is left zero.
+    double* efinal;
+    unsigned* ecount;
 };
+
+__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 
 __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
     const int i = blockIdx.x * kEpiThreads + threadIdx.x;
@@ -131,6 +139,35 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
             P.eblk[blockIdx.x * 3 + 0] = eK;
             P.eblk[blockIdx.x * 3 + 1] = eC;
             P.eblk[blockIdx.x * 3 + 2] = eT;
+        }
+        if (P.efinal) {
+            __shared__ int last;
+            if (threadIdx.x == 0) {
+                __threadfence();  // this block's partials before its arrival
+                last = atomicAdd(P.ecount, 1u) == gridDim.x - 1;
+            }
+            __syncthreads();
+            if (last) {
+                __threadfence();  // every block's partials are visible
+                double a = 0.0, b = 0.0, c = 0.0;
+                for (int k = threadIdx.x; k < (int)gridDim.x; k += kEpiThreads) {
+                    a += P.eblk[k * 3 + 0];
+                    b += P.eblk[k * 3 + 1];
+                    c += P.eblk[k * 3 + 2];
+                }
+                block_sum3(a, b, c);
+                if (threadIdx.x == 0) {
+                    if (mode & EPI_UC_ONLY) {
+                        P.efinal[0] = b;
+                    } else {
+                        P.efinal[0] = a;
+                        P.efinal[1] = b;
+                        P.efinal[2] = c;
+                        P.efinal[3] = a + b + c;
+                    }
+                    *P.ecount = 0u;
+                }
+            }
         }
     }
 }
