@@ -21,11 +21,24 @@
 #include "internal.hpp"
 #include "rsqrt.hpp"
 #include "step_common.hpp"
+#include "wave_reduce.hpp"
 
 namespace cb {
 
 constexpr int kBatchWG = 512;
 constexpr int kBatchP = 4;
+
+// Newton's-third-law pass for the largest runs (the ones that bound the
+// launch's makespan): blocks of kSymBS ions (one wave, kSymBP per lane), every
+// unordered pair of blocks once in a round-robin schedule in which the eight
+// waves hold disjoint pairs of blocks, so each block's force accumulator is
+// touched by one wave per round.  The accumulators (force / k_C, [3][4096] per
+// workgroup) live in the workspace and stay in L2.  Runs of at most
+// kSymBatchMin ions (fewer than 13 blocks would leave waves idle) and
+// energy-recording steps take the direct pass.
+constexpr int kSymBP = 4;
+constexpr int kSymBS = 64 * kSymBP;
+constexpr int kSymBatchMin = 3072;
 
 struct BatchParams {
     int nrun;
@@ -41,6 +54,7 @@ struct BatchParams {
     int init;
     double* energies;  // [nrun][nsteps/every+1][4] or null
     unsigned* flags;
+    double* facc;  // [gridDim.x][3][kMaxBatchIons]: force / k_C of the Newton's-third-law pass
 };
 
 template <int PREC, bool POT>
@@ -92,6 +106,143 @@ __device__ __forceinline__ void batch_pairs(const double4* __restrict__ sh, int 
             fz[p] += az[p];
             if (POT) ph[p] += ap[p];
         }
+    }
+}
+
+// Round r of the circle method over Bp (even) blocks: slot k pairs (a, b).
+__device__ __forceinline__ void rr_pair(int Bp, int r, int k, int& a, int& b) {
+    if (k == 0) {
+        a = r;
+        b = Bp - 1;
+    } else {
+        a = (r + k) % (Bp - 1);
+        b = (r - k + Bp - 1) % (Bp - 1);
+    }
+}
+
+// Pairs between block I (i's, one per lane and slot) and block J > I (j's):
+// i sums into F[I] (q_i q_j d r^-3), reactions -q_j sum_i q_i d r^-3 into F[J].
+// F is [3][kMaxBatchIons].  Block I is full; J may be the run's ragged last.
+template <int PREC>
+__device__ __forceinline__ void sym_block_pair(const double4* __restrict__ sh, int n, int I, int J, double eps2,
+                                               const SeriesK& K, double* __restrict__ F) {
+    const int lane = threadIdx.x & 63;
+    double xi[kSymBP], yi[kSymBP], zi[kSymBP], qi[kSymBP], ia[kSymBP][3];
+#pragma unroll
+    for (int p = 0; p < kSymBP; ++p) {
+        const double4 r = sh[I * kSymBS + p * 64 + lane];
+        xi[p] = r.x;
+        yi[p] = r.y;
+        zi[p] = r.z;
+        qi[p] = r.w;
+        ia[p][0] = ia[p][1] = ia[p][2] = 0.0;
+    }
+    const int j0 = J * kSymBS, j1 = min(n, j0 + kSymBS);
+    for (int jg = j0; jg < j1; jg += 4) {
+        const int live = min(4, j1 - jg);
+        double jv[12];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double4 rj = sh[jg + min(u, live - 1)];
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+            for (int p = 0; p < kSymBP; ++p) {
+                const double dx = xi[p] - rj.x, dy = yi[p] - rj.y, dz = zi[p] - rj.z;
+                const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
+                double s, y;
+                inv_r<PREC, true, false>(r2, qi[p], K, s, y);  // q_i r^-3
+                if (u >= live) s = 0.0;
+                const double sq = s * rj.w;
+                ia[p][0] = __builtin_fma(dx, sq, ia[p][0]);
+                ia[p][1] = __builtin_fma(dy, sq, ia[p][1]);
+                ia[p][2] = __builtin_fma(dz, sq, ia[p][2]);
+                a0 = __builtin_fma(dx, s, a0);
+                a1 = __builtin_fma(dy, s, a1);
+                a2 = __builtin_fma(dz, s, a2);
+            }
+            jv[3 * u + 0] = a0;
+            jv[3 * u + 1] = a1;
+            jv[3 * u + 2] = a2;
+        }
+        // keep the i-sum updates ahead of the reduction (register pressure)
+#pragma unroll
+        for (int p = 0; p < kSymBP; ++p) asm volatile("" : "+v"(ia[p][0]), "+v"(ia[p][1]), "+v"(ia[p][2]));
+        double o[3];
+        reduce_scatter12(jv, o);
+        const int g = lane >> 4, c = lane & 15;
+        if (g < live && c < 3) {
+            const int j = jg + g;
+            F[c * kMaxBatchIons + j] -= sh[j].w * ((c == 0) ? o[0] : ((c == 1) ? o[1] : o[2]));
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < kSymBP; ++p) {
+        const int i = I * kSymBS + p * 64 + lane;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) F[c * kMaxBatchIons + i] += ia[p][c];
+    }
+}
+
+// Pairs inside block I (each ordered pair, the self pair masked): into F[I].
+template <int PREC>
+__device__ __forceinline__ void sym_block_diag(const double4* __restrict__ sh, int n, int I, double eps2,
+                                               const SeriesK& K, double* __restrict__ F) {
+    const int lane = threadIdx.x & 63;
+    const int b0 = I * kSymBS, b1 = min(n, b0 + kSymBS);
+    double xi[kSymBP], yi[kSymBP], zi[kSymBP], acc[kSymBP][3];
+    int ii[kSymBP];
+#pragma unroll
+    for (int p = 0; p < kSymBP; ++p) {
+        ii[p] = b0 + p * 64 + lane;
+        const double4 r = sh[min(ii[p], b1 - 1)];
+        xi[p] = r.x;
+        yi[p] = r.y;
+        zi[p] = r.z;
+        acc[p][0] = acc[p][1] = acc[p][2] = 0.0;
+    }
+    for (int j = b0; j < b1; ++j) {
+        const double4 rj = sh[j];
+#pragma unroll
+        for (int p = 0; p < kSymBP; ++p) {
+            const double dx = xi[p] - rj.x, dy = yi[p] - rj.y, dz = zi[p] - rj.z;
+            const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
+            double s, y;
+            inv_r<PREC, true, false>(r2, rj.w, K, s, y);  // q_j r^-3
+            if (ii[p] == j) s = 0.0;
+            acc[p][0] = __builtin_fma(dx, s, acc[p][0]);
+            acc[p][1] = __builtin_fma(dy, s, acc[p][1]);
+            acc[p][2] = __builtin_fma(dz, s, acc[p][2]);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < kSymBP; ++p)
+        if (ii[p] < b1) {
+            const double qi = sh[ii[p]].w;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) F[c * kMaxBatchIons + ii[p]] += qi * acc[p][c];
+        }
+}
+
+// Forces / k_C of every ion of the run into F, Newton's third law.  Called by
+// the whole workgroup; every thread reaches every barrier.
+template <int PREC>
+__device__ void sym_run_forces(const double4* __restrict__ sh, int n, double eps2, const SeriesK& K,
+                               double* __restrict__ F) {
+    const int tid = threadIdx.x, w = tid >> 6;
+    constexpr int kWaves = kBatchWG / 64;
+    const int B = (n + kSymBS - 1) / kSymBS;  // <= 16
+    const int Bp = B + (B & 1);
+    for (int i = tid; i < n; i += kBatchWG) F[i] = F[kMaxBatchIons + i] = F[2 * kMaxBatchIons + i] = 0.0;
+    __syncthreads();
+    for (int I = w; I < B; I += kWaves) sym_block_diag<PREC>(sh, n, I, eps2, K, F);
+    __syncthreads();
+    for (int r = 0; r < Bp - 1; ++r) {
+        if (w < Bp / 2) {
+            int a, b;
+            rr_pair(Bp, r, w, a, b);
+            if (a < B && b < B) sym_block_pair<PREC>(sh, n, min(a, b), max(a, b), eps2, K, F);
+        }
+        __syncthreads();
     }
 }
 
@@ -215,13 +366,13 @@ __global__ void __launch_bounds__(kBatchWG) k_batched(BatchParams B) {
             const TrapK k = trap_k(tr, step_time(B.t0, dt, s));
             const bool rec = Erun && (s % B.every == 0);
             double eK = 0.0, eC = 0.0, eT = 0.0;
-            auto op = [&](int i, double fx, double fy, double fz, double ph) {
-                const double c = kCoulomb * Q[i];
+            // kick of ion i with its Coulomb force (Fx, Fy, Fz)
+            auto kick = [&](int i, double Fx, double Fy, double Fz) {
                 const double mi = M[i];
                 const double4 r = sh[i];
-                const double anx = c * fx / mi - k.kx * r.x;
-                const double any = c * fy / mi - k.ky * r.y;
-                const double anz = c * fz / mi - k.kz * r.z;
+                const double anx = Fx / mi - k.kx * r.x;
+                const double any = Fy / mi - k.ky * r.y;
+                const double anz = Fz / mi - k.kz * r.z;
                 double vx, vy, vz;
                 if (Gam == 0.0) {
                     vx = VX[i] + hdt * (AX[i] + anx);
@@ -242,12 +393,24 @@ __global__ void __launch_bounds__(kBatchWG) k_batched(BatchParams B) {
                 bad |= !(__builtin_isfinite(anx) && __builtin_isfinite(any) && __builtin_isfinite(anz));
                 if (rec) {
                     eK += 0.5 * mi * (vx * vx + vy * vy + vz * vz);
-                    eC += 0.5 * c * ph;
                     eT += 0.5 * mi * (k.kx * r.x * r.x + k.ky * r.y * r.y + k.kz * r.z * r.z);
                 }
             };
-            if (rec) for_groups<PREC, true>(sh, n, eps2, K, op);
-            else for_groups<PREC, false>(sh, n, eps2, K, op);
+            auto op = [&](int i, double fx, double fy, double fz, double ph) {
+                const double c = kCoulomb * Q[i];
+                kick(i, c * fx, c * fy, c * fz);
+                if (rec) eC += 0.5 * c * ph;
+            };
+            if (rec) {
+                for_groups<PREC, true>(sh, n, eps2, K, op);
+            } else if (n > kSymBatchMin) {
+                double* F = B.facc + (size_t)blockIdx.x * 3 * kMaxBatchIons;
+                sym_run_forces<PREC>(sh, n, eps2, K, F);
+                for (int i = tid; i < n; i += kBatchWG)
+                    kick(i, kCoulomb * F[i], kCoulomb * F[kMaxBatchIons + i], kCoulomb * F[2 * kMaxBatchIons + i]);
+            } else {
+                for_groups<PREC, false>(sh, n, eps2, K, op);
+            }
             if (rec) {
                 block_sum3_wg(eK, eC, eT, red);
                 if (tid == 0) {
@@ -334,13 +497,14 @@ cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s
     B.init = (flags & CB_INIT_ACCEL) ? 1 : 0;
     B.energies = energies;
     B.flags = fl;
+    B.facc = reinterpret_cast<double*>(static_cast<char*>(ws) + L.aux);
 
     const size_t lds = sizeof(double4) * (size_t)nmax + sizeof(double) * 3 * kBatchWG;
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return fail(CB_EHIP, "md_run: device query failed");
     const int per_cu = std::max(1, (int)((160 * 1024) / lds));
-    const int grid = std::min(nrun, ncu * std::min(per_cu, 2));
+    const int grid = std::min(std::min(nrun, ncu * std::min(per_cu, 2)), kBatchGridMax);
     auto launch = [&](auto kern) -> cb_status {
         if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds) != hipSuccess)

@@ -174,6 +174,8 @@ WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec) {
     } else {
         L.batch = off;
         off += al((sizeof(int64_t) * 2 + sizeof(cb_trap) + sizeof(int)) * (size_t)nrun + 64);
+        L.aux = off;  // force accumulators of the batched kernel's Newton's-third-law pass
+        off += al(sizeof(double) * 3 * (size_t)kMaxBatchIons * (size_t)std::min<int32_t>(nrun, kBatchGridMax));
     }
     L.total = off + 256;
     return L;

@@ -12,6 +12,7 @@ namespace cb {
 constexpr int kMaxSplits = 64;       // j-splits per launch
 constexpr int kMaxVec = 8;           // HVP vectors per call
 constexpr int kMaxBatchIons = 4096;  // ions per run in the batched kernel (LDS bound)
+constexpr int kBatchGridMax = 2048;  // workgroups of one batched launch (force accumulator slots)
 constexpr int kEpiBlock = 256;       // threads per element-wise block
 constexpr int64_t kSymMaxN = int64_t(1) << 18;  // largest n for the symmetric kernel (partials grow as n^2)
 
