@@ -47,10 +47,17 @@ STAGE_KERNELS = {
 
 
 def kernel_hash() -> str:
+    """Hash of the force stage's source code, comments and whitespace removed
+    (a comment edit leaves the committed counter summary valid)."""
+    import re
+
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update(re.sub(r"\s+", " ", src).strip().encode())
     return h.hexdigest()[:16]
 
 

@@ -9,9 +9,9 @@
 // SGPRs) each lane evaluates its P pairs once and
 //   - adds q_i q_j d y^3 to its own i accumulators (force on i, up to k_C);
 //   - adds q_i d y^3 over its P ions into a per-j value; after a group of
-//     4 j's the 12 per-j values are summed over the wave by a reduce-scatter
-//     (wave_reduce.hpp), giving the reaction on those j (up to -k_C q_j),
-//     which one lane per value stores.
+//     4 j's the 12 per-j values are summed over the wave (wave_reduce.hpp:
+//     cross-lane permutes and DPP, or an LDS transpose), giving the reaction
+//     on those j (up to -k_C q_j), which one lane per value stores.
 // The tile writes its i sums to Pi[tile][3][IB] and its reactions to
 // R[tile][3][JL]; nothing is accumulated across workgroups, so results are
 // deterministic.  The diagonal i-block (pairs inside one block) is evaluated
