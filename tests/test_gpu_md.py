@@ -179,3 +179,37 @@ def test_md_run_with_friction_matches_oracle(api, oracle, n, every):
     v_f = np.linalg.norm(got[3:6])
     v_0 = np.linalg.norm(state_host(ts0)[3:6])
     assert v_f < v_0
+
+
+def test_md_run_captured_in_a_hip_graph_replays_bitwise(api):
+    """The single-run md_run enqueues kernels only (no memset, no host sync),
+    so a caller can capture it in a HIP graph: every replay, with eager work
+    in between, equals the eager run bitwise (state and energy records)."""
+    import torch
+    from _gpu_util import dev, state_tensors
+    d = inputs.cloud1024()
+    st = inputs.state9(d)
+    q, m = dev(d["q"]), dev(d["m"])
+    nsteps = 40
+    eager = state_tensors(st)
+    en_eager = api.md_run(eager, q, m, d["trap"], 0.0, d["dt"], nsteps, every=1).clone()
+    ref = torch.stack(eager)
+    static = state_tensors(st)
+    api.md_run(static, q, m, d["trap"], 0.0, d["dt"], 2, every=1)  # warm-up: workspace, library state
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s0 = torch.stack(state_tensors(st))
+    for k in range(9):
+        static[k].copy_(s0[k])
+    with torch.cuda.graph(g):
+        en_static = api.md_run(static, q, m, d["trap"], 0.0, d["dt"], nsteps, every=1)
+    for rep in range(3):
+        for k in range(9):
+            static[k].copy_(s0[k])
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(torch.stack(static), ref), rep
+        assert torch.equal(en_static, en_eager), rep
+        other = state_tensors(st)  # eager work between replays
+        api.md_run(other, q, m, d["trap"], 0.0, d["dt"], 5)
+        torch.cuda.synchronize()
