@@ -514,7 +514,8 @@ def bench_rsqrt_sweep(args):
     from oracle import oracle as O
 
     variants = {"ieee": "SQRT+DIV (IEEE sqrt, division)", "fp64": "FP32 seed + 2nd-order refinement",
-                "mixed": "FP32 seed + one Newton step", "fp32": "FP32 seed only"}
+                "mixed": "FP32 seed + one Newton step", "fp32": "FP32 seed only",
+                "mixed_f32d": "ablation: one Newton step on FP32-rounded displacements (direct kernel)"}
     sizes = [1024, 4096, 16384, 32768, 65536, 100000]
     rows = []
     for n in sizes:

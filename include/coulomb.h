@@ -65,9 +65,10 @@ typedef enum {
 
 /* How 1/sqrt(r^2 + eps2) is evaluated (paper, sections 2 and 4: the cost and
  * accuracy of the inverse square root decide the speed of the pair loop).
- *  CB_FP64      hardware FP64 reciprocal-square-root estimate refined by
- *               Newton-Raphson steps y <- y (3 - x y^2)/2 (section 4) to full
- *               double precision; FP64 throughout.  The default.
+ *  CB_FP64      FP32 hardware estimate of the FP32-rounded r^2, refined to
+ *               full double precision by a second-order correction of
+ *               q r^-3 (one order beyond the Newton-Raphson step of
+ *               section 4); FP64 throughout.  The default.
  *  CB_MIXED     FP32 hardware estimate of the FP32-rounded r^2 followed by ONE
  *               FP64 Newton-Raphson step on the FP64 r^2 (the analogue of the
  *               paper's "RSQRT14 + 1 N-W"); displacements, r^2, the force
@@ -77,8 +78,20 @@ typedef enum {
  *  CB_FP64_IEEE one correctly rounded square root and one correctly rounded
  *               division (the paper's "SQRT+DIV"); the slow reference.
  *  CB_FP32_RSQ  the FP32 hardware estimate alone, no refinement (the
- *               analogue of the paper's lowest-accuracy "RSQRT14"). */
-typedef enum { CB_FP64 = 0, CB_MIXED = 1, CB_FP64_IEEE = 2, CB_FP32_RSQ = 3 } cb_precision;
+ *               analogue of the paper's lowest-accuracy "RSQRT14").
+ *  CB_MIXED_F32D  ablation of CB_MIXED: as CB_MIXED, but each displacement
+ *               is rounded to FP32 and used so in r^2 and in the force
+ *               numerator (the literal "FP32 displacement" reading of the
+ *               mixed path; relative force error about 2^-24 per pair).
+ *               coulomb_forces and coulomb_forces_range only (the direct
+ *               kernel); other entry points return CB_EUNSUPPORTED. */
+typedef enum {
+    CB_FP64 = 0,
+    CB_MIXED = 1,
+    CB_FP64_IEEE = 2,
+    CB_FP32_RSQ = 3,
+    CB_MIXED_F32D = 4
+} cb_precision;
 
 /* Operation codes for cb_workspace_size / cb_autotune. */
 typedef enum { CB_OP_FORCES = 0, CB_OP_ENERGY = 1, CB_OP_MD_STEP = 2, CB_OP_MD_RUN = 3,

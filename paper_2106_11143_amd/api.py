@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libcoulomb_mi355x.so")
 
 CB_OK, CB_EINVAL, CB_EHIP, CB_ENOWS, CB_ENONFINITE, CB_EUNSUPPORTED = range(6)
 STATUS_NAMES = {0: "CB_OK", 1: "CB_EINVAL", 2: "CB_EHIP", 3: "CB_ENOWS", 4: "CB_ENONFINITE", 5: "CB_EUNSUPPORTED"}
-PRECISIONS = {"fp64": 0, "mixed": 1, "ieee": 2, "fp32": 3}
+PRECISIONS = {"fp64": 0, "mixed": 1, "ieee": 2, "fp32": 3, "mixed_f32d": 4}
 OPS = {"forces": 0, "energy": 1, "md_step": 2, "md_run": 3, "hvp": 4, "adjoint": 5}
 CB_INIT_ACCEL = 1
 CB_ADJ_FINAL = 1

@@ -60,6 +60,7 @@ using namespace cb;
 extern "C" {
 
 cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_path) {
+    if (prec == CB_MIXED_F32D) return fail(CB_EUNSUPPORTED, "cb_autotune: CB_MIXED_F32D is an ablation, not tuned");
     if (op < 0 || op > CB_OP_ADJOINT || n < 2 || n > (int64_t(1) << 26) || prec < CB_FP64 || prec > CB_FP32_RSQ)
         return fail(CB_EINVAL, "cb_autotune: bad argument");
     const bool hv = (op == CB_OP_HVP || op == CB_OP_ADJOINT);

@@ -214,7 +214,7 @@ extern "C" {
 const char* cb_last_error(void) { return t_err.c_str(); }
 
 size_t cb_workspace_size(int32_t op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec) {
-    if (n < 1 || op < 0 || op > CB_OP_ADJOINT || prec < 0 || prec > CB_FP32_RSQ) return 0;
+    if (n < 1 || op < 0 || op > CB_OP_ADJOINT || prec < 0 || prec > CB_MIXED_F32D) return 0;
     if (op == CB_OP_HVP && (nvec < 1 || nvec > kMaxVec)) return 0;
     return ws_layout(op, n, nrun, nvec).total;
 }

@@ -23,7 +23,7 @@ static bool overlaps(const void* a, const void* b, int64_t n) {
 static cb_status check_common(const char* who, int64_t n, int32_t prec, double eps2, void* ws, size_t ws_bytes,
                               size_t need) {
     if (n < 1 || n > (int64_t(1) << 28)) return fail(CB_EINVAL, "%s: n = %lld out of range [1, 2^28]", who, (long long)n);
-    if (prec < CB_FP64 || prec > CB_FP32_RSQ) return fail(CB_EINVAL, "%s: unknown precision %d", who, prec);
+    if (prec < CB_FP64 || prec > CB_MIXED_F32D) return fail(CB_EINVAL, "%s: unknown precision %d", who, prec);
     if (!(eps2 >= 0.0) || !std::isfinite(eps2)) return fail(CB_EINVAL, "%s: eps2 must be finite and >= 0", who);
     if (!ws) return fail(CB_EINVAL, "%s: workspace is NULL", who);
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(CB_EINVAL, "%s: workspace not 256-byte aligned", who);
@@ -67,7 +67,7 @@ static cb_status force_stage(int op, int prec, int64_t n, const double* x, const
                              bool* prescaled) {
     const LaunchCfg cfg = get_cfg(op, n, prec);
     double* part = at(ws, L.part);
-    if (is_sym(cfg.algo) && n <= kSymMaxN) {
+    if (is_sym(cfg.algo) && n <= kSymMaxN && prec != CB_MIXED_F32D) {
         *S_out = 1;
         *prescaled = true;
         void* scratch = static_cast<char*>(ws) + L.part + al256(sizeof(double) * 3 * (size_t)n);
@@ -294,6 +294,7 @@ cb_status coulomb_energy(int64_t n, const double* x, const double* y, const doub
     const WsLayout L = ws_layout(CB_OP_ENERGY, n > 0 ? n : 1, 1, 1);
     cb_status rc = check_common("coulomb_energy", n, prec, eps2, ws, ws_bytes, L.total);
     if (rc) return rc;
+    if (prec == CB_MIXED_F32D) return fail(CB_EUNSUPPORTED, "coulomb_energy: CB_MIXED_F32D is for the forces only");
     if (!x || !y || !z || !q || !u_out) return fail(CB_EINVAL, "coulomb_energy: NULL argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const PairRun pr = plan(CB_OP_ENERGY, n, prec);
@@ -323,6 +324,7 @@ cb_status md_step(int64_t n, const cb_state* s, const double* q, const double* m
     const WsLayout L = ws_layout(CB_OP_MD_STEP, n > 0 ? n : 1, 1, 1);
     cb_status rc = check_common("md_step", n, prec, eps2, ws, ws_bytes, L.total);
     if (rc) return rc;
+    if (prec == CB_MIXED_F32D) return fail(CB_EUNSUPPORTED, "md_step: CB_MIXED_F32D is for the forces only");
     if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t)) return fail(CB_EINVAL, "md_step: need finite t and dt > 0");
     if (!trap_ok(trap, "md_step", &rc)) return rc;
     if (!state_ok(s, n, q, m, "md_step", &rc)) return rc;
@@ -341,6 +343,7 @@ cb_status md_run(int32_t nrun, const int64_t* offsets, const cb_state* s, const 
     const WsLayout L = ws_layout(CB_OP_MD_RUN, n, nrun, 1);
     cb_status rc = check_common("md_run", n, prec, eps2, ws, ws_bytes, L.total);
     if (rc) return rc;
+    if (prec == CB_MIXED_F32D) return fail(CB_EUNSUPPORTED, "md_run: CB_MIXED_F32D is for the forces only");
     if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t0)) return fail(CB_EINVAL, "md_run: need finite t0 and dt > 0");
     if (nsteps < 0) return fail(CB_EINVAL, "md_run: nsteps < 0");
     if (energies && every < 1) return fail(CB_EINVAL, "md_run: every must be >= 1 when energies are requested");

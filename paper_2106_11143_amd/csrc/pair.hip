@@ -55,6 +55,7 @@ cb_status launch_pair_range(int prec, const LaunchCfg& c, bool force, bool pot, 
         case PREC_MIXED: okk = go_p<PREC_MIXED>(c.p, force, pot, grid, block, st, a); break;
         case PREC_IEEE: okk = go_p<PREC_IEEE>(c.p, force, pot, grid, block, st, a); break;
         case PREC_FP32: okk = go_p<PREC_FP32>(c.p, force, pot, grid, block, st, a); break;
+        case PREC_F32D: okk = force && !pot && go_p<PREC_F32D>(c.p, force, pot, grid, block, st, a); break;
         default: break;
     }
     if (!okk) return fail(CB_EINVAL, "launch_pair: unsupported precision %d / p %d", prec, c.p);

@@ -62,9 +62,14 @@ __device__ __forceinline__ void pair_j(const IBlock<P>& ib, Acc<P, FORCE, POT>& 
                                        double zj, double qj, double eps2, int j, const SeriesK& K) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const double dx = ib.x[p] - xj;
-        const double dy = ib.y[p] - yj;
-        const double dz = ib.z[p] - zj;
+        double dx = ib.x[p] - xj;
+        double dy = ib.y[p] - yj;
+        double dz = ib.z[p] - zj;
+        if (PREC == PREC_F32D) {
+            dx = (double)(float)dx;
+            dy = (double)(float)dy;
+            dz = (double)(float)dz;
+        }
         const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
         double s, r;
         inv_r<PREC, FORCE, POT>(r2, qj, K, s, r);

@@ -22,7 +22,9 @@
 
 namespace cb {
 
-enum : int { PREC_FP64 = 0, PREC_MIXED = 1, PREC_IEEE = 2, PREC_FP32 = 3 };
+// PREC_F32D: the mixed refinement on displacements rounded to FP32 (an
+// ablation; the rounding happens where the displacement is formed).
+enum : int { PREC_FP64 = 0, PREC_MIXED = 1, PREC_IEEE = 2, PREC_FP32 = 3, PREC_F32D = 4 };
 
 __device__ __forceinline__ double rsq_seed(double r2) {
     return static_cast<double>(__builtin_amdgcn_rsqf(static_cast<float>(r2)));

@@ -200,3 +200,24 @@ def test_symmetric_config_validation(api):
             api.set_config(bad["op"], bad["n"], "fp64", p=bad["p"], wg=bad["wg"], splits=bad["splits"], algo=2)
         with pytest.raises(api.CoulombError):
             api.set_config(bad["op"], bad["n"], "fp64", p=bad["p"], wg=bad["wg"], splits=bad["splits"], algo=1)
+
+
+def test_fp32_displacement_ablation_is_forces_only(api):
+    L = api.lib()
+    big = 1 << 40
+    P = C.c_void_p(1 << 21)
+    assert L.cb_workspace_size(0, 100, 1, 1, 4) > 0
+    assert L.cb_workspace_size(0, 100, 1, 1, 5) == 0
+    assert L.coulomb_energy(10, P, P, P, P, 0.0, 4, P, _ws(), big, None) == api.CB_EUNSUPPORTED
+    arrs = [C.c_void_p((k + 1) << 24) for k in range(11)]
+    s = api.State(*arrs[:9])
+    tr = api.make_trap(dict(kind=0, wx=1e6, wy=1e6, wz=1e5))
+    assert L.md_step(10, C.byref(s), arrs[9], arrs[10], C.byref(tr), 0.0, 1e-9, 0.0, 4, _ws(), big,
+                     None) == api.CB_EUNSUPPORTED
+    offs = (C.c_int64 * 2)(0, 10)
+    assert L.md_run(1, offs, C.byref(s), arrs[9], arrs[10], C.byref(tr), 0.0, 1e-9, 5, 0.0, 4, 1, None, 0, _ws(),
+                    big, None) == api.CB_EUNSUPPORTED
+    v = C.c_void_p(1 << 30)
+    assert L.coulomb_hvp(10, P, P, P, P, 1, v, C.c_void_p(1 << 31), None, None, 0.0, 0.0, 4, _ws(), big,
+                         None) == api.CB_EUNSUPPORTED
+    assert L.cb_autotune(0, 1000, 4, None) == api.CB_EUNSUPPORTED

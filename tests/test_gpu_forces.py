@@ -188,6 +188,23 @@ def test_forces_at_the_symmetric_size_limit(api, oracle, n):
     api.clear_workspace_cache()
 
 
+def test_fp32_displacement_ablation_error(api, oracle):
+    """CB_MIXED_F32D, the literal "FP32 displacement" reading of the mixed
+    path (displacements rounded to FP32 in r^2 and in the numerator), on the
+    cloud100k shape at N = 6000: its error is reported, stays at the 2^-24
+    level, and is far above CB_MIXED's (which keeps FP64 displacements)."""
+    from _gpu_util import per_ion_rel, report
+    d = inputs.cloud100k(n=6000, seed=12)
+    fx, fy, fz, kappa = oracle.forces(d["x"], d["y"], d["z"], d["q"], kappa=True)
+    ref = np.stack([fx, fy, fz])
+    e_abl = per_ion_rel(_forces(api, d, "mixed_f32d"), ref)
+    e_mix = per_ion_rel(_forces(api, d, "mixed"), ref)
+    report("ablation fp32 displacement", e_abl, kappa)
+    report("mixed (fp64 displacement)", e_mix, kappa)
+    assert e_abl.max() < 1e-4 and np.sqrt(np.mean(e_abl ** 2)) < 1e-6
+    assert e_abl.max() > 100 * e_mix.max()
+
+
 def test_forces_are_deterministic(api):
     from _gpu_util import dev
     d = inputs.cloud1024(n=5000, seed=5)
