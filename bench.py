@@ -369,13 +369,14 @@ def bench_md_single(args, which):
 
 
 def bench_kz(args):
-    """kz512: 512 runs, N uniform in [64, 4096], ramp, in one batched
-    launch; FP64 and mixed.  --steps sets the steps per run (10000 in the
-    full workload)."""
+    """kz512: 512 runs, N uniform in [64, 4096], ramp, in one md_run; FP64
+    and mixed on the default (stepped) ensemble path, and FP64 on the
+    persistent kernel for comparison.  --steps sets the steps per run (10000
+    in the full workload)."""
     np, torch, api, inputs, dev = _setup()
     from paper_2106_11143_amd import drivers
 
-    nsteps = args.steps if args.steps != 50 else 1000
+    nsteps = args.steps if args.steps != 50 else 10000
     d = inputs.kz512(nsteps=nsteps)
     offs = d["offsets"]
     ns = np.diff(offs)
@@ -383,23 +384,36 @@ def bench_kz(args):
     st0 = inputs.state9(d)
     q, m = dev(d["q"]), dev(d["m"])
     res = {}
-    for prec in ("fp64", "mixed"):
-        ts = [dev(st0[k]) for k in range(9)]
+    ntot = int(offs[-1])
+    # the default path (the stepped one for this ensemble), then the
+    # persistent kernel forced, for comparison
+    # (the persistent kernel over at most 1000 steps: its rate per step is steady)
+    for key, prec, force in (("fp64", "fp64", False), ("mixed", "mixed", False), ("fp64_persistent", "fp64", True)):
+        k = min(nsteps, 1000) if force else nsteps
+        if force:
+            api.set_config("md_ensemble", ntot, prec, p=4, wg=512, splits=1, algo=0)
+        ts = [dev(st0[c]) for c in range(9)]
         torch.cuda.synchronize()
         e0, e1 = _timer(torch)
         e0.record()
-        api.md_run(ts, q, m, d["traps"], 0.0, d["dt"], nsteps, offsets=offs, prec=prec)
+        api.md_run(ts, q, m, d["traps"], 0.0, d["dt"], k, offsets=offs, prec=prec)
         e1.record()
         torch.cuda.synchronize()
+        if force:
+            api.reset_config("md_ensemble", ntot, prec)
         ms = e0.elapsed_time(e1)
         got = np.stack([t.cpu().numpy() for t in ts[:3]])
         defects = [drivers.count_defects(*got[:, offs[r]:offs[r + 1]]) for r in range(d["nrun"])]
-        res[prec] = {"ms": ms, "runs_per_s": d["nrun"] / (ms * 1e-3), "pairs_per_s": pairs / (ms * 1e-3),
-                     "defects_mean": float(np.mean(defects)), "finite": bool(np.isfinite(got).all())}
-    extra = {"mixed": res["mixed"], "fp64": res["fp64"], "nrun": d["nrun"], "nsteps_per_run": nsteps,
+        kp = pairs / nsteps * k
+        res[key] = {"ms": ms, "steps": k, "ms_per_step": ms / k, "runs_per_s": d["nrun"] / (ms * 1e-3),
+                    "pairs_per_s": kp / (ms * 1e-3), "defects_mean": float(np.mean(defects)),
+                    "finite": bool(np.isfinite(got).all())}
+    extra = {"mixed": res["mixed"], "fp64": res["fp64"], "fp64_persistent_kernel": res["fp64_persistent"],
+             "path": "stepped (p = 4, JL = 256: the default for runs above 512 ions)", "nrun": d["nrun"],
+             "nsteps_per_run": nsteps,
              "sum_N2": float((ns.astype(np.float64) ** 2).sum()),
              "roofline": _roof(FLOPS_PER_PAIR * pairs, res["fp64"]["ms"] * 1e-3,
-                               "cb::k_batched<FP64> (one persistent launch for all runs)")}
+                               "whole md_run: per step k_pair_sym_ens<FP64> over every run's tiles + k_ens_step<FP64>")}
     if not args.no_cpu:
         from oracle import oracle as O
 

@@ -93,9 +93,11 @@ typedef enum {
     CB_MIXED_F32D = 4
 } cb_precision;
 
-/* Operation codes for cb_workspace_size / cb_autotune. */
+/* Operation codes for cb_workspace_size / cb_autotune.  CB_OP_MD_ENSEMBLE
+ * only keys the launch configuration of md_run with nrun > 1
+ * (cb_get_config / cb_set_config); its workspace is that of CB_OP_MD_RUN. */
 typedef enum { CB_OP_FORCES = 0, CB_OP_ENERGY = 1, CB_OP_MD_STEP = 2, CB_OP_MD_RUN = 3,
-               CB_OP_HVP = 4, CB_OP_ADJOINT = 5 } cb_op;
+               CB_OP_HVP = 4, CB_OP_ADJOINT = 5, CB_OP_MD_ENSEMBLE = 6 } cb_op;
 
 /* md_run flags. */
 #define CB_INIT_ACCEL 1u /* compute a(r_0, t0) before the first step instead of using s->a* */
@@ -133,7 +135,9 @@ typedef struct {
 } cb_state;
 
 /* Size in bytes of the workspace the call `op` needs for n ions (n_total for
- * md_run), nrun runs, nvec HVP vectors and precision prec.  0 on bad input. */
+ * md_run), nrun runs, nvec HVP vectors and precision prec.  0 on bad input.
+ * For md_run with nrun > 1 it covers both ensemble paths for any split of
+ * n_total into nrun runs of at most 4096 ions (about 0.5 KB per ion). */
 size_t cb_workspace_size(int32_t op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec);
 
 /* Forces F_i (N) on all n ions (eq. (1), Coulomb term times m; section 3
@@ -186,9 +190,20 @@ cb_status md_step(int64_t n, const cb_state* s, const double* q, const double* m
  * hold a_0.  When energies is non-NULL (device, [nrun][nsteps/every + 1][4])
  * it receives (K, U_C, U_trap, K + U_C + U_trap) of steps 0, every, 2 every,
  * ..., for each run; every >= 1 then.
- * nrun = 1 runs the multi-workgroup step kernels (any n); nrun > 1 runs the
- * batched persistent kernel, one workgroup per run, which needs every run to
- * hold at most 4096 ions (CB_EUNSUPPORTED otherwise). */
+ * nrun = 1 runs the multi-workgroup step kernels (any n).  nrun > 1 needs
+ * every run to hold at most 4096 ions (CB_EUNSUPPORTED otherwise) and takes
+ * one of two ensemble paths (configuration key CB_OP_MD_ENSEMBLE):
+ *  - algorithm 0: one persistent launch, one workgroup per run at a time,
+ *    positions in LDS, runs taken largest first;
+ *  - algorithm 2: per step, one launch of the Newton's-third-law pair tiles
+ *    of every run and one launch that finishes the forces and applies the
+ *    kick and drift (p i-particles per lane, j-segment length JL).
+ * Without a forced or tuned entry the path with the smaller estimated step
+ * time is taken (algorithm 0 wins only for ensembles of small runs whose
+ * step is shorter than the stepped path's launch latency), with p = 8,
+ * JL = 512 when no run exceeds 512 ions, else p = 4, JL = 256.  Both paths
+ * give the same trajectories up to rounding (different summation orders);
+ * each is deterministic. */
 cb_status md_run(int32_t nrun, const int64_t* offsets, const cb_state* s, const double* q, const double* m,
                  const cb_trap* traps, double t0, double dt, int64_t nsteps, double eps2, int32_t prec,
                  uint32_t flags, double* energies, int64_t every, void* ws, size_t ws_bytes, void* stream);
@@ -252,6 +267,9 @@ cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]);
  * and adjoint), wg in {64,128,256}, splits in 1..64.  Algorithms 1 and 2 (forces,
  * md_step, md_run; n <= 2^18): p in {2,3,4,5,6,8}, wg = j's per reduction
  * group = 4, splits = segment length in {256,512,1024,2048}.
+ * For CB_OP_MD_ENSEMBLE (n = total ions): algorithm 0 with p = 4, wg = 512,
+ * splits = 1 (the persistent kernel's fixed shape), or algorithm 2 with p in
+ * {4, 8}, wg = 4, splits = JL in {256, 512}.
  * algo = p = wg = splits = 0 removes a forced or tuned entry (back to the
  * built-in heuristic).  CB_EINVAL if unsupported. */
 cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t algo, int32_t p, int32_t wg, int32_t splits);

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libcoulomb_mi355x.so")
 CB_OK, CB_EINVAL, CB_EHIP, CB_ENOWS, CB_ENONFINITE, CB_EUNSUPPORTED = range(6)
 STATUS_NAMES = {0: "CB_OK", 1: "CB_EINVAL", 2: "CB_EHIP", 3: "CB_ENOWS", 4: "CB_ENONFINITE", 5: "CB_EUNSUPPORTED"}
 PRECISIONS = {"fp64": 0, "mixed": 1, "ieee": 2, "fp32": 3, "mixed_f32d": 4}
-OPS = {"forces": 0, "energy": 1, "md_step": 2, "md_run": 3, "hvp": 4, "adjoint": 5}
+OPS = {"forces": 0, "energy": 1, "md_step": 2, "md_run": 3, "hvp": 4, "adjoint": 5, "md_ensemble": 6}
 CB_INIT_ACCEL = 1
 CB_ADJ_FINAL = 1
 
@@ -344,6 +344,9 @@ def set_config(op, n: int, prec="fp64", p: int = 1, wg: int = 256, splits: int =
     default).  algo 1 = the Newton's-third-law force kernel (n <= 2^18), with
     p in {2, 3, 4, 5, 6, 8}, wg = j's per reduction group = 4 and splits =
     segment length in {256, 512, 1024, 2048}; algo 2 = the same kernel with
-    the per-j reactions summed through LDS."""
+    the per-j reactions summed through LDS.  op "md_ensemble" (n = total
+    ions) picks the path of md_run with several runs: algo 0 with p = 4,
+    wg = 512, splits = 1 is the persistent kernel; algo 2 with p in {4, 8},
+    wg = 4, splits in {256, 512} is the stepped path."""
     _check(lib().cb_set_config(_op(op), int(n), _prec(prec), int(algo), int(p), int(wg), int(splits)),
            "cb_set_config")

@@ -25,9 +25,6 @@
 
 namespace cb {
 
-constexpr int kBatchWG = 512;
-constexpr int kBatchP = 4;
-
 // Newton's-third-law pass for the largest runs (the ones that bound the
 // launch's makespan): blocks of kSymBS ions (one wave, kSymBP per lane), every
 // unordered pair of blocks once in a round-robin schedule in which the eight
@@ -444,7 +441,6 @@ cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s
                          const double* m, const cb_trap* traps, double t0, double dt, int64_t nsteps,
                          double eps2, int32_t prec, uint32_t flags, double* energies, int64_t every, void* ws,
                          size_t ws_bytes, hipStream_t st) {
-    (void)ws_bytes;  // checked by the caller
     int nmax = 0;
     for (int r = 0; r < nrun; ++r) nmax = std::max<int>(nmax, (int)(offsets[r + 1] - offsets[r]));
     if (nmax > kMaxBatchIons)
@@ -452,6 +448,32 @@ cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s
                     nmax);
     if (prec != CB_FP64 && prec != CB_MIXED && prec != CB_FP64_IEEE && prec != CB_FP32_RSQ)
         return fail(CB_EINVAL, "md_run: unknown precision %d", prec);
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return fail(CB_EHIP, "md_run: device query failed");
+    // Path.  A forced or tuned entry decides.  Otherwise estimate the time of
+    // one step on each path from rates measured on MI355X: this kernel runs
+    // a small run at about 1.6e9 ordered pairs/s per CU (its runs are spread
+    // over the CUs, the largest bounding the step); the stepped path costs
+    // about 40 us of launch latency per step plus the pairs at 1.8e12/s.
+    // The stepped path uses 512-ion i-blocks when no run is larger (each run
+    // is then finished by its diagonal pass alone), else 256-ion blocks.
+    LaunchCfg ec = get_cfg(CB_OP_MD_ENSEMBLE, offsets[nrun], prec);
+    if (!ec.tuned) {
+        double pairs = 0.0;
+        for (int r = 0; r < nrun; ++r)
+            pairs += (double)(offsets[r + 1] - offsets[r]) * (double)(offsets[r + 1] - offsets[r]);
+        const double t_persistent = std::ceil((double)nrun / ncu) * (double)nmax * nmax / 1.6e9;
+        const double t_stepped = 40e-6 + pairs / 1.8e12;
+        ec.algo = t_stepped < t_persistent ? ALGO_SYM_LDS : ALGO_DIRECT;
+        ec.p = nmax <= 512 ? 8 : 4;
+        ec.splits = nmax <= 512 ? 512 : 256;
+    }
+    if (ec.algo == ALGO_SYM_LDS) {
+        const WsLayout LE = ws_layout(CB_OP_MD_RUN, offsets[nrun], nrun, 1);
+        return md_run_ensemble(nrun, offsets, s, q, m, traps, t0, dt, nsteps, eps2, prec, flags, energies, every, ec.p,
+                               ec.splits, static_cast<char*>(ws) + LE.aux, ws_bytes - LE.aux, st);
+    }
     unsigned* fl = flags_ptr();
     if (!fl) return fail(CB_EHIP, "md_run: device flag symbol not found");
 
@@ -500,9 +522,6 @@ cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s
     B.facc = reinterpret_cast<double*>(static_cast<char*>(ws) + L.aux);
 
     const size_t lds = sizeof(double4) * (size_t)nmax + sizeof(double) * 3 * kBatchWG;
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return fail(CB_EHIP, "md_run: device query failed");
     const int per_cu = std::max(1, (int)((160 * 1024) / lds));
     const int grid = std::min(std::min(nrun, ncu * std::min(per_cu, 2)), kBatchGridMax);
     auto launch = [&](auto kern) -> cb_status {

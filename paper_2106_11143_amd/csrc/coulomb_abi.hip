@@ -80,6 +80,15 @@ LaunchCfg default_cfg(int op, int64_t n, int prec) {
     c.tuned = 0;
     c.algo = ALGO_DIRECT;
     (void)prec;
+    if (op == CB_OP_MD_ENSEMBLE) {
+        // Stepped ensemble path (ensemble.hip).  While this entry is untuned,
+        // md_run_batched picks the path and (p, JL) from the run sizes.
+        c.algo = ALGO_SYM_LDS;
+        c.p = 4;
+        c.wg = kSymGroup;
+        c.splits = 256;
+        return c;
+    }
     const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
     if (force_op && n >= 16384 && n <= kSymMaxN) {
         // Newton's third law: each pair once (see pair_sym.hpp), reactions
@@ -125,6 +134,9 @@ void drop_cfg(int op, int64_t n, int prec) {
 }
 
 bool valid_cfg(int op, const LaunchCfg& c) {
+    if (op == CB_OP_MD_ENSEMBLE)
+        return (c.algo == ALGO_DIRECT && c.p == kBatchP && c.wg == kBatchWG && c.splits == 1) ||
+               (c.algo == ALGO_SYM_LDS && c.wg == kSymGroup && ens_cfg_ok(c.p, c.splits));
     const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
     if (is_sym(c.algo)) return force_op && sym_cfg_ok(c.p, c.wg, c.splits);
     if (c.algo != ALGO_DIRECT) return false;
@@ -174,8 +186,11 @@ WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec) {
     } else {
         L.batch = off;
         off += al((sizeof(int64_t) * 2 + sizeof(cb_trap) + sizeof(int)) * (size_t)nrun + 64);
-        L.aux = off;  // force accumulators of the batched kernel's Newton's-third-law pass
-        off += al(sizeof(double) * 3 * (size_t)kMaxBatchIons * (size_t)std::min<int32_t>(nrun, kBatchGridMax));
+        // Persistent kernel: force accumulators of its Newton's-third-law pass.
+        // Stepped path: its tables, partials and second position buffer.
+        L.aux = off;
+        off += al(std::max(sizeof(double) * 3 * (size_t)kMaxBatchIons * (size_t)std::min<int32_t>(nrun, kBatchGridMax),
+                           ens_ws_bound(n, nrun)));
     }
     L.total = off + 256;
     return L;
@@ -220,7 +235,7 @@ size_t cb_workspace_size(int32_t op, int64_t n, int32_t nrun, int32_t nvec, int3
 }
 
 cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]) {
-    if (!out || n < 1 || op < 0 || op > CB_OP_ADJOINT) return fail(CB_EINVAL, "cb_get_config: bad argument");
+    if (!out || n < 1 || op < 0 || op > CB_OP_MD_ENSEMBLE) return fail(CB_EINVAL, "cb_get_config: bad argument");
     LaunchCfg c = get_cfg(op, n, prec);
     out[0] = c.algo;
     out[1] = c.p;
@@ -231,13 +246,13 @@ cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]) {
 }
 
 cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t algo, int32_t p, int32_t wg, int32_t splits) {
-    if (n < 1 || op < 0 || op > CB_OP_ADJOINT) return fail(CB_EINVAL, "cb_set_config: bad argument");
+    if (n < 1 || op < 0 || op > CB_OP_MD_ENSEMBLE) return fail(CB_EINVAL, "cb_set_config: bad argument");
     if (algo == 0 && p == 0 && wg == 0 && splits == 0) {
         drop_cfg(op, n, prec);
         return ok();
     }
     LaunchCfg c{p, wg, splits, 1, algo};
-    if (!valid_cfg(op, c) || (is_sym(algo) && n > kSymMaxN))
+    if (!valid_cfg(op, c) || (is_sym(algo) && op != CB_OP_MD_ENSEMBLE && n > kSymMaxN))
         return fail(CB_EINVAL, "cb_set_config: unsupported configuration algo=%d p=%d wg=%d splits=%d", algo, p, wg,
                     splits);
     put_cfg(op, n, prec, c);

@@ -13,6 +13,8 @@ constexpr int kMaxSplits = 64;       // j-splits per launch
 constexpr int kMaxVec = 8;           // HVP vectors per call
 constexpr int kMaxBatchIons = 4096;  // ions per run in the batched kernel (LDS bound)
 constexpr int kBatchGridMax = 2048;  // workgroups of one batched launch (force accumulator slots)
+constexpr int kBatchWG = 512;        // threads per workgroup of the persistent batched kernel
+constexpr int kBatchP = 4;           // ions per thread and register group in that kernel
 constexpr int kEpiBlock = 256;       // threads per element-wise block
 constexpr int64_t kSymMaxN = int64_t(1) << 18;  // largest n for the symmetric kernel (partials grow as n^2)
 
@@ -83,7 +85,18 @@ cb_status launch_hvp(int prec, const LaunchCfg& c, int nvec, int n, const double
                      const double* z, const double* q, const double* v, double eps2, int jlen, double* part,
                      hipStream_t st);
 
-// Batched persistent md_run (batched.hip).
+// Stepped ensemble md_run (ensemble.hip): supported (p, JL), a workspace
+// bound over every split of ntot ions into nrun runs of at most
+// kMaxBatchIons, and the driver.
+bool ens_cfg_ok(int p, int jl);
+size_t ens_ws_bound(int64_t ntot, int32_t nrun);
+cb_status md_run_ensemble(int32_t nrun, const int64_t* offsets, const cb_state* s, const double* q,
+                          const double* m, const cb_trap* traps, double t0, double dt, int64_t nsteps, double eps2,
+                          int32_t prec, uint32_t flags, double* energies, int64_t every, int P, int JL, void* ws,
+                          size_t ws_bytes, hipStream_t st);
+
+// Batched md_run (batched.hip): picks the persistent kernel or the stepped
+// ensemble path.
 cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s, const double* q,
                          const double* m, const cb_trap* traps, double t0, double dt, int64_t nsteps,
                          double eps2, int32_t prec, uint32_t flags, double* energies, int64_t every, void* ws,

@@ -33,50 +33,6 @@ __host__ __device__ __forceinline__ int sym_nseg(int n, int IB, int JL, int I) {
     return a > 0 ? (a + JL - 1) / JL : 0;
 }
 
-// Tile table, one workgroup.  rowstart[I] = first tile of row I (exclusive
-// prefix sum over rows of their segment counts), rowstart[nI] = tiles T;
-// tiles[t] = (row, segment) of tile t.  Each thread sums the segments of a
-// contiguous share of rows, the shares are scanned in LDS (Hillis-Steele),
-// the row starts are kept in LDS, and each wave then writes whole rows of
-// the table, its lanes taking consecutive segments.
-constexpr int kPlanThreads = 1024;
-constexpr int kPlanMaxRows = 2048;  // n <= 2^18 ions in blocks of >= 128
-
-__global__ void __launch_bounds__(kPlanThreads) k_sym_plan(int n, int IB, int JL, int nI, int* __restrict__ rowstart,
-                                                           int2* __restrict__ tiles) {
-    __shared__ int sh[kPlanThreads];
-    __shared__ int rs[kPlanMaxRows + 1];
-    const int t = threadIdx.x;
-    const int per = (nI + kPlanThreads - 1) / kPlanThreads;
-    const int r0 = min(nI, t * per), r1 = min(nI, r0 + per);
-    int mine = 0;
-    for (int I = r0; I < r1; ++I) mine += sym_nseg(n, IB, JL, I);
-    sh[t] = mine;
-    __syncthreads();
-    for (int w = 1; w < kPlanThreads; w <<= 1) {
-        const int add = t >= w ? sh[t - w] : 0;
-        __syncthreads();
-        sh[t] += add;
-        __syncthreads();
-    }
-    int acc = sh[t] - mine;  // exclusive prefix of this thread's rows
-    for (int I = r0; I < r1; ++I) {
-        rs[I] = acc;
-        rowstart[I] = acc;
-        acc += sym_nseg(n, IB, JL, I);
-    }
-    if (t == kPlanThreads - 1) {
-        rs[nI] = sh[t];
-        rowstart[nI] = sh[t];
-    }
-    __syncthreads();
-    const int lane = t & 63;
-    for (int I = t >> 6; I < nI; I += kPlanThreads / 64) {
-        const int s0 = rs[I], ns = rs[I + 1] - s0;
-        for (int sg = lane; sg < ns; sg += 64) tiles[s0 + sg] = make_int2(I, sg);
-    }
-}
-
 // s = q r^{-3} refined as in the direct kernel (the series on r^-3).
 template <int PREC>
 __device__ __forceinline__ double sym_s(double r2, double q, const SeriesK& K) {
@@ -171,17 +127,14 @@ constexpr int sym_waves() {
     return PREC == PREC_IEEE ? (P <= 4 ? 4 : (P <= 6 ? 3 : 2)) : (P <= 5 ? 4 : 3);
 }
 
+// Tile (row I, segment sg) of a run of n ions at x, y, z, q: i sums to
+// Pi[t][3][IB], reactions to R[t][3][JL].  red: the LDS reduction buffer.
 template <int PREC, int P, int RED>
-__global__ void __launch_bounds__(64, (sym_waves<PREC, P>())) k_pair_sym(int n, const double* __restrict__ x,
-                                                                 const double* __restrict__ y,
-                                                                 const double* __restrict__ z,
-                                                                 const double* __restrict__ q, double eps2, int JL,
-                                                                 const int2* __restrict__ tiles,
-                                                                 double* __restrict__ Pi, double* __restrict__ R) {
+__device__ __forceinline__ void sym_tile(int n, const double* __restrict__ x, const double* __restrict__ y,
+                                         const double* __restrict__ z, const double* __restrict__ q, double eps2,
+                                         int JL, int I, int sg, int t, double* __restrict__ red,
+                                         double* __restrict__ Pi, double* __restrict__ R) {
     constexpr int IB = 64 * P;
-    const int t = blockIdx.x;
-    const int2 tl = tiles[t];
-    const int I = tl.x, sg = tl.y;
     const int lane = threadIdx.x;
     double xi[P], yi[P], zi[P], qi[P], ia[P][3];
 #pragma unroll
@@ -194,8 +147,6 @@ __global__ void __launch_bounds__(64, (sym_waves<PREC, P>())) k_pair_sym(int n, 
         ia[p][0] = ia[p][1] = ia[p][2] = 0.0;
     }
     const SeriesK K;
-    __shared__ __align__(16) double red_buf[RED == 1 ? 12 * kRedStride : 2];
-    double* red = red_buf;
     const int j0 = (I + 1) * IB + sg * JL;
     const int j1 = min(n, j0 + JL);
     const int jfull = j0 + (j1 - j0) / kGroupJ * kGroupJ;
@@ -226,6 +177,19 @@ __global__ void __launch_bounds__(64, (sym_waves<PREC, P>())) k_pair_sym(int n, 
     for (int p = 0; p < P; ++p)
 #pragma unroll
         for (int c = 0; c < 3; ++c) Pt[(size_t)c * IB + p * 64 + lane] = ia[p][c];
+}
+
+template <int PREC, int P, int RED>
+__global__ void __launch_bounds__(64, (sym_waves<PREC, P>())) k_pair_sym(int n, const double* __restrict__ x,
+                                                                 const double* __restrict__ y,
+                                                                 const double* __restrict__ z,
+                                                                 const double* __restrict__ q, double eps2, int JL,
+                                                                 const int2* __restrict__ tiles,
+                                                                 double* __restrict__ Pi, double* __restrict__ R) {
+    __shared__ __align__(16) double red_buf[RED == 1 ? 12 * kRedStride : 2];
+    const int t = blockIdx.x;
+    const int2 tl = tiles[t];
+    sym_tile<PREC, P, RED>(n, x, y, z, q, eps2, JL, tl.x, tl.y, t, red_buf, Pi, R);
 }
 
 // Per ion k: direct pairs inside its own i-block, plus its i sums over the

@@ -15,6 +15,17 @@ constexpr double kCoulomb = 1.0 / (4.0 * kPi * kEps0);
 
 constexpr int kEpiThreads = 256;
 
+// What one element-wise launch does per ion.
+enum : unsigned {
+    EPI_FORCES = 1u,   // write F to fx, fy, fz
+    EPI_ACCEL = 2u,    // a <- F/m + trap (initial acceleration)
+    EPI_KICK = 4u,     // a_new = F/m + trap; v += dt/2 (a + a_new); a <- a_new
+    EPI_DRIFT = 8u,    // r += v dt + a dt^2/2 (after any kick)
+    EPI_ENERGY = 16u,  // per-block sums of K, U_C, U_trap of the resulting state
+    EPI_UC_ONLY = 32u,   // energy: only U_C (no m, v, trap)
+    EPI_PRESCALED = 64u  // part holds finished forces [3][n] (S = 1), not sums to scale by k_C q_i
+};
+
 struct TrapK {
     double kx, ky, kz;
 };

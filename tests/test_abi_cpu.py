@@ -221,3 +221,31 @@ def test_fp32_displacement_ablation_is_forces_only(api):
     assert L.coulomb_hvp(10, P, P, P, P, 1, v, C.c_void_p(1 << 31), None, None, 0.0, 0.0, 4, _ws(), big,
                          None) == api.CB_EUNSUPPORTED
     assert L.cb_autotune(0, 1000, 4, None) == api.CB_EUNSUPPORTED
+
+
+def test_ensemble_config_validation_and_workspace(api):
+    """The ensemble path key of md_run with several runs: default, the two
+    valid shapes, rejections; the md_run workspace covers the stepped path
+    (about 0.5 KB per ion for any split into runs of at most 4096)."""
+    c = api.get_config("md_ensemble", 1_000_000, "fp64")
+    assert (c["algo"], c["p"], c["wg"], c["splits"], c["tuned"]) == (2, 4, 4, 256, False)
+    api.set_config("md_ensemble", 1_000_000, "fp64", p=4, wg=512, splits=1, algo=0)
+    c = api.get_config("md_ensemble", 1_000_000, "fp64")
+    assert (c["algo"], c["tuned"]) == (0, True)
+    for p in (4, 8):
+        for jl in (256, 512):
+            api.set_config("md_ensemble", 1_000_000, "mixed", p=p, wg=4, splits=jl, algo=2)
+            c = api.get_config("md_ensemble", 1_000_000, "mixed")
+            assert (c["algo"], c["p"], c["splits"], c["tuned"]) == (2, p, jl, True)
+    api.reset_config("md_ensemble", 1_000_000, "fp64")
+    api.reset_config("md_ensemble", 1_000_000, "mixed")
+    assert not api.get_config("md_ensemble", 1_000_000, "mixed")["tuned"]
+    for bad in (dict(p=2, wg=4, splits=256, algo=2), dict(p=4, wg=4, splits=1024, algo=2),
+                dict(p=4, wg=4, splits=256, algo=1), dict(p=4, wg=256, splits=1, algo=0),
+                dict(p=1, wg=512, splits=1, algo=0), dict(p=8, wg=8, splits=512, algo=2)):
+        with pytest.raises(api.CoulombError):
+            api.set_config("md_ensemble", 1_000_000, "fp64", **bad)
+    assert api.lib().cb_workspace_size(6, 1000, 2, 1, 0) == 0  # a configuration key, not a call
+    for ntot, nrun in ((1_070_000, 512), (8192, 2), (5000, 100)):
+        ws = api.workspace_size("md_run", ntot, nrun=nrun)
+        assert 400 * ntot <= ws <= 1000 * ntot + (1 << 24), (ntot, nrun, ws)

@@ -1,5 +1,9 @@
-"""GPU batched persistent md_run (many runs of uneven size in one launch)
-against the oracle run by run, and against the single-run path."""
+"""GPU md_run with many runs of uneven size, on both ensemble paths (the
+persistent kernel, one workgroup per run; the stepped path, two launches per
+step over every run's Newton's-third-law tiles), against the oracle run by
+run, against the single-run path and against each other."""
+import contextlib
+
 import numpy as np
 import pytest
 
@@ -16,6 +20,25 @@ def api():
     from paper_2106_11143_amd import api as A
     A.lib()
     return A
+
+
+PERSISTENT = ("persistent",)
+STEPPED4 = ("stepped", 4, 256)
+STEPPED8 = ("stepped", 8, 512)
+PATHS = [PERSISTENT, STEPPED4, STEPPED8]
+
+
+@contextlib.contextmanager
+def _path(api, ntot, prec, path):
+    """Forces the ensemble path of md_run for ntot ions at prec."""
+    if path[0] == "persistent":
+        api.set_config("md_ensemble", ntot, prec, p=4, wg=512, splits=1, algo=0)
+    else:
+        api.set_config("md_ensemble", ntot, prec, p=path[1], wg=4, splits=path[2], algo=2)
+    try:
+        yield
+    finally:
+        api.reset_config("md_ensemble", ntot, prec)
 
 
 def _ensemble(sizes, seed, trap):
@@ -48,8 +71,9 @@ def _check_run(oracle, st, q, m, trap, dt, nsteps, got, en_got, every, tag):
         assert np.all(np.abs(en_got - en) <= 10 * np.abs(en2 - en) + 1e-12 * np.abs(en).max(axis=0)), tag
 
 
+@pytest.mark.parametrize("path", PATHS, ids=lambda p: "-".join(map(str, p)))
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_batched_ramp_matches_oracle_run_by_run(api, oracle, prec):
+def test_batched_ramp_matches_oracle_run_by_run(api, oracle, prec, path):
     from _gpu_util import dev
     trap = inputs.ramp_trap(1.5e6, 0.6e6, 0.15e6, 0.0, 60e-9)
     sizes = [64, 65, 130, 257, 500, 1000, 333]
@@ -57,7 +81,9 @@ def test_batched_ramp_matches_oracle_run_by_run(api, oracle, prec):
     st = np.concatenate(parts, axis=1)
     ts = [dev(st[k]) for k in range(9)]
     dt, nsteps, every = 2e-9, 40, 10
-    en = api.md_run(ts, dev(q), dev(m), [trap] * len(sizes), 0.0, dt, nsteps, offsets=offs, every=every, prec=prec)
+    with _path(api, offs[-1], prec, path):
+        en = api.md_run(ts, dev(q), dev(m), [trap] * len(sizes), 0.0, dt, nsteps, offsets=offs, every=every,
+                        prec=prec)
     got = np.stack([t.cpu().numpy() for t in ts])
     en = en.cpu().numpy()
     for r, n in enumerate(sizes):
@@ -70,14 +96,16 @@ def test_batched_ramp_matches_oracle_run_by_run(api, oracle, prec):
     assert api.poll_flags() == 0
 
 
-def test_batched_equals_single_run_path(api):
+@pytest.mark.parametrize("path", PATHS, ids=lambda p: "-".join(map(str, p)))
+def test_batched_equals_single_run_path(api, path):
     from _gpu_util import dev
     trap = inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6)
     sizes = [200, 96, 1500]
     parts, offs, q, m = _ensemble(sizes, 5, trap)
     st = np.concatenate(parts, axis=1)
     ts = [dev(st[k]) for k in range(9)]
-    api.md_run(ts, dev(q), dev(m), [trap] * 3, 0.0, 1e-9, 25, offsets=offs)
+    with _path(api, offs[-1], "fp64", path):
+        api.md_run(ts, dev(q), dev(m), [trap] * 3, 0.0, 1e-9, 25, offsets=offs)
     got = np.stack([t.cpu().numpy() for t in ts])
     for r in range(3):
         sl = slice(offs[r], offs[r + 1])
@@ -89,16 +117,19 @@ def test_batched_equals_single_run_path(api):
             assert np.abs(got[blk, sl] - single[blk]).max() <= 1e-11 * scale
 
 
-def test_batched_largest_run_and_order(api, oracle):
-    """A 4096-ion run (the LDS limit) mixed with small ones; runs are taken in
-    largest-first order but each lands in its own slice."""
+@pytest.mark.parametrize("path", PATHS, ids=lambda p: "-".join(map(str, p)))
+def test_batched_largest_run_and_order(api, oracle, path):
+    """A 4096-ion run (the size limit) mixed with small ones; the persistent
+    kernel takes runs largest first and the stepped path launches tiles
+    longest first, but each run lands in its own slice."""
     from _gpu_util import dev
     trap = inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6)
     sizes = [70, 4096, 64, 2049]
     parts, offs, q, m = _ensemble(sizes, 8, trap)
     st = np.concatenate(parts, axis=1)
     ts = [dev(st[k]) for k in range(9)]
-    api.md_run(ts, dev(q), dev(m), [trap] * 4, 0.0, 1e-9, 3, offsets=offs)
+    with _path(api, offs[-1], "fp64", path):
+        api.md_run(ts, dev(q), dev(m), [trap] * 4, 0.0, 1e-9, 3, offsets=offs)
     got = np.stack([t.cpu().numpy() for t in ts])
     for r in (0, 1, 3):
         sl = slice(offs[r], offs[r + 1])
@@ -126,18 +157,20 @@ def test_kz_ensemble_small(api):
     print(f"[kz small] defect counts {counts}", flush=True)
 
 
-def test_batched_with_friction_matches_oracle_run_by_run(api, oracle):
+@pytest.mark.parametrize("path", PATHS, ids=lambda p: "-".join(map(str, p)))
+def test_batched_with_friction_matches_oracle_run_by_run(api, oracle, path):
     """Runs with different friction coefficients (one of them zero) in one
-    batched launch, each against the oracle."""
+    md_run, each against the oracle."""
     from _gpu_util import dev
     base = inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6)
     traps = [dict(base, gamma=g * inputs.MASS_40U) for g in (0.0, 2e5, 1e6)]
-    sizes = [130, 64, 257]
+    sizes = [130, 64, 600]
     parts, offs, q, m = _ensemble(sizes, 17, base)
     st = np.concatenate(parts, axis=1)
     ts = [dev(st[k]) for k in range(9)]
     nsteps, every = 40, 10
-    en = api.md_run(ts, dev(q), dev(m), traps, 0.0, 2e-9, nsteps, offsets=offs, every=every).cpu().numpy()
+    with _path(api, offs[-1], "fp64", path):
+        en = api.md_run(ts, dev(q), dev(m), traps, 0.0, 2e-9, nsteps, offsets=offs, every=every).cpu().numpy()
     got = np.stack([t.cpu().numpy() for t in ts])
     for r in range(3):
         sl = slice(offs[r], offs[r + 1])
@@ -146,7 +179,7 @@ def test_batched_with_friction_matches_oracle_run_by_run(api, oracle):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batched_newton_pass_matches_oracle(api, oracle, prec):
-    """Runs above 3072 ions take the Newton's-third-law block-pair pass
+    """In the persistent kernel, runs above 3072 ions take the Newton's-third-law block-pair pass
     (round-robin over 256-ion blocks, ragged last block); a small run in the
     same launch takes the direct pass.  Each run against the oracle, with
     energies recorded every 4 steps (recording steps use the direct pass)."""
@@ -157,10 +190,83 @@ def test_batched_newton_pass_matches_oracle(api, oracle, prec):
     st = np.concatenate(parts, axis=1)
     ts = [dev(st[k]) for k in range(9)]
     nsteps, every = 10, 4
-    en = api.md_run(ts, dev(q), dev(m), [trap] * len(sizes), 0.0, 2e-9, nsteps, offsets=offs, every=every,
-                    prec=prec).cpu().numpy()
+    with _path(api, offs[-1], prec, PERSISTENT):
+        en = api.md_run(ts, dev(q), dev(m), [trap] * len(sizes), 0.0, 2e-9, nsteps, offsets=offs, every=every,
+                        prec=prec).cpu().numpy()
     got = np.stack([t.cpu().numpy() for t in ts])
     for r in range(len(sizes)):
         sl = slice(offs[r], offs[r + 1])
         _check_run(oracle, parts[r], q[sl], m[sl], trap, 2e-9, nsteps, got[:, sl], en[r], every, f"run {r}")
     assert api.poll_flags() == 0
+
+
+@pytest.mark.parametrize("path", [STEPPED4, STEPPED8], ids=lambda p: "-".join(map(str, p)))
+@pytest.mark.parametrize("prec", ["fp64", "ieee"])
+def test_stepped_ensemble_block_edges_and_traps(api, oracle, prec, path):
+    """The stepped path on run sizes at and around its i-block (64 p) and
+    segment edges, a single-ion run, and one trap kind per run (static,
+    ramp, RF drive, friction), energies every step; each run against the
+    oracle."""
+    from _gpu_util import dev
+    base = inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6)
+    kinds = [base, inputs.ramp_trap(1.5e6, 0.6e6, 0.15e6, 0.0, 20e-9),
+             inputs.rf_trap(0.0, 0.3, 10e6, 0.15e6), dict(base, gamma=5e5 * inputs.MASS_40U)]
+    sizes = [1, 63, 64, 65, 255, 256, 257, 511, 512, 513, 769, 1100, 1537]
+    traps = [kinds[r % 4] for r in range(len(sizes))]
+    parts, offs, q, m = _ensemble(sizes, 29, base)
+    st = np.concatenate(parts, axis=1)
+    ts = [dev(st[k]) for k in range(9)]
+    nsteps, every = 12, 1
+    with _path(api, offs[-1], prec, path):
+        en = api.md_run(ts, dev(q), dev(m), traps, 0.0, 1e-9, nsteps, offsets=offs, every=every,
+                        prec=prec).cpu().numpy()
+    got = np.stack([t.cpu().numpy() for t in ts])
+    for r, n in enumerate(sizes):
+        sl = slice(offs[r], offs[r + 1])
+        if n == 1:  # no pairs: the trap alone, against the oracle's trajectory
+            ref, en_ref, _ = oracle.md_run(parts[r], q[sl], m[sl], traps[r], 0.0, 1e-9, nsteps, every=every)
+            assert np.abs(got[:, sl] - ref).max() <= 1e-12 * np.abs(ref).max()
+            assert np.abs(en[r] - en_ref).max() <= 1e-12 * np.abs(en_ref).max()
+            continue
+        _check_run(oracle, parts[r], q[sl], m[sl], traps[r], 1e-9, nsteps, got[:, sl], en[r], every, f"run {r} n={n}")
+    assert api.poll_flags() == 0
+
+
+@pytest.mark.parametrize("path", [STEPPED4, STEPPED8], ids=lambda p: "-".join(map(str, p)))
+def test_stepped_equals_persistent_and_is_deterministic(api, path):
+    """A Kibble-Zurek-shaped ensemble (40 runs, N uniform in [64, 4096], the
+    ramp) on both paths: trajectories agree to rounding (different summation
+    orders), and the stepped path repeats bit for bit.  Also without
+    CB_INIT_ACCEL (the state's a is used as a_0)."""
+    import torch
+    from _gpu_util import dev
+    d = inputs.kz512(nrun=40, nmin=64, nmax=4096, nsteps=6)
+    st = inputs.state9(d)
+    q, m, offs = dev(d["q"]), dev(d["m"]), d["offsets"]
+    runs = {}
+    for tag, pth, init in (("persistent", PERSISTENT, True), ("stepped", path, True), ("again", path, True),
+                           ("persistent_a0", PERSISTENT, False), ("stepped_a0", path, False)):
+        ts = [dev(st[k]) for k in range(9)]
+        if not init:  # a_0 from one force evaluation of the start state (same on both paths)
+            a0 = [dev(st[k]) for k in range(9)]
+            with _path(api, offs[-1], "fp64", PERSISTENT):
+                api.md_run(a0, q, m, d["traps"], 0.0, d["dt"], 0, offsets=offs)
+            for k in range(6, 9):
+                ts[k].copy_(a0[k])
+        with _path(api, offs[-1], "fp64", pth):
+            en = api.md_run(ts, q, m, d["traps"], 0.0, d["dt"], d["nsteps"], offsets=offs, every=3,
+                            init_accel=init)
+        torch.cuda.synchronize()
+        runs[tag] = (np.stack([t.cpu().numpy() for t in ts]), en.cpu().numpy())
+    assert api.poll_flags() == 0
+    assert np.array_equal(runs["stepped"][0], runs["again"][0])
+    assert np.array_equal(runs["stepped"][1], runs["again"][1])
+    for a, b in (("persistent", "stepped"), ("persistent_a0", "stepped_a0")):
+        ga, gb = runs[a][0], runs[b][0]
+        for blk in (slice(0, 3), slice(3, 6), slice(6, 9)):
+            scale = np.abs(ga[blk]).max()
+            err = np.abs(ga[blk] - gb[blk]).max()
+            print(f"[{a} vs {b}] block {blk.start}: max diff {err / scale:.2e} of scale", flush=True)
+            assert err <= 1e-11 * scale, (a, b, blk, err / scale)
+        ea, eb = runs[a][1], runs[b][1]
+        assert np.abs(ea - eb).max() <= 1e-11 * np.abs(ea).max()
