@@ -244,7 +244,9 @@ const char* cb_last_error(void);
  * size, j-split count) of `op` at n ions and precision prec on the current
  * device, keeps the fastest for all later calls with n in the same
  * power-of-two bucket, and, when cache_path is non-NULL, merges it into that
- * JSON-lines file.  Uses synthetic inputs it allocates itself (this call, and
+ * JSON-lines file.  For md_step / md_run at n <= 8192 the force kernel is
+ * tuned for coulomb_forces, and the j-parts of the one-launch step
+ * (algorithm 3) for the md calls.  Uses synthetic inputs it allocates itself (this call, and
  * cb_load_tuning, are the only ones that allocate).  Synchronous. */
 cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_path);
 
@@ -255,10 +257,15 @@ cb_status cb_load_tuning(const char* cache_path);
  * out[0] = algorithm (0: every ordered pair evaluated, j-split partial sums;
  *          1: each unordered pair evaluated once and applied to both ions by
  *          Newton's third law, forces only, n <= 2^18, the reactions summed
- *          over the wave by cross-lane permutes; 2: as 1, summed through LDS),
+ *          over the wave by cross-lane permutes; 2: as 1, summed through LDS;
+ *          3: md_step / md_run of one run of at most 8192 ions in one launch
+ *          per step, every ordered pair evaluated by one wave per 64 ions and
+ *          j-part, the parts added in a fixed order by the last to finish,
+ *          then trap, kick and drift -- the default up to 512 ions),
  * out[1] = i-particles per lane, out[2] = workgroup size (algorithm 0) or
  *          j's per reduction group (algorithm 1),
- * out[3] = j-splits (algorithm 0) or j-segment length (algorithm 1),
+ * out[3] = j-splits (algorithm 0), j-segment length (algorithms 1, 2) or
+ *          j-parts per 64 ions (algorithm 3),
  * out[4] = 1 if it came from tuning or cb_set_config. */
 cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]);
 
@@ -266,7 +273,8 @@ cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]);
  * the fields of cb_get_config.  Algorithm 0: p in {1,2,4} ({1,2} for the HVP
  * and adjoint), wg in {64,128,256}, splits in 1..64.  Algorithms 1 and 2 (forces,
  * md_step, md_run; n <= 2^18): p in {2,3,4,5,6,8}, wg = j's per reduction
- * group = 4, splits = segment length in {256,512,1024,2048}.
+ * group = 4, splits = segment length in {256,512,1024,2048}.  Algorithm 3
+ * (md_step, md_run; n <= 8192): p = 1, wg = 64, splits = j-parts in 1..32.
  * For CB_OP_MD_ENSEMBLE (n = total ions): algorithm 0 with p = 4, wg = 512,
  * splits = 1 (the persistent kernel's fixed shape), or algorithm 2 with p in
  * {4, 8}, wg = 4, splits = JL in {256, 512}.

@@ -159,17 +159,71 @@ cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_pat
             }
         (void)hipStreamSynchronize(st);
     }
+    // md_step / md_run of at most kSmallRunMax ions: whole steps (md_run on
+    // the synthetic cloud at rest) of the two-launch step with the best force
+    // configuration and of the one-launch step for each j-part count; the
+    // faster is kept for the md calls.
+    const bool md_op = (op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
+    LaunchCfg md_best = best;
+    float md_ms = 1e30f;
+    if (rc == CB_OK && md_op && n <= kSmallRunMax) {
+        DevBuf state, mass, mws;
+        const size_t need = cb_workspace_size(CB_OP_MD_RUN, n, 1, 1, prec);
+        if (hipMalloc(&state.p, sizeof(double) * 9 * (size_t)n) != hipSuccess ||
+            hipMalloc(&mass.p, sizeof(double) * (size_t)n) != hipSuccess || hipMalloc(&mws.p, need) != hipSuccess)
+            rc = fail(CB_EHIP, "cb_autotune: allocation failed");
+        std::vector<double> hs(9 * (size_t)n, 0.0), hm((size_t)n, 6.6421562664e-26);  // at rest, 40 u
+        std::copy(h.begin(), h.begin() + 3 * (size_t)n, hs.begin());
+        if (!rc && (hipMemcpy(state.p, hs.data(), sizeof(double) * hs.size(), hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(mass.p, hm.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice) != hipSuccess))
+            rc = fail(CB_EHIP, "cb_autotune: upload failed");
+        double* sp = static_cast<double*>(state.p);
+        const cb_state s9{sp, sp + n, sp + 2 * n, sp + 3 * n, sp + 4 * n, sp + 5 * n, sp + 6 * n, sp + 7 * n, sp + 8 * n};
+        cb_trap tr{};
+        tr.wx = tr.wy = 6.283185307179586e6;
+        tr.wz = 1.2566370614359172e6;
+        const int64_t offs[2] = {0, n};
+        std::vector<LaunchCfg> cands{best};
+        for (int S = 1; S <= kSmallPartsMax && (S == 1 || n / S >= 16); S *= 2) cands.push_back({1, 64, S, 1, ALGO_SMALL});
+        for (const LaunchCfg& c : cands) {
+            if (rc) break;
+            put_cfg(CB_OP_MD_RUN, n, prec, c);
+            auto launch = [&]() {
+                return md_run(1, offs, &s9, q, static_cast<const double*>(mass.p), &tr, 0.0, 1e-9, 8, 0.0, prec,
+                              CB_INIT_ACCEL, nullptr, 0, mws.p, need, st);
+            };
+            if ((rc = launch())) break;
+            (void)hipEventRecord(e0, st);
+            rc = launch();
+            (void)hipEventRecord(e1, st);
+            if (rc || hipEventSynchronize(e1) != hipSuccess) {
+                if (!rc) rc = fail(CB_EHIP, "cb_autotune: timing failed");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < md_ms) {
+                md_ms = ms;
+                md_best = c;
+            }
+        }
+        drop_cfg(CB_OP_MD_RUN, n, prec);
+        (void)hipStreamSynchronize(st);
+    }
     (void)hipStreamSynchronize(st);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(st);
     if (rc) return rc;
     if (best.p == 0) return fail(CB_EHIP, "cb_autotune: no candidate ran");
-    // forces, md_step and md_run share the force kernel
-    if (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN) {
+    // forces, md_step and md_run share the force kernel; md_step and md_run
+    // of at most kSmallRunMax ions get the faster whole step
+    if (op == CB_OP_FORCES || md_op) {
         put_cfg(CB_OP_FORCES, n, prec, best);
-        put_cfg(CB_OP_MD_STEP, n, prec, best);
-        put_cfg(CB_OP_MD_RUN, n, prec, best);
+        if (md_op || n > kSmallRunMax) {
+            put_cfg(CB_OP_MD_STEP, n, prec, md_best);
+            put_cfg(CB_OP_MD_RUN, n, prec, md_best);
+        }
     } else if (hv) {
         put_cfg(CB_OP_HVP, n, prec, best);
         put_cfg(CB_OP_ADJOINT, n, prec, best);
@@ -179,11 +233,14 @@ cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_pat
     if (cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (!f) return fail(CB_EINVAL, "cb_autotune: cannot open %s", cache_path);
-        std::fprintf(f,
-                     "{\"arch\": \"%s\", \"op\": %d, \"prec\": %d, \"bucket\": %d, \"n\": %lld, \"p\": %d, "
-                     "\"wg\": %d, \"splits\": %d, \"algo\": %d, \"ms\": %.6f}\n",
-                     arch_name().c_str(), op, prec, n_bucket(n), (long long)n, best.p, best.wg, best.splits, best.algo,
-                     best_ms);
+        auto line = [&](int o, const LaunchCfg& c, float ms) {
+            std::fprintf(f,
+                         "{\"arch\": \"%s\", \"op\": %d, \"prec\": %d, \"bucket\": %d, \"n\": %lld, \"p\": %d, "
+                         "\"wg\": %d, \"splits\": %d, \"algo\": %d, \"ms\": %.6f}\n",
+                         arch_name().c_str(), o, prec, n_bucket(n), (long long)n, c.p, c.wg, c.splits, c.algo, ms);
+        };
+        line(op, best, best_ms);
+        if (md_op && n <= kSmallRunMax) line(CB_OP_MD_RUN, md_best, md_ms);
         std::fclose(f);
     }
     return ok();
@@ -209,9 +266,16 @@ cb_status cb_load_tuning(const char* cache_path) {
         LaunchCfg c{p, wg, sp, 1, algo};
         if (!valid_cfg(op, c)) continue;
         if (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN) {
-            put_cfg(CB_OP_FORCES, n, prec, c);
-            put_cfg(CB_OP_MD_STEP, n, prec, c);
-            put_cfg(CB_OP_MD_RUN, n, prec, c);
+            // as cb_autotune: a forces line also sets the md calls above
+            // kSmallRunMax ions; an md line sets the md calls (and forces,
+            // unless it is the one-launch step)
+            const bool md_line = op != CB_OP_FORCES;
+            if (c.algo == ALGO_SMALL && n > kSmallRunMax) continue;
+            if (c.algo != ALGO_SMALL) put_cfg(CB_OP_FORCES, n, prec, c);
+            if (md_line || n > kSmallRunMax) {
+                put_cfg(CB_OP_MD_STEP, n, prec, c);
+                put_cfg(CB_OP_MD_RUN, n, prec, c);
+            }
         } else if (op == CB_OP_HVP || op == CB_OP_ADJOINT) {
             put_cfg(CB_OP_HVP, n, prec, c);
             put_cfg(CB_OP_ADJOINT, n, prec, c);

@@ -84,6 +84,12 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
                            double t0, double dt, int64_t nsteps, double eps2, int32_t prec, uint32_t flags,
                            double* energies, int64_t every, void* ws, int op, hipStream_t st) {
     const WsLayout L = ws_layout(op, n, 1, 1);
+    // One launch per step (every pair direct, then trap, kick and drift) when
+    // so configured: the default up to kSmallRunMax ions.
+    const LaunchCfg sc = get_cfg(op, n, prec);
+    if (sc.algo == ALGO_SMALL && n <= kSmallRunMax && md_small_ws_bytes(n, sc.splits) <= L.ppot - L.part)
+        return md_run_small(n, s, q, m, trap, t0, dt, nsteps, eps2, prec, flags, energies, every, sc.splits,
+                            static_cast<char*>(ws) + L.part, L.ppot - L.part, st);
     const PairRun pr = plan(op, n, prec);
     double* part = at(ws, L.part);
     double* ppot = at(ws, L.ppot);

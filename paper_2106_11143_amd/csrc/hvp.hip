@@ -8,6 +8,7 @@
 
 #include "hvp_kernels.hpp"
 #include "internal.hpp"
+#include "split_sum.hpp"
 #include "step_common.hpp"
 
 namespace cb {
@@ -67,16 +68,20 @@ __global__ void __launch_bounds__(kEpiThreads) k_hvp_epi(int n, int S, int nv, c
     const double c = kCoulomb * q[i];
     const double kk[3] = {k.kx, k.ky, k.kz};
     bool ok = true;
-    for (int b = 0; b < nv; ++b)
+    const size_t stride = (size_t)nv * 3 * n;
+    for (int b = 0; b < nv; ++b) {
+        double s[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) s[d] = split_sum(part + ((size_t)b * 3 + d) * n + i, stride, S);
+#pragma unroll
         for (int d = 0; d < 3; ++d) {
-            double s = 0.0;
-            for (int sp = 0; sp < S; ++sp) s += part[(((size_t)sp * nv + b) * 3 + d) * n + i];
-            double h = c * s;
+            double h = c * s[d];
             const size_t e = ((size_t)b * 3 + d) * n + i;
             if (m) h += m[i] * kk[d] * v[e];
             hv[e] = h;
             ok = ok && __builtin_isfinite(h);
         }
+    }
     if (!ok) atomicOr(flags, 1u);
 }
 
@@ -114,9 +119,11 @@ __global__ void __launch_bounds__(kEpiThreads) k_adj_post(int n, int S, const do
         } else {
             const double kk[3] = {k.kx, k.ky, k.kz};
             const double cq = kCoulomb * q[i];
+            double ss[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ss[c] = split_sum(part + (size_t)c * n + i, 3 * (size_t)n, S);
             for (int c = 0; c < 3; ++c) {
-                double s = 0.0;
-                for (int sp = 0; sp < S; ++sp) s += part[((size_t)sp * 3 + c) * n + i];
+                const double s = ss[c];
                 const size_t e = (size_t)c * n + i;
                 const double hu = cq * s + m[i] * kk[c] * u[e];
                 const double lr = lam[e], lv = lam[3 * (size_t)n + e], la = lam[6 * (size_t)n + e];

@@ -20,7 +20,9 @@ constexpr int64_t kSymMaxN = int64_t(1) << 18;  // largest n for the symmetric k
 
 // ALGO_SYM and ALGO_SYM_LDS differ only in how the per-j reactions are summed
 // over the wave (cross-lane permutes and DPP, or LDS).
-enum : int { ALGO_DIRECT = 0, ALGO_SYM = 1, ALGO_SYM_LDS = 2 };
+// ALGO_SMALL (md_step / md_run of one run of at most kSmallRunMax ions):
+// one launch per step, every pair direct (md_run_small).
+enum : int { ALGO_DIRECT = 0, ALGO_SYM = 1, ALGO_SYM_LDS = 2, ALGO_SMALL = 3 };
 
 constexpr bool is_sym(int algo) { return algo == ALGO_SYM || algo == ALGO_SYM_LDS; }
 
@@ -94,6 +96,18 @@ cb_status md_run_ensemble(int32_t nrun, const int64_t* offsets, const cb_state* 
                           const double* m, const cb_trap* traps, double t0, double dt, int64_t nsteps, double eps2,
                           int32_t prec, uint32_t flags, double* energies, int64_t every, int P, int JL, void* ws,
                           size_t ws_bytes, hipStream_t st);
+
+// One run of at most kSmallRunMax ions in one launch per step
+// (ensemble.hip), with S j-parts per 64 ions (1..kSmallPartsMax): workspace
+// bytes, the default S and the driver.
+constexpr int64_t kSmallRunMax = 8192;
+constexpr int64_t kSmallRunDefault = 512;  // largest run that takes it by default
+constexpr int kSmallPartsMax = 32;
+size_t md_small_ws_bytes(int64_t n, int S);
+int small_parts(int64_t n);
+cb_status md_run_small(int64_t n, const cb_state* s, const double* q, const double* m, const cb_trap* trap,
+                       double t0, double dt, int64_t nsteps, double eps2, int32_t prec, uint32_t flags,
+                       double* energies, int64_t every, int S, void* ws, size_t ws_bytes, hipStream_t st);
 
 // Batched md_run (batched.hip): picks the persistent kernel or the stepped
 // ensemble path.

@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "split_sum.hpp"
 #include "step_common.hpp"
 
 namespace cb {
@@ -41,14 +42,12 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
         double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
         const bool need_f = (mode & (EPI_FORCES | EPI_ACCEL | EPI_KICK)) != 0;
         const bool need_p = (mode & EPI_ENERGY) && P.ppot != nullptr;
-        if (need_f)
-            for (int s = 0; s < P.S; ++s) {
-                sx += P.part[(size_t)(s * 3 + 0) * n + i];
-                sy += P.part[(size_t)(s * 3 + 1) * n + i];
-                sz += P.part[(size_t)(s * 3 + 2) * n + i];
-            }
-        if (need_p)
-            for (int s = 0; s < P.S; ++s) sp += P.ppot[(size_t)s * n + i];
+        if (need_f) {
+            sx = split_sum(P.part + i, 3 * (size_t)n, P.S);
+            sy = split_sum(P.part + n + i, 3 * (size_t)n, P.S);
+            sz = split_sum(P.part + 2 * (size_t)n + i, 3 * (size_t)n, P.S);
+        }
+        if (need_p) sp = split_sum(P.ppot + i, (size_t)n, P.S);
         const double c = kCoulomb * P.q[i];
         const double cf = (mode & EPI_PRESCALED) ? 1.0 : c;
         const double Fx = cf * sx, Fy = cf * sy, Fz = cf * sz;

@@ -177,7 +177,20 @@ def test_symmetric_config_validation(api):
     assert (c["algo"], c["p"], c["wg"], c["splits"], c["tuned"]) == (1, 3, 4, 2048, True)
     api.reset_config("md_run", 50000, "fp64")
     assert api.get_config("md_run", 50000, "fp64")["algo"] == 2  # the default at this size
+    c = api.get_config("md_run", 300, "fp64")  # small runs: one launch per step
+    assert (c["algo"], c["p"], c["wg"], c["splits"], c["tuned"]) == (3, 1, 64, 8, False)
+    assert api.get_config("forces", 300, "fp64")["algo"] == 0
     assert api.get_config("md_run", 1000, "fp64")["algo"] == 0
+    assert api.get_config("md_run", 10000, "fp64")["algo"] == 0
+    api.set_config("md_step", 8192, "fp64", p=1, wg=64, splits=7, algo=3)
+    assert api.get_config("md_step", 8192, "fp64")["splits"] == 7
+    api.reset_config("md_step", 8192, "fp64")
+    for bad in (dict(op="forces", n=1000, p=1, wg=64, splits=8),  # md_step / md_run only
+                dict(op="md_run", n=8193, p=1, wg=64, splits=8),  # beyond the small-run limit
+                dict(op="md_run", n=1000, p=1, wg=64, splits=33),
+                dict(op="md_run", n=1000, p=2, wg=64, splits=8)):
+        with pytest.raises(api.CoulombError):
+            api.set_config(bad["op"], bad["n"], "fp64", p=bad["p"], wg=bad["wg"], splits=bad["splits"], algo=3)
     assert api.get_config("energy", 50000, "fp64")["algo"] == 0  # the potential needs every ordered pair
     for algo in (1, 2):
         for p in (2, 3, 4, 5, 6, 8):

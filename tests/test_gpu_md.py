@@ -181,13 +181,16 @@ def test_md_run_with_friction_matches_oracle(api, oracle, n, every):
     assert v_f < v_0
 
 
-def test_md_run_captured_in_a_hip_graph_replays_bitwise(api):
-    """The single-run md_run enqueues kernels only (no memset, no host sync),
-    so a caller can capture it in a HIP graph: every replay, with eager work
-    in between, equals the eager run bitwise (state and energy records)."""
+@pytest.mark.parametrize("n", [1024, 256])
+def test_md_run_captured_in_a_hip_graph_replays_bitwise(api, n):
+    """The single-run md_run enqueues kernels and device copies only (no
+    memset, no host sync), so a caller can capture it in a HIP graph: every
+    replay, with eager work in between, equals the eager run bitwise (state
+    and energy records).  At 1024 ions the two-launch step, at 256 the
+    one-launch step."""
     import torch
     from _gpu_util import dev, state_tensors
-    d = inputs.cloud1024()
+    d = inputs.cloud1024(n=n)
     st = inputs.state9(d)
     q, m = dev(d["q"]), dev(d["m"])
     nsteps = 40
@@ -213,3 +216,51 @@ def test_md_run_captured_in_a_hip_graph_replays_bitwise(api):
         other = state_tensors(st)  # eager work between replays
         api.md_run(other, q, m, d["trap"], 0.0, d["dt"], 5)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1000, 4097, 8192])
+def test_small_run_path_matches_two_launch_path_and_oracle(api, oracle, n):
+    """Runs of at most 8192 ions can take one launch per step (algorithm 3:
+    every pair of the run evaluated directly by one wave per 64 ions and
+    j-part, then trap, kick and drift; the default up to 512 ions) or the
+    two-launch step (algorithm 0).  Both agree to rounding, with and without
+    CB_INIT_ACCEL, on an RF trap with friction, energies every other step;
+    small runs also against the oracle."""
+    import torch
+    from _gpu_util import dev, state_host, state_tensors
+    g = np.random.Generator(np.random.PCG64(1000 + n))
+    trap = dict(inputs.rf_trap(0.0, 0.3, 10e6, 0.2e6), gamma=2e5 * M40)
+    sig = inputs.crystal_sigma(max(n, 2), 2 * math.pi * 0.5e6, 2 * math.pi * 0.5e6, trap["wz"])
+    st = np.zeros((9, n))
+    st[:3] = g.normal(size=(3, n)) * sig[:, None]
+    st[3:6] = inputs.maxwell(g, n, 10e-3, M40)
+    st[6:9] = g.normal(size=(3, n)) * 1e9  # a_0 used as given without CB_INIT_ACCEL
+    q = np.full(n, E)
+    q[::5] *= 2.0
+    m = np.full(n, M40)
+    dt, nsteps, every = 5e-9, 12, 2
+    res = {}
+    for path in ("small", "two-launch"):
+        for init in (True, False):
+            if path == "two-launch":
+                api.set_config("md_run", n, "fp64", p=1, wg=64, splits=max(1, min(16, n // 64)), algo=0)
+            else:
+                api.set_config("md_run", n, "fp64", p=1, wg=64, splits=max(1, min(8, n // 32)), algo=3)
+            ts = state_tensors(st)
+            en = api.md_run(ts, dev(q), dev(m), trap, 0.0, dt, nsteps, every=every, init_accel=init)
+            torch.cuda.synchronize()
+            api.reset_config("md_run", n, "fp64")
+            res[path, init] = (state_host(ts), en.cpu().numpy()[0])
+    assert api.poll_flags() == 0
+    for init in (True, False):
+        a, b = res["small", init], res["two-launch", init]
+        for blk in (slice(0, 3), slice(3, 6), slice(6, 9)):
+            scale = np.abs(b[0][blk]).max()
+            assert np.abs(a[0][blk] - b[0][blk]).max() <= 1e-12 * scale, (n, init, blk)
+        assert np.abs(a[1] - b[1]).max() <= 1e-12 * np.abs(b[1]).max(), (n, init)
+    if n <= 1000:  # the oracle at full size
+        ref, en_ref, _ = oracle.md_run(st, q, m, trap, 0.0, dt, nsteps, every=every)
+        got, en = res["small", True]
+        for blk in (slice(0, 3), slice(3, 6), slice(6, 9)):
+            assert np.abs(got[blk] - ref[blk]).max() <= 1e-11 * np.abs(ref[blk]).max(), (n, blk)
+        assert np.abs(en - en_ref).max() <= 1e-11 * np.abs(en_ref).max()
