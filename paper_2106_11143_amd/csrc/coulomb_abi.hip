@@ -117,10 +117,15 @@ LaunchCfg default_cfg(int op, int64_t n, int prec) {
     c.p = 1;
     const int64_t waves = (n + 64 * c.p - 1) / (64 * c.p);
     // HVP-shaped work (more registers per lane, fewer waves per SIMD) runs
-    // best with longer j-ranges per wave: about 2048 waves over the launch
-    // instead of 65536 (measured on MI355X at n = 8192: 16 splits).
+    // best with longer j-ranges per wave: about 3072 waves over the launch
+    // in 256-thread workgroups (measured on MI355X at n = 8192: 24 splits,
+    // 0.41 ms for 8 vectors against 0.53 with 16 splits of 64 threads).
+    // Below 16384 ions the force kernel, too, prefers about 4096 waves in
+    // 256-thread workgroups (md steps at 4096 and 8192 ions).
     const bool hv = (op == CB_OP_HVP || op == CB_OP_ADJOINT);
-    int64_t s = ((hv ? 2048 : 65536) + waves - 1) / waves;
+    const bool small = n < 16384;
+    if (hv || small) c.wg = 256;
+    int64_t s = ((hv ? 3072 : (small ? 4096 : 65536)) + waves - 1) / waves;
     s = std::max<int64_t>(1, std::min<int64_t>(s, kMaxSplits));
     s = std::min<int64_t>(s, std::max<int64_t>(1, n / 64));
     c.splits = (int)s;
