@@ -101,37 +101,26 @@ def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, max_iter=100000, method="l
         S, Y = [], []
         h0 = 1.0 / (float(m.mean()) * wmax * wmax)
         cap = 0.2 * a
+        fmax = float(g.norm(dim=0).max())
         for it in range(max_iter):
-            if float(g.norm(dim=0).max()) <= tol:
+            if fmax <= tol:
                 break
-            z = g.clone()
-            al = []
-            for s, y in reversed(list(zip(S, Y))):
-                a_ = float((s * z).sum()) / float((y * s).sum())
-                al.append(a_)
-                z = z - a_ * y
-            gamma = float((S[-1] * Y[-1]).sum()) / float((Y[-1] * Y[-1]).sum()) if S else h0
-            z = gamma * z
-            for (s, y), a_ in zip(zip(S, Y), reversed(al)):
-                b = float((y * z).sum()) / float((y * s).sum())
-                z = z + (a_ - b) * s
-            p = -z
-            gp = float((g * p).sum())
+            p = lbfgs_direction(g, S, Y, h0)
+            Hp = api.coulomb_hvp(*_rows(r), q, p.contiguous(), m, trap, 0.0, eps2)
+            gp, pHp = torch.stack([(g * p).sum(), (p * Hp).sum()]).tolist()
             if gp >= 0:  # not a descent direction: restart from steepest descent
                 S.clear()
                 Y.clear()
                 p = -h0 * g
-                gp = float((g * p).sum())
-            Hp = api.coulomb_hvp(*_rows(r), q, p.contiguous(), m, trap, 0.0, eps2)
-            pHp = float((p * Hp).sum())
+                Hp = api.coulomb_hvp(*_rows(r), q, p.contiguous(), m, trap, 0.0, eps2)
+                gp, pHp = torch.stack([(g * p).sum(), (p * Hp).sum()]).tolist()
             step = (-gp / pHp if pHp > 0 else 1.0) * p
-            mx = float(step.norm(dim=0).max())
-            if mx > cap:
-                step = step * (cap / mx)
+            step = step * torch.clamp(cap / step.norm(dim=0).max(), max=1.0)  # at most `cap` per ion
             r = r + step
             gn = -total_force(r, q, m, trap, 0.0, eps2)
             y = gn - g
-            if float((step * y).sum()) > 0:
+            sy, fmax = torch.stack([(step * y).sum(), gn.norm(dim=0).max()]).tolist()
+            if sy > 0:
                 S.append(step)
                 Y.append(y)
                 if len(S) > memory:
@@ -140,6 +129,30 @@ def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, max_iter=100000, method="l
             g = gn
     info = {"method": method, "iters": it, "fmax_rel": float(g.norm(dim=0).max()) / fscale, "force_scale": fscale}
     return r, info
+
+
+def lbfgs_direction(g, S, Y, h0):
+    """-H g for the L-BFGS inverse-Hessian approximation H built from the
+    curvature pairs (s_i, y_i), oldest first (s_i . y_i > 0), with H_0 =
+    gamma I, gamma = s.y / y.y of the newest pair (h0 without pairs): the
+    two-loop recursion (Nocedal and Wright, Algorithm 7.4), with every scalar
+    kept on the device, so that the 4m dependent dot products cost kernel
+    launches and no host synchronisation."""
+    if not S:
+        return -h0 * g
+    z = g.reshape(-1).clone()
+    ss = [s.reshape(-1) for s in S]
+    ys = [y.reshape(-1) for y in Y]
+    rho = [1.0 / torch.dot(y, s) for s, y in zip(ss, ys)]
+    al = []
+    for s, y, r in zip(reversed(ss), reversed(ys), reversed(rho)):
+        a = r * torch.dot(s, z)
+        al.append(a)
+        z = torch.addcmul(z, a, y, value=-1.0)
+    z = z * (torch.dot(ss[-1], ys[-1]) / torch.dot(ys[-1], ys[-1]))
+    for s, y, r, a in zip(ss, ys, rho, reversed(al)):
+        z = torch.addcmul(z, a - r * torch.dot(y, z), s)
+    return -z.reshape(g.shape)
 
 
 def _band_ritz(band, k):

@@ -94,3 +94,33 @@ def test_block_lanczos_resolves_exactly_degenerate_modes():
     V = vecs.numpy().reshape(6, -1)
     assert np.abs(V @ V.T - np.eye(6)).max() <= 1e-9
     assert np.abs(V @ H - lam[:, None] * V).max() <= 1e-8 * lam0.max()
+
+
+def test_lbfgs_direction_matches_the_two_loop_recursion():
+    """The device-scalar L-BFGS inverse-Hessian product against the two-loop
+    recursion written out with host floats, on curvature pairs of a random
+    symmetric positive definite quadratic; with one pair and H itself
+    quadratic, H s = y is reproduced (the secant condition)."""
+    import torch
+    from paper_2106_11143_amd import drivers
+    g_ = np.random.default_rng(5)
+    n, k = 40, 7
+    B = g_.standard_normal((3 * n, 3 * n))
+    H = B @ B.T + 3 * n * np.eye(3 * n)
+    S = [torch.as_tensor(g_.standard_normal((3, n))) for _ in range(k)]
+    Y = [torch.as_tensor((H @ s.numpy().reshape(-1)).reshape(3, n)) for s in S]
+    g = torch.as_tensor(g_.standard_normal((3, n)))
+    got = drivers.lbfgs_direction(g, S, Y, 0.1)
+    z, al = g.clone(), []
+    for s, y in reversed(list(zip(S, Y))):
+        a = float((s * z).sum()) / float((y * s).sum())
+        al.append(a)
+        z = z - a * y
+    z = z * float((S[-1] * Y[-1]).sum()) / float((Y[-1] * Y[-1]).sum())
+    for (s, y), a in zip(zip(S, Y), reversed(al)):
+        z = z + (a - float((y * z).sum()) / float((y * s).sum())) * s
+    assert torch.allclose(got, -z, rtol=1e-10, atol=1e-12 * float(z.abs().max()))
+    assert torch.equal(drivers.lbfgs_direction(g, [], [], 0.1), -0.1 * g)
+    # secant condition of the newest pair: H y_last = s_last
+    hy = -drivers.lbfgs_direction(Y[-1], S, Y, 0.1)
+    assert torch.allclose(hy, S[-1], rtol=1e-9, atol=1e-12 * float(S[-1].abs().max()))
