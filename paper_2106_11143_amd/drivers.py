@@ -188,6 +188,23 @@ def _band_ritz(band, k):
     return theta, S
 
 
+def _tsmm(A, W, P=64):
+    """A^T W for a tall A (K, c) -- also a column slice of a wider matrix --
+    and W (K, b).  K is cut into P blocks whose products run as one batched
+    GEMM and are then summed: a single GEMM with K ~ 1e4 and a small output
+    runs on one workgroup's worth of the chip and takes milliseconds (2.6 ms
+    for 8 x 8 at K = 24576 on MI355X, 0.03 ms this way)."""
+    K = A.shape[0]
+    K0 = K // P * P
+    if K0 == 0:
+        return A.T @ W
+    out = torch.bmm(W[:K0].reshape(P, K0 // P, W.shape[1]).transpose(1, 2).contiguous(),
+                    A[:K0].reshape(P, K0 // P, A.shape[1])).sum(0).T
+    if K0 < K:
+        out = out + A[K0:].T @ W[K0:]
+    return out
+
+
 def lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=12000, eps2=0.0, seed=0, tol=1e-8, check_every=20,
                    hvp=None):
     """Lowest k eigenpairs of the mass-weighted Hessian M^-1/2 H M^-1/2 of
@@ -222,17 +239,18 @@ def lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=12000, eps2=0.0, seed=0,
     Bprev = None
     theta = S = res = None
     used = 0
+    next_check = check_every
     for j in range(nblk):
         c0, c1 = j * block, (j + 1) * block
         Qj = Q[:, c0:c1]
         W = A(Qj)
         if Bprev is not None:
             W = W - Q[:, c0 - block:c0] @ Bprev.T
-        Aj = Qj.T @ W
+        Aj = _tsmm(Qj, W)
         Aj = 0.5 * (Aj + Aj.T)
         W = W - Qj @ Aj
         for _ in range(2):
-            W = W - Q[:, :c1] @ (Q[:, :c1].T @ W)
+            W = W - Q[:, :c1] @ _tsmm(Q[:, :c1], W)
         Qn, Bj = torch.linalg.qr(W)
         Q[:, c1:c1 + block] = Qn
         Ah, Bh = Aj.cpu().numpy(), Bj.cpu().numpy()
@@ -245,12 +263,15 @@ def lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=12000, eps2=0.0, seed=0,
                     band[block + a_ - b_, c0 + b_] = Bh[a_, b_]
         Bprev = Bj
         used = c1
-        if (j + 1) % check_every == 0 or j == nblk - 1:
+        if j + 1 >= next_check or j == nblk - 1:
             kk = min(k, used)
             theta, S = _band_ritz(band[:, :used], kk)
             res = np.linalg.norm(Bh @ S[used - block:used, :], axis=0)
             if np.all(res <= tol * max(abs(theta[-1]), 1e-300)):
                 break
+            # the check (a banded eigenvalue solve, O(basis^2)) outgrows the
+            # blocks between checks: space the checks geometrically
+            next_check = max(j + 1 + check_every, int(1.25 * (j + 1)))
     Y = Q[:, :used] @ torch.as_tensor(S, dtype=dt, device=dev)
     info = {"basis": used, "max_residual": float(res.max()), "theta_k": float(theta[-1])}
     return (torch.as_tensor(theta, dtype=dt, device=dev), Y.T.reshape(-1, 3, n),

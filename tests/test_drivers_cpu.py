@@ -124,3 +124,20 @@ def test_lbfgs_direction_matches_the_two_loop_recursion():
     # secant condition of the newest pair: H y_last = s_last
     hy = -drivers.lbfgs_direction(Y[-1], S, Y, 0.1)
     assert torch.allclose(hy, S[-1], rtol=1e-9, atol=1e-12 * float(S[-1].abs().max()))
+
+
+def test_split_k_product_equals_plain_product():
+    """A^T W by blocks of K summed (Lanczos reorthogonalisation) against the
+    plain product: K a multiple of the block count and not, a column slice of
+    a wider matrix, and K below one block."""
+    import torch
+    from paper_2106_11143_amd import drivers
+    g_ = torch.Generator().manual_seed(3)
+    for K in (24576, 900, 40):
+        Q = torch.randn(K, 130, dtype=torch.float64, generator=g_)
+        W = torch.randn(K, 8, dtype=torch.float64, generator=g_)
+        for c in (8, 57, 130):
+            ref = Q[:, :c].T @ W
+            got = drivers._tsmm(Q[:, :c], W)
+            assert got.shape == ref.shape
+            assert torch.allclose(got, ref, rtol=0, atol=1e-13 * float(ref.abs().max()) * (K ** 0.5))
