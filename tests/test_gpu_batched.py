@@ -270,3 +270,75 @@ def test_stepped_equals_persistent_and_is_deterministic(api, path):
             assert err <= 1e-11 * scale, (a, b, blk, err / scale)
         ea, eb = runs[a][1], runs[b][1]
         assert np.abs(ea - eb).max() <= 1e-11 * np.abs(ea).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_stepped_whole_run_blocks_match_oracle(api, oracle, prec):
+    """Every run within one 512-ion i-block (the default shape when no run
+    exceeds 512 ions): no pair launch, the step kernel evaluates each run's
+    pairs directly with 16 waves per 64 ions.  Sizes from 1 to 512, every
+    trap kind and friction, energies every other step, against the oracle
+    run by run and against the persistent kernel."""
+    from _gpu_util import dev
+    base = inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6)
+    kinds = [base, inputs.ramp_trap(1.5e6, 0.6e6, 0.15e6, 0.0, 20e-9),
+             inputs.rf_trap(0.0, 0.3, 10e6, 0.15e6), dict(base, gamma=5e5 * inputs.MASS_40U)]
+    sizes = [1, 5, 64, 100, 257, 512, 333, 65]
+    traps = [kinds[r % 4] for r in range(len(sizes))]
+    parts, offs, q, m = _ensemble(sizes, 31, base)
+    st = np.concatenate(parts, axis=1)
+    nsteps, every = 10, 2
+    got = {}
+    for path in (STEPPED8, PERSISTENT):
+        ts = [dev(st[k]) for k in range(9)]
+        with _path(api, offs[-1], prec, path):
+            en = api.md_run(ts, dev(q), dev(m), traps, 0.0, 1e-9, nsteps, offsets=offs, every=every,
+                            prec=prec).cpu().numpy()
+        got[path] = (np.stack([t.cpu().numpy() for t in ts]), en)
+    assert api.poll_flags() == 0
+    a, b = got[STEPPED8], got[PERSISTENT]
+    for blk in (slice(0, 3), slice(3, 6), slice(6, 9)):
+        assert np.abs(a[0][blk] - b[0][blk]).max() <= 1e-11 * np.abs(b[0][blk]).max()
+    assert np.abs(a[1] - b[1]).max() <= 1e-11 * np.abs(b[1]).max()
+    if prec == "fp64":
+        for r, n in enumerate(sizes):
+            sl = slice(offs[r], offs[r + 1])
+            if n == 1:
+                ref, en_ref, _ = oracle.md_run(parts[r], q[sl], m[sl], traps[r], 0.0, 1e-9, nsteps, every=every)
+                assert np.abs(a[0][:, sl] - ref).max() <= 1e-12 * np.abs(ref).max()
+                assert np.abs(a[1][r] - en_ref).max() <= 1e-12 * np.abs(en_ref).max()
+                continue
+            _check_run(oracle, parts[r], q[sl], m[sl], traps[r], 1e-9, nsteps, a[0][:, sl], a[1][r], every,
+                       f"run {r} n={n}")
+
+
+@pytest.mark.parametrize("path", [STEPPED4, PERSISTENT], ids=lambda p: "-".join(map(str, p)))
+def test_ensemble_zero_steps_and_softening(api, oracle, path):
+    """nsteps = 0 with CB_INIT_ACCEL and a record: the state is unchanged but
+    for a_0, and the one record is the oracle's energy at t0; then a short
+    run with softening eps2 > 0 against the oracle."""
+    from _gpu_util import dev
+    trap = inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6)
+    sizes = [700, 64, 1300]
+    parts, offs, q, m = _ensemble(sizes, 37, trap)
+    st = np.concatenate(parts, axis=1)
+    ts = [dev(st[k]) for k in range(9)]
+    with _path(api, offs[-1], "fp64", path):
+        en = api.md_run(ts, dev(q), dev(m), [trap] * 3, 0.0, 1e-9, 0, offsets=offs, every=1).cpu().numpy()
+    got = np.stack([t.cpu().numpy() for t in ts])
+    assert np.array_equal(got[:6], st[:6])
+    for r in range(3):
+        sl = slice(offs[r], offs[r + 1])
+        ref, en_ref, _ = oracle.md_run(parts[r], q[sl], m[sl], trap, 0.0, 1e-9, 0, every=1)
+        assert np.abs(got[6:, sl] - ref[6:]).max() <= 1e-12 * np.abs(ref[6:]).max()
+        assert np.abs(en[r] - en_ref).max() <= 1e-12 * np.abs(en_ref).max()
+    eps2 = (2e-6) ** 2
+    ts = [dev(st[k]) for k in range(9)]
+    with _path(api, offs[-1], "fp64", path):
+        api.md_run(ts, dev(q), dev(m), [trap] * 3, 0.0, 1e-9, 5, offsets=offs, eps2=eps2)
+    got = np.stack([t.cpu().numpy() for t in ts])
+    for r in range(3):
+        sl = slice(offs[r], offs[r + 1])
+        ref, _, _ = oracle.md_run(parts[r], q[sl], m[sl], trap, 0.0, 1e-9, 5, eps2=eps2)
+        for blk in (slice(0, 3), slice(3, 6), slice(6, 9)):
+            assert np.abs(got[blk, sl] - ref[blk]).max() <= 1e-11 * np.abs(ref[blk]).max(), (r, blk)
