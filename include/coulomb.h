@@ -203,7 +203,10 @@ cb_status md_step(int64_t n, const cb_state* s, const double* q, const double* m
  * step is shorter than the stepped path's launch latency), with p = 8,
  * JL = 512 when no run exceeds 512 ions, else p = 4, JL = 256.  Both paths
  * give the same trajectories up to rounding (different summation orders);
- * each is deterministic. */
+ * each is deterministic.  Both copy run tables from host memory, so md_run
+ * with nrun > 1 returns CB_EUNSUPPORTED on a stream that is being captured
+ * into a graph; with nrun = 1 it enqueues kernels and device copies only
+ * and may be captured. */
 cb_status md_run(int32_t nrun, const int64_t* offsets, const cb_state* s, const double* q, const double* m,
                  const cb_trap* traps, double t0, double dt, int64_t nsteps, double eps2, int32_t prec,
                  uint32_t flags, double* energies, int64_t every, void* ws, size_t ws_bytes, void* stream);

@@ -448,6 +448,13 @@ cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s
                     nmax);
     if (prec != CB_FP64 && prec != CB_MIXED && prec != CB_FP64_IEEE && prec != CB_FP32_RSQ)
         return fail(CB_EINVAL, "md_run: unknown precision %d", prec);
+    // Both ensemble paths copy their run tables from host memory that is
+    // freed on return, which a captured graph would read again on replay.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess)
+        return fail(CB_EHIP, "md_run: stream capture query failed");
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(CB_EUNSUPPORTED, "md_run: several runs cannot be captured in a graph (launch it eagerly)");
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return fail(CB_EHIP, "md_run: device query failed");

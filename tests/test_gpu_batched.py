@@ -342,3 +342,29 @@ def test_ensemble_zero_steps_and_softening(api, oracle, path):
         ref, _, _ = oracle.md_run(parts[r], q[sl], m[sl], trap, 0.0, 1e-9, 5, eps2=eps2)
         for blk in (slice(0, 3), slice(3, 6), slice(6, 9)):
             assert np.abs(got[blk, sl] - ref[blk]).max() <= 1e-11 * np.abs(ref[blk]).max(), (r, blk)
+
+
+def test_ensemble_refuses_graph_capture(api):
+    """md_run with several runs copies its run tables from host memory, so
+    on a capturing stream it fails with CB_EUNSUPPORTED and enqueues
+    nothing; the same call runs eagerly afterwards."""
+    import torch
+    from _gpu_util import dev
+    trap = inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6)
+    sizes = [100, 200]
+    parts, offs, q, m = _ensemble(sizes, 41, trap)
+    st = np.concatenate(parts, axis=1)
+    ts = [dev(st[k]) for k in range(9)]
+    qd, md = dev(q), dev(m)
+    api.md_run(ts, qd, md, [trap] * 2, 0.0, 1e-9, 2, offsets=offs)  # warm-up: workspace
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(api.CoulombError) as err:
+        with torch.cuda.graph(g):
+            api.md_run(ts, qd, md, [trap] * 2, 0.0, 1e-9, 2, offsets=offs)
+    assert err.value.status == api.CB_EUNSUPPORTED
+    torch.cuda.synchronize()
+    ts2 = [dev(st[k]) for k in range(9)]
+    api.md_run(ts2, qd, md, [trap] * 2, 0.0, 1e-9, 2, offsets=offs)
+    torch.cuda.synchronize()
+    assert np.isfinite(np.stack([t.cpu().numpy() for t in ts2])).all()
