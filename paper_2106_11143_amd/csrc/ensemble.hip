@@ -6,10 +6,11 @@
 //      run, one wave per tile, longest tiles first.  A tile entry holds its
 //      run's first ion and size, the slot of its partials, and its row and
 //      segment.
-//   2. k_ens_step: per 64 ions of one run, the finish of the force (pairs
-//      inside the ion's own i-block, the i sums of its row and the reactions
-//      from the rows above, each summed in a fixed order) fused with the trap,
-//      the kick and the next drift.  The drift writes the other of two
+//      Each row's first tile is its diagonal block (the ordered pairs inside
+//      the i-block, evaluated directly).
+//   2. k_ens_step: per 64 ions of one run, the finish of the force (the i
+//      sums of its row and the reactions from the rows above, each summed in
+//      a fixed order) fused with the trap, the kick and the next drift.  The drift writes the other of two
 //      position buffers: other workgroups of the launch still read the
 //      current positions of the same i-block.
 // When no run is longer than an i-block there are no tiles, and the second
@@ -33,6 +34,84 @@
 
 namespace cb {
 
+// Diagonal tile of row I: the ordered pairs inside i-block I (ions b0 ..
+// b1-1; a run's last block may be short) evaluated directly, the self pair
+// skipped, into the i sums Pi[t] (q_i q_j d r^-3, as the row's other tiles).
+// The j data of the next group of 4 are requested before the current group
+// is evaluated; at most 4 rows per lane are held at a time, so the tile fits
+// the register budget of the symmetric tiles it shares a kernel with.  Lanes beyond the block compute on a clamped ion and their
+// sums are never read.
+template <int PREC, int P>
+__device__ __forceinline__ void diag_tile(int n, const double* __restrict__ x, const double* __restrict__ y,
+                                          const double* __restrict__ z, const double* __restrict__ q, double eps2,
+                                          int I, int t, double* __restrict__ Pi) {
+    constexpr int IB = 64 * P;
+    constexpr int H = P < 4 ? P : 4;  // i rows held per pass: the block in P / H passes over its j's
+    const int lane = threadIdx.x;
+    const int b0 = I * IB, b1 = min(n, b0 + IB);
+    double* Pt = Pi + (size_t)t * 3 * IB;
+    const SeriesK K;
+    const int full = b0 + (b1 - b0) / kGroupJ * kGroupJ;
+#pragma unroll 1
+    for (int h = 0; h < P / H; ++h) {
+        double xi[H], yi[H], zi[H], qi[H], ia[H][3];
+        int ii[H];
+#pragma unroll
+        for (int p = 0; p < H; ++p) {
+            ii[p] = b0 + (h * H + p) * 64 + lane;
+            const int ic = min(ii[p], b1 - 1);
+            xi[p] = x[ic];
+            yi[p] = y[ic];
+            zi[p] = z[ic];
+            qi[p] = q[ic];
+            ia[p][0] = ia[p][1] = ia[p][2] = 0.0;
+        }
+        auto group = [&](const JGroup& g, int jg, int live) {
+#pragma unroll
+            for (int u = 0; u < kGroupJ; ++u) {
+#pragma unroll
+                for (int p = 0; p < H; ++p) {
+                    const double dx = xi[p] - g.x[u], dy = yi[p] - g.y[u], dz = zi[p] - g.z[u];
+                    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
+                    double s = sym_s<PREC>(r2, qi[p], K);  // q_i r^-3
+                    if (u >= live || ii[p] == jg + u) s = 0.0;
+                    const double sq = s * g.q[u];
+                    ia[p][0] = __builtin_fma(dx, sq, ia[p][0]);
+                    ia[p][1] = __builtin_fma(dy, sq, ia[p][1]);
+                    ia[p][2] = __builtin_fma(dz, sq, ia[p][2]);
+                }
+                // an empty asm ties each j's updates here, so that only H pairs are in flight
+#pragma unroll
+                for (int p = 0; p < H; ++p) asm volatile("" : "+v"(ia[p][0]), "+v"(ia[p][1]), "+v"(ia[p][2]));
+            }
+        };
+        int jg = b0;
+        if (jg < full) {
+            JGroup cur;
+            load_group<false>(cur, jg, 0, x, y, z, q);
+            for (; jg < full; jg += kGroupJ) {
+                JGroup nxt;
+                const int jn = jg + kGroupJ;
+                load_group<false>(nxt, jn < full ? jn : jg, 0, x, y, z, q);
+                __builtin_amdgcn_sched_barrier(0);  // keep the requests ahead of the arithmetic
+                group(cur, jg, kGroupJ);
+                cur = nxt;
+            }
+        }
+        if (jg < b1) {
+            JGroup tail;
+            load_group<true>(tail, jg, b1 - jg - 1, x, y, z, q);
+            group(tail, jg, b1 - jg);
+        }
+#pragma unroll
+        for (int p = 0; p < H; ++p)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Pt[(size_t)c * IB + (h * H + p) * 64 + lane] = ia[p][c];
+    }
+}
+
+constexpr int kDiagSeg = 0xffff;  // segment field of a diagonal tile
+
 template <int PREC, int P>
 __global__ void __launch_bounds__(64, (sym_waves<PREC, P>())) k_pair_sym_ens(const double* __restrict__ x,
                                                                      const double* __restrict__ y,
@@ -44,8 +123,11 @@ __global__ void __launch_bounds__(64, (sym_waves<PREC, P>())) k_pair_sym_ens(con
     __shared__ __align__(16) double red_buf[12 * kRedStride];
     const int4 tl = tiles[blockIdx.x];  // first ion, ions, slot, row << 16 | segment
     const int o = tl.x;
-    sym_tile<PREC, P, 1>(tl.y, x + o, y + o, z + o, q + o, eps2, JL, tl.w >> 16, tl.w & 0xffff, tl.z, red_buf, Pi,
-                         R);
+    if ((tl.w & 0xffff) == kDiagSeg)
+        diag_tile<PREC, P>(tl.y, x + o, y + o, z + o, q + o, eps2, tl.w >> 16, tl.z, Pi);
+    else
+        sym_tile<PREC, P, 1>(tl.y, x + o, y + o, z + o, q + o, eps2, JL, tl.w >> 16, tl.w & 0xffff, tl.z, red_buf,
+                             Pi, R);
 }
 
 struct EnsParams {
@@ -279,12 +361,7 @@ __global__ void __launch_bounds__(64 * PARTS) k_ens_step(EnsParams P) {
         else if (need_f) direct_range<PREC, true, false>(lo, hi, kc, xk, yk, zk, X, Y, Z, Q, P.eps2, K, f, u);
         else if (need_p) direct_range<PREC, false, true>(lo, hi, kc, xk, yk, zk, X, Y, Z, Q, P.eps2, K, f, u);
     } else {
-        if (need_f) {  // pairs inside the ion's own i-block
-            const int b0 = k0 / P.IB * P.IB, b1 = min(n, b0 + P.IB);
-            int lo, hi;
-            part_of<PARTS>(b0, b1, w, lo, hi);
-            direct_range<PREC, true, false>(lo, hi, kc, xk, yk, zk, X, Y, Z, Q, P.eps2, K, f, u);
-        }
+        // (the pairs inside the ion's own i-block come from the row's diagonal tile)
         if (need_p) {  // potential over the whole run
             int lo, hi;
             part_of<PARTS>(0, n, w, lo, hi);
@@ -295,7 +372,7 @@ __global__ void __launch_bounds__(64 * PARTS) k_ens_step(EnsParams P) {
     v[1] = f[1];
     v[2] = f[2];
     v[kPot] = u;
-    if (!WHOLE && need_f) {  // i sums of the ion's row, reactions from the rows above
+    if (!WHOLE && need_f) {  // i sums of the ion's row (diagonal tile first), reactions from the rows above
         const int IB = P.IB, JL = P.JL, lgJL = P.lgJL;
         const int Ik = k0 / IB;
         const int off = kc - Ik * IB;
@@ -330,7 +407,7 @@ __global__ void __launch_bounds__(64 * PARTS) k_ens_step(EnsParams P) {
             for (int u = 0; u < U; ++u) {
                 const int rel = kc - (min(I + u, hi - 1) + 1) * IB;
                 const int sI = rel >> lgJL;
-                const double* Rt = P.R + (size_t)(slot[u] + sI) * 3 * JL + (rel - (sI << lgJL));
+                const double* Rt = P.R + (size_t)(slot[u] + 1 + sI) * 3 * JL + (rel - (sI << lgJL));
                 a[u][0] = Rt[0];
                 a[u][1] = Rt[JL];
                 a[u][2] = Rt[2 * JL];
@@ -485,6 +562,10 @@ static EnsTables ens_tables(int nrun, const int64_t* offsets, int IB, int JL) {
     };
     std::vector<Tile> tl;
     int slot = 0;
+    // With any run longer than one i-block, every row gets a diagonal tile
+    // (its first slot); otherwise there are no tiles at all.
+    bool diag = false;
+    for (int r = 0; r < nrun; ++r) diag = diag || offsets[r + 1] - offsets[r] > IB;
     E.runs.resize(nrun);
     for (int r = 0; r < nrun; ++r) {
         const int o = (int)offsets[r], n = (int)(offsets[r + 1] - offsets[r]);
@@ -492,6 +573,10 @@ static EnsTables ens_tables(int nrun, const int64_t* offsets, int IB, int JL) {
         E.runs[r] = make_int4(o, n, (int)E.rowstart.size(), (int)E.chunks.size());
         for (int I = 0; I < nI; ++I) {
             E.rowstart.push_back(slot);
+            if (diag) {
+                tl.push_back({make_int4(o, n, slot, (I << 16) | kDiagSeg), std::min(IB, n - I * IB)});
+                ++slot;
+            }
             const int ns = sym_nseg(n, IB, JL, I);
             for (int sg = 0; sg < ns; ++sg) {
                 const int j0 = (I + 1) * IB + sg * JL;
@@ -518,14 +603,15 @@ static int whole_ib(int64_t nmax) { return (int)((nmax + 63) / 64 * 64); }
 
 // Upper bound of ens_tables(...).bytes over every ensemble of ntot ions in
 // nrun runs of at most kMaxBatchIons, for every allowed (P, JL).  A run of n
-// ions has at most n^2 / (2 IB JL) + n / IB tiles.
+// ions has at most n^2 / (2 IB JL) + n / IB off-diagonal tiles and
+// ceil(n / IB) <= n / IB + 1 diagonal ones.
 size_t ens_ws_bound(int64_t ntot, int32_t nrun) {
     size_t best = 0;
     const double N = (double)ntot;
     for (int P : {4, 8})
         for (int JL : {256, 512}) {
             const int IB = 64 * P;
-            const size_t T = (size_t)std::ceil(N * (0.5 * kMaxBatchIons / ((double)IB * JL) + 1.0 / IB)) + nrun;
+            const size_t T = (size_t)std::ceil(N * (0.5 * kMaxBatchIons / ((double)IB * JL) + 2.0 / IB)) + 2 * (size_t)nrun;
             const size_t rows = (size_t)std::ceil(N / IB) + 2 * (size_t)nrun;
             const size_t nch = (size_t)std::ceil(N / 64) + nrun;
             const size_t b = al(sizeof(int4) * (T + 1)) + al(sizeof(int4) * nrun) + al(sizeof(int) * rows) +
