@@ -409,7 +409,7 @@ def bench_kz(args):
                     "pairs_per_s": kp / (ms * 1e-3), "defects_mean": float(np.mean(defects)),
                     "finite": bool(np.isfinite(got).all())}
     extra = {"mixed": res["mixed"], "fp64": res["fp64"], "fp64_persistent_kernel": res["fp64_persistent"],
-             "path": "stepped (p = 4, JL = 256: the default for runs above 512 ions)", "nrun": d["nrun"],
+             "path": "stepped (p = 4, JL = 256, the default shape)", "nrun": d["nrun"],
              "nsteps_per_run": nsteps,
              "sum_N2": float((ns.astype(np.float64) ** 2).sum()),
              "roofline": _roof(FLOPS_PER_PAIR * pairs, res["fp64"]["ms"] * 1e-3,

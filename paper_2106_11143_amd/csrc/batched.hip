@@ -463,8 +463,9 @@ cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s
     // a small run at about 1.6e9 ordered pairs/s per CU (its runs are spread
     // over the CUs, the largest bounding the step); the stepped path costs
     // about 40 us of launch latency per step plus the pairs at 1.8e12/s.
-    // The stepped path uses 512-ion i-blocks when no run is larger (each run
-    // is then finished by its diagonal pass alone), else 256-ion blocks.
+    // The stepped path uses 256-ion i-blocks and 256-ion j-segments, the
+    // fastest shape measured for every mix of run sizes tried (runs of 64 to
+    // 4096 ions, 8 to 512 runs).
     LaunchCfg ec = get_cfg(CB_OP_MD_ENSEMBLE, offsets[nrun], prec);
     if (!ec.tuned) {
         double pairs = 0.0;
@@ -473,8 +474,8 @@ cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s
         const double t_persistent = std::ceil((double)nrun / ncu) * (double)nmax * nmax / 1.6e9;
         const double t_stepped = 40e-6 + pairs / 1.8e12;
         ec.algo = t_stepped < t_persistent ? ALGO_SYM_LDS : ALGO_DIRECT;
-        ec.p = nmax <= 512 ? 8 : 4;
-        ec.splits = nmax <= 512 ? 512 : 256;
+        ec.p = 4;
+        ec.splits = 256;
     }
     if (ec.algo == ALGO_SYM_LDS) {
         const WsLayout LE = ws_layout(CB_OP_MD_RUN, offsets[nrun], nrun, 1);
