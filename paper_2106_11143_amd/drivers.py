@@ -98,61 +98,143 @@ def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, max_iter=100000, method="l
             r = r + dt * v
             g = -total_force(r, q, m, trap, 0.0, eps2)
     else:
-        S, Y = [], []
+        k = torch.tensor(trap_k(trap, 0.0), dtype=r.dtype, device=r.device).reshape(3, 1)
+        mk = m.reshape(1, -1) * k  # trap stiffness per ion and axis, kept on the device
+        grad = lambda r: mk * r - torch.stack(api.coulomb_forces(*_rows(r), q, eps2, "fp64"))
+        mem = LbfgsMemory(g.shape, memory, g.device, g.dtype)
+        mem.set_gradient(g)
         h0 = 1.0 / (float(m.mean()) * wmax * wmax)
         cap = 0.2 * a
         fmax = float(g.norm(dim=0).max())
+        hvp = lambda v: api.coulomb_hvp(*_rows(r), q, v, m, trap, 0.0, eps2)
         for it in range(max_iter):
             if fmax <= tol:
                 break
-            p = lbfgs_direction(g, S, Y, h0)
-            Hp = api.coulomb_hvp(*_rows(r), q, p.contiguous(), m, trap, 0.0, eps2)
+            p = mem.direction(h0)
+            Hp = hvp(p)
             gp, pHp = torch.stack([(g * p).sum(), (p * Hp).sum()]).tolist()
             if gp >= 0:  # not a descent direction: restart from steepest descent
-                S.clear()
-                Y.clear()
+                mem.clear()
                 p = -h0 * g
-                Hp = api.coulomb_hvp(*_rows(r), q, p.contiguous(), m, trap, 0.0, eps2)
+                Hp = hvp(p)
                 gp, pHp = torch.stack([(g * p).sum(), (p * Hp).sum()]).tolist()
             step = (-gp / pHp if pHp > 0 else 1.0) * p
             step = step * torch.clamp(cap / step.norm(dim=0).max(), max=1.0)  # at most `cap` per ion
             r = r + step
-            gn = -total_force(r, q, m, trap, 0.0, eps2)
-            y = gn - g
-            sy, fmax = torch.stack([(step * y).sum(), gn.norm(dim=0).max()]).tolist()
-            if sy > 0:
-                S.append(step)
-                Y.append(y)
-                if len(S) > memory:
-                    S.pop(0)
-                    Y.pop(0)
+            gn = grad(r)
+            D = mem.load(gn, step, gn - g)
+            host = torch.cat([D.reshape(-1), gn.norm(dim=0).max().reshape(1)]).cpu().numpy()
+            fmax = float(host[-1])
+            mem.absorb(host[:-1].reshape(D.shape))  # keeps the pair if s . y > 0
             g = gn
     info = {"method": method, "iters": it, "fmax_rel": float(g.norm(dim=0).max()) / fscale, "force_scale": fscale}
     return r, info
 
 
+class LbfgsMemory:
+    """The newest (at most m) curvature pairs (s_i, y_i), s_i . y_i > 0, of
+    L-BFGS as columns of one device matrix W (3n, 2m + 3): s in slots
+    [0, m), y in [m, 2m), then the current gradient g and the newest
+    candidate pair.  Their inner products (s_i . y_k, y_i . y_k, s_i . g,
+    y_i . g) are kept on the host and refreshed by one split-K product
+    W^T [g s y] per iteration, so that the two-loop recursion (Nocedal and
+    Wright, Algorithm 7.4) runs on host scalars and -H g is one
+    matrix-vector product with W.  The recursion is unchanged; each of its
+    dot products is expanded over the stored pairs' inner products."""
+
+    def __init__(self, shape, m, device, dtype):
+        self.shape, self.m = tuple(shape), m
+        self.W = torch.zeros(math.prod(self.shape), 2 * m + 3, dtype=dtype, device=device)
+        self.order = []  # slots in use, oldest first
+        self.SY = np.zeros((m, m))  # SY[i, k] = s_i . y_k
+        self.YY = np.zeros((m, m))  # YY[i, k] = y_i . y_k
+        self.Sg = np.zeros(m)
+        self.Yg = np.zeros(m)
+        pin = self.W.is_cuda
+        self.c = torch.zeros(2 * m + 3, dtype=dtype, pin_memory=pin)  # coefficients, host side
+        self.c_np = self.c.numpy()
+
+    def clear(self):
+        self.order = []
+
+    def set_gradient(self, g):
+        """Stores g without products (enough while no pair is held)."""
+        self.W[:, 2 * self.m] = g.reshape(-1)
+        self.order = []
+
+    def load(self, g, s, y):
+        """Stores the gradient g and the candidate pair (s, y); returns the
+        device products W^T [g s y], (2m + 3, 3), for absorb()."""
+        m, W = self.m, self.W
+        W[:, 2 * m] = g.reshape(-1)
+        W[:, 2 * m + 1] = s.reshape(-1)
+        W[:, 2 * m + 2] = y.reshape(-1)
+        return _tsmm(W, W[:, 2 * m:])
+
+    def absorb(self, D):
+        """Takes the products of load() (host array): refreshes s_i . g and
+        y_i . g, and keeps the candidate pair if s . y > 0 (the oldest pair
+        makes room when m are held)."""
+        m = self.m
+        for i in self.order:
+            self.Sg[i], self.Yg[i] = D[i, 0], D[m + i, 0]
+        if not D[2 * m + 1, 2] > 0:
+            return
+        if len(self.order) == m:
+            slot = self.order.pop(0)
+        else:
+            slot = min(set(range(m)) - set(self.order))
+        self.W[:, slot] = self.W[:, 2 * m + 1]
+        self.W[:, m + slot] = self.W[:, 2 * m + 2]
+        for i in self.order:
+            self.SY[i, slot] = D[i, 2]  # s_i . y
+            self.SY[slot, i] = D[m + i, 1]  # s . y_i
+            self.YY[i, slot] = self.YY[slot, i] = D[m + i, 2]
+        self.SY[slot, slot], self.YY[slot, slot] = D[2 * m + 1, 2], D[2 * m + 2, 2]
+        self.Sg[slot], self.Yg[slot] = D[2 * m + 1, 0], D[2 * m + 2, 0]
+        self.order.append(slot)
+
+    def direction(self, h0):
+        """-H g, with H_0 = gamma I, gamma = s.y / y.y of the newest pair (h0
+        without pairs)."""
+        m, W = self.m, self.W
+        if not self.order:
+            return (-h0 * W[:, 2 * m]).reshape(self.shape)
+        o = np.asarray(self.order)
+        k = len(o)
+        SY, YY = self.SY[np.ix_(o, o)], self.YY[np.ix_(o, o)]
+        rho = 1.0 / np.diag(SY)
+        # first loop, newest first: alpha_t = rho_t s_t . (g - sum_{u>t} alpha_u y_u)
+        al = np.zeros(k)
+        for t in range(k - 1, -1, -1):
+            al[t] = rho[t] * (self.Sg[o[t]] - SY[t, t + 1:] @ al[t + 1:])
+        gam = SY[-1, -1] / YY[-1, -1]
+        # z = gam (g - sum_u alpha_u y_u); second loop, oldest first:
+        # beta_t = rho_t y_t . z, then z += (alpha_t - beta_t) s_t
+        yq = self.Yg[o] - YY @ al
+        be = np.zeros(k)
+        for t in range(k):
+            be[t] = rho[t] * (gam * yq[t] + (al[:t] - be[:t]) @ SY[:t, t])
+        # the pinned buffer is rewritten only after the previous copy was
+        # awaited (every iteration reads products back in between)
+        c = self.c_np
+        c[:] = 0.0
+        c[2 * m] = gam
+        c[o] = al - be
+        c[m + o] = -gam * al
+        return -(W @ self.c.to(W.device, non_blocking=True)).reshape(self.shape)
+
+
 def lbfgs_direction(g, S, Y, h0):
     """-H g for the L-BFGS inverse-Hessian approximation H built from the
     curvature pairs (s_i, y_i), oldest first (s_i . y_i > 0), with H_0 =
-    gamma I, gamma = s.y / y.y of the newest pair (h0 without pairs): the
-    two-loop recursion (Nocedal and Wright, Algorithm 7.4), with every scalar
-    kept on the device, so that the 4m dependent dot products cost kernel
-    launches and no host synchronisation."""
-    if not S:
-        return -h0 * g
-    z = g.reshape(-1).clone()
-    ss = [s.reshape(-1) for s in S]
-    ys = [y.reshape(-1) for y in Y]
-    rho = [1.0 / torch.dot(y, s) for s, y in zip(ss, ys)]
-    al = []
-    for s, y, r in zip(reversed(ss), reversed(ys), reversed(rho)):
-        a = r * torch.dot(s, z)
-        al.append(a)
-        z = torch.addcmul(z, a, y, value=-1.0)
-    z = z * (torch.dot(ss[-1], ys[-1]) / torch.dot(ys[-1], ys[-1]))
-    for s, y, r, a in zip(ss, ys, rho, reversed(al)):
-        z = torch.addcmul(z, a - r * torch.dot(y, z), s)
-    return -z.reshape(g.shape)
+    gamma I, gamma = s.y / y.y of the newest pair (h0 without pairs); the
+    two-loop recursion of LbfgsMemory."""
+    mem = LbfgsMemory(g.shape, max(1, len(S)), g.device, g.dtype)
+    mem.set_gradient(g)
+    for s, y in zip(S, Y):
+        mem.absorb(mem.load(g, s, y).cpu().numpy())
+    return mem.direction(h0)
 
 
 def _band_ritz(band, k):

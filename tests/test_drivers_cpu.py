@@ -97,8 +97,8 @@ def test_block_lanczos_resolves_exactly_degenerate_modes():
 
 
 def test_lbfgs_direction_matches_the_two_loop_recursion():
-    """The device-scalar L-BFGS inverse-Hessian product against the two-loop
-    recursion written out with host floats, on curvature pairs of a random
+    """The L-BFGS inverse-Hessian product (two-loop recursion over stored
+    inner products) against the two-loop recursion written out on vectors, on curvature pairs of a random
     symmetric positive definite quadratic; with one pair and H itself
     quadratic, H s = y is reproduced (the secant condition)."""
     import torch
@@ -124,6 +124,51 @@ def test_lbfgs_direction_matches_the_two_loop_recursion():
     # secant condition of the newest pair: H y_last = s_last
     hy = -drivers.lbfgs_direction(Y[-1], S, Y, 0.1)
     assert torch.allclose(hy, S[-1], rtol=1e-9, atol=1e-12 * float(S[-1].abs().max()))
+
+
+def _two_loop(g, S, Y):
+    z, al = g.clone(), []
+    for s, y in reversed(list(zip(S, Y))):
+        a = float((s * z).sum()) / float((y * s).sum())
+        al.append(a)
+        z = z - a * y
+    z = z * float((S[-1] * Y[-1]).sum()) / float((Y[-1] * Y[-1]).sum())
+    for (s, y), a in zip(zip(S, Y), reversed(al)):
+        z = z + (a - float((y * z).sum()) / float((y * s).sum())) * s
+    return -z
+
+
+def test_lbfgs_memory_keeps_the_newest_pairs_with_positive_curvature():
+    """A memory of 3 fed 6 candidate pairs, one with s . y < 0, along with a
+    changing gradient: it keeps the 3 newest accepted pairs (slots reused
+    oldest first) and gives the two-loop recursion's direction for them and
+    the last gradient; after clear() it gives -h0 g."""
+    import torch
+    from paper_2106_11143_amd import drivers
+    g_ = np.random.default_rng(9)
+    n = 30
+    B = g_.standard_normal((3 * n, 3 * n))
+    H = B @ B.T + 3 * n * np.eye(3 * n)
+    mem = drivers.LbfgsMemory((3, n), 3, "cpu", torch.float64)
+    g = torch.as_tensor(g_.standard_normal((3, n)))
+    mem.set_gradient(g)
+    kept_s, kept_y = [], []
+    for k in range(6):
+        s = torch.as_tensor(g_.standard_normal((3, n)))
+        y = torch.as_tensor((H @ s.numpy().reshape(-1)).reshape(3, n))
+        if k == 3:
+            y = -y  # negative curvature: rejected
+        else:
+            kept_s.append(s)
+            kept_y.append(y)
+        g = torch.as_tensor(g_.standard_normal((3, n)))
+        mem.absorb(mem.load(g, s, y).numpy())
+    assert len(mem.order) == 3
+    got = mem.direction(0.1)
+    ref = _two_loop(g, kept_s[-3:], kept_y[-3:])
+    assert torch.allclose(got, ref, rtol=1e-10, atol=1e-12 * float(ref.abs().max()))
+    mem.clear()
+    assert torch.equal(mem.direction(0.1), -0.1 * g)
 
 
 def test_split_k_product_equals_plain_product():
