@@ -237,37 +237,39 @@ def lbfgs_direction(g, S, Y, h0):
     return mem.direction(h0)
 
 
-def _band_ritz(band, k):
+def _band_ritz(band, k, dense_max=512):
     """Lowest k eigenpairs of the symmetric banded matrix T given in lower
-    form, band[d, c] = T[c + d, c]: eigenvalues by the banded eigenvalue
-    solver, eigenvectors by inverse iteration with banded LU solves, each
-    re-orthogonalised against the earlier vectors of its cluster of equal
-    eigenvalues (exactly degenerate modes are common in symmetric traps).
-    Forming the banded solver's own eigenvectors would build the full
-    orthogonal matrix of its band reduction, which costs O(n^3)."""
-    from scipy.linalg import eigvals_banded, solve_banded
+    form, band[d, c] = T[c + d, c].  Up to dense_max rows: the dense
+    symmetric eigensolver.  Beyond: shift-and-invert Lanczos (ARPACK, through
+    scipy's eigsh) around a shift sigma certified below the spectrum by a
+    banded Cholesky factorisation of T - sigma I, so that the k eigenvalues
+    of (T - sigma I)^-1 of largest magnitude belong to the k lowest of T.
+    Each solve costs O(n b) after one sparse LU, where reducing the band to
+    tridiagonal form (the banded eigenvalue solver) costs O(n^2 b)."""
+    from scipy.linalg import LinAlgError, cholesky_banded
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
 
     b, n = band.shape[0] - 1, band.shape[1]
-    theta = eigvals_banded(band, lower=True, select="i", select_range=(0, k - 1))
-    ab = np.zeros((2 * b + 1, n))  # the general banded form solve_banded takes: ab[b + i - j, j] = T[i, j]
-    for d in range(b + 1):
-        ab[b + d, :n - d] = band[d, :n - d]
-        ab[b - d, d:] = band[d, :n - d]
-    scale = float(np.abs(band).sum(axis=0).max())  # bound on |T|
-    rng = np.random.default_rng(0)
-    S = np.empty((n, k))
-    for i, th in enumerate(theta):
-        shifted = ab.copy()
-        shifted[b] -= th + 1e-14 * scale
-        cluster = [c for c in range(i) if abs(theta[c] - th) <= 1e-10 * scale]
-        x = rng.standard_normal(n)
-        for _ in range(3):
-            x = solve_banded((b, b), shifted, x)
-            for c in cluster:
-                x -= (S[:, c] @ x) * S[:, c]
-            x /= np.linalg.norm(x)
-        S[:, i] = x
-    return theta, S
+    T = sp.diags([band[d, :n - d] for d in range(b + 1)], list(range(0, -b - 1, -1)), shape=(n, n))
+    T = (T + sp.tril(T, -1).T).tocsc()
+    if n <= max(dense_max, 3 * k):
+        w, V = np.linalg.eigh(T.toarray())
+        return w[:k], V[:, :k]
+    scale = float(np.abs(band).sum(axis=0).max())  # bound on |T| (Gershgorin)
+    sigma = -1e-9 * scale
+    for _ in range(12):  # reaches -1e2 scale, below every eigenvalue
+        shifted = band.copy()
+        shifted[0] -= sigma
+        try:
+            cholesky_banded(shifted, lower=True)
+            break
+        except LinAlgError:
+            sigma *= 10.0
+    v0 = np.random.default_rng(0).standard_normal(n)
+    w, V = sla.eigsh(T, k=k, sigma=sigma, which="LM", v0=v0, tol=0)
+    o = np.argsort(w)
+    return w[o], V[:, o]
 
 
 def _tsmm(A, W, P=64):
@@ -285,6 +287,30 @@ def _tsmm(A, W, P=64):
     if K0 < K:
         out = out + A[K0:].T @ W[K0:]
     return out
+
+
+def _chol_qr2(W, G):
+    """W = Q R for a tall W (K, b) with Gram matrix G = W^T W (host): two
+    rounds of Cholesky QR (R_1 = chol(G), W R_1^-1, and again on the result),
+    which give Q orthonormal to rounding while cond(W) stays below about
+    1e7.  A Gram matrix that is not safely positive definite (a nearly
+    rank-deficient block) goes to Householder QR instead.  Returns (Q on W's
+    device, R on the host)."""
+    def chol(G):
+        L = np.linalg.cholesky(0.5 * (G + G.T))  # raises if not positive definite
+        d = np.abs(np.diag(L))
+        if d.min() <= 1e-7 * d.max():
+            raise np.linalg.LinAlgError("ill-conditioned block")
+        return L.T
+
+    try:
+        R1 = chol(G)
+        Q1 = W @ torch.as_tensor(np.linalg.inv(R1), dtype=W.dtype, device=W.device)
+        R2 = chol(_tsmm(Q1, Q1).cpu().numpy())
+        return Q1 @ torch.as_tensor(np.linalg.inv(R2), dtype=W.dtype, device=W.device), R2 @ R1
+    except np.linalg.LinAlgError:
+        Qh, Rh = torch.linalg.qr(W)
+        return Qh, Rh.cpu().numpy()
 
 
 def lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=12000, eps2=0.0, seed=0, tol=1e-8, check_every=20,
@@ -331,11 +357,21 @@ def lanczos_lowest(r, q, m, trap, k=32, block=8, maxdim=12000, eps2=0.0, seed=0,
         Aj = _tsmm(Qj, W)
         Aj = 0.5 * (Aj + Aj.T)
         W = W - Qj @ Aj
-        for _ in range(2):
+        # full reorthogonalisation against the basis; a second pass only where
+        # the first removed more than half of a column's squared norm
+        # (Daniel, Gragg, Kaufman and Stewart's criterion)
+        n0 = (W * W).sum(0)
+        W = W - Q[:, :c1] @ _tsmm(Q[:, :c1], W)
+        host = torch.cat([Aj.reshape(-1), n0, _tsmm(W, W).reshape(-1)]).cpu().numpy()
+        Ah = host[:block * block].reshape(block, block)
+        n0h = host[block * block:block * block + block]
+        G = host[block * block + block:].reshape(block, block)
+        if np.any(np.diag(G) < 0.5 * n0h):
             W = W - Q[:, :c1] @ _tsmm(Q[:, :c1], W)
-        Qn, Bj = torch.linalg.qr(W)
+            G = _tsmm(W, W).cpu().numpy()
+        Qn, Bh = _chol_qr2(W, G)
         Q[:, c1:c1 + block] = Qn
-        Ah, Bh = Aj.cpu().numpy(), Bj.cpu().numpy()
+        Bj = torch.as_tensor(Bh, dtype=dt, device=dev)
         for a_ in range(block):  # diagonal block A_j (lower half)
             for b_ in range(a_ + 1):
                 band[a_ - b_, c0 + b_] = Ah[a_, b_]
