@@ -256,10 +256,11 @@ def md_step(state, q, m, trap: dict, t: float, dt: float, eps2: float = 0.0, pre
 
 
 def md_run(state, q, m, traps, t0: float, dt: float, nsteps: int, offsets=None, eps2: float = 0.0, prec="fp64",
-           init_accel: bool = True, every: int = 0):
+           init_accel: bool = True, every: int = 0, out=None):
     """nsteps velocity-Verlet steps in place.  traps: one dict, or one per run
     with offsets (sequence of nrun+1 ints).  Returns the energies tensor
-    [nrun][nsteps//every + 1][4] (K, U_C, U_trap, E) when every > 0."""
+    [nrun][nsteps//every + 1][4] (K, U_C, U_trap, E) when every > 0 (written
+    into `out` when given: contiguous float64 on the device, that shape)."""
     s = _state(state)
     dev = _dev_f64(q, m)
     n = q.numel()
@@ -274,7 +275,14 @@ def md_run(state, q, m, traps, t0: float, dt: float, nsteps: int, offsets=None, 
     tarr = (Trap * nrun)(*[make_trap(t) for t in traps])
     en = None
     if every:
-        en = torch.empty((nrun, nsteps // every + 1, 4), dtype=torch.float64, device=dev)
+        shape = (nrun, nsteps // every + 1, 4)
+        if out is not None:
+            if tuple(out.shape) != shape or out.dtype != torch.float64 or not out.is_contiguous():
+                raise ValueError(f"out must be a contiguous float64 tensor of shape {shape}")
+            _dev_f64(q, m, out)
+            en = out
+        else:
+            en = torch.empty(shape, dtype=torch.float64, device=dev)
     ws = _workspace("md_run", n, nrun=nrun, prec=prec, device=dev)
     _check(lib().md_run(nrun, offs, C.byref(s), q.data_ptr(), m.data_ptr(), tarr, float(t0), float(dt), int(nsteps),
                         float(eps2), _prec(prec), CB_INIT_ACCEL if init_accel else 0,

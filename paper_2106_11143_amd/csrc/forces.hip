@@ -362,7 +362,7 @@ cb_status md_run(int32_t nrun, const int64_t* offsets, const cb_state* s, const 
         const int64_t nrec = nsteps / every + 1;
         double* arr[9] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->ax, s->ay, s->az};
         for (auto a : arr)
-            if (overlaps(a, energies, std::max<int64_t>(n, 4 * nrec * nrun)))
+            if (overlaps2(a, n, energies, 4 * nrec * nrun))
                 return fail(CB_EINVAL, "md_run: energies overlaps the state");
     }
     hipStream_t st = static_cast<hipStream_t>(stream);

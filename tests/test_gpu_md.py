@@ -218,6 +218,41 @@ def test_md_run_captured_in_a_hip_graph_replays_bitwise(api, n):
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("nrun", [1, 3])
+def test_energy_records_next_to_the_state_are_not_aliases(api, nrun):
+    """Energy records in the same allocation as the state arrays, directly
+    before or after them, are accepted and give the results of separate
+    buffers (single run and ensemble); records overlapping a state array
+    are refused with CB_EINVAL."""
+    import torch
+    from _gpu_util import dev
+    d = inputs.cloud1024(n=900)
+    st = inputs.state9(d)
+    n = st.shape[1]
+    offs = [0, 300, 600, 900] if nrun == 3 else None
+    nsteps, every = 6, 2
+    nrec = nsteps // every + 1
+    q, m = dev(d["q"]), dev(d["m"])
+    ref = [dev(st[k]) for k in range(9)]
+    en_ref = api.md_run(ref, q, m, d["trap"], 0.0, d["dt"], nsteps, offsets=offs, every=every)
+    E = 4 * nrec * nrun
+    for where in ("before", "after"):
+        buf = torch.zeros(E + 9 * n + E, dtype=torch.float64, device="cuda")
+        ts = [buf[E + k * n:E + (k + 1) * n] for k in range(9)]
+        for k in range(9):
+            ts[k].copy_(dev(st[k]))
+        rec = buf[:E] if where == "before" else buf[E + 9 * n:]
+        api.md_run(ts, q, m, d["trap"], 0.0, d["dt"], nsteps, offsets=offs, every=every,
+                   out=rec.view(nrun, nrec, 4))
+        torch.cuda.synchronize()
+        assert torch.equal(torch.stack(ts), torch.stack(ref)), where
+        assert torch.equal(rec.view(nrun, nrec, 4), en_ref), where
+    with pytest.raises(api.CoulombError) as err:
+        api.md_run(ts, q, m, d["trap"], 0.0, d["dt"], nsteps, offsets=offs, every=every,
+                   out=buf[E + 4 * n - 2:E + 4 * n - 2 + E].view(nrun, nrec, 4))
+    assert err.value.status == api.CB_EINVAL
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1000, 4097, 8192])
 def test_small_run_path_matches_two_launch_path_and_oracle(api, oracle, n):
     """Runs of at most 8192 ions can take one launch per step (algorithm 3:
