@@ -200,13 +200,17 @@ cb_status md_step(int64_t n, const cb_state* s, const double* q, const double* m
  *    kick and drift (p i-particles per lane, j-segment length JL).
  * Without a forced or tuned entry the path with the smaller estimated step
  * time is taken (algorithm 0 wins only for ensembles of small runs whose
- * step is shorter than the stepped path's launch latency), with p = 8,
- * JL = 512 when no run exceeds 512 ions, else p = 4, JL = 256.  Both paths
- * give the same trajectories up to rounding (different summation orders);
- * each is deterministic.  Both copy run tables from host memory, so md_run
- * with nrun > 1 returns CB_EUNSUPPORTED on a stream that is being captured
- * into a graph; with nrun = 1 it enqueues kernels and device copies only
- * and may be captured. */
+ * step is shorter than the stepped path's launch latency), with p = 4,
+ * JL = 256.  Both paths give the same trajectories up to rounding
+ * (different summation orders); each is deterministic.
+ * Graph capture: md_run may be called on a stream that is being captured.
+ * With nrun = 1 it enqueues kernels and device copies only.  With nrun > 1
+ * it also copies run tables (built from offsets and traps at the call) from
+ * host memory; under capture those tables are first copied into a host
+ * block that the captured graph owns (released after the graph is
+ * destroyed), so offsets and traps may be freed on return and every replay
+ * repeats the captured call: same runs, traps, t0, nsteps, energy slots and
+ * workspace, continuing from whatever state s holds. */
 cb_status md_run(int32_t nrun, const int64_t* offsets, const cb_state* s, const double* q, const double* m,
                  const cb_trap* traps, double t0, double dt, int64_t nsteps, double eps2, int32_t prec,
                  uint32_t flags, double* energies, int64_t every, void* ws, size_t ws_bytes, void* stream);

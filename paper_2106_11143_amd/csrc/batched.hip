@@ -448,13 +448,6 @@ cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s
                     nmax);
     if (prec != CB_FP64 && prec != CB_MIXED && prec != CB_FP64_IEEE && prec != CB_FP32_RSQ)
         return fail(CB_EINVAL, "md_run: unknown precision %d", prec);
-    // Both ensemble paths copy their run tables from host memory that is
-    // freed on return, which a captured graph would read again on replay.
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cap) != hipSuccess)
-        return fail(CB_EHIP, "md_run: stream capture query failed");
-    if (cap != hipStreamCaptureStatusNone)
-        return fail(CB_EUNSUPPORTED, "md_run: several runs cannot be captured in a graph (launch it eagerly)");
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return fail(CB_EHIP, "md_run: device query failed");
@@ -499,13 +492,14 @@ cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return (offsets[a + 1] - offsets[a]) > (offsets[b + 1] - offsets[b]);
     });
-    // Host buffers are pageable: HIP consumes them before hipMemcpyAsync returns.
-    if (hipMemcpyAsync(d_off, offsets, sizeof(int64_t) * (nrun + 1), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(d_order, order.data(), sizeof(int) * nrun, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(d_traps, traps, sizeof(cb_trap) * nrun, hipMemcpyHostToDevice, st) != hipSuccess)
-        return fail(CB_EHIP, "md_run: run table upload failed");
+    HostUpload up;
+    up.add(d_off, offsets, sizeof(int64_t) * (nrun + 1));
+    up.add(d_order, order.data(), sizeof(int) * nrun);
+    up.add(d_traps, traps, sizeof(cb_trap) * nrun);
+    cb_status rc = up.run(st, "md_run");
+    if (rc) return rc;
     k_zero_int<<<1, 1, 0, st>>>(d_queue);
-    cb_status rc = check_launch("k_zero_int");
+    rc = check_launch("k_zero_int");
     if (rc) return rc;
 
     BatchParams B{};

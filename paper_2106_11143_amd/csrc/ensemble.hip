@@ -670,14 +670,13 @@ cb_status md_run_ensemble(int32_t nrun, const int64_t* offsets, const cb_state* 
     double* echunk = reinterpret_cast<double*>(carve(sizeof(double) * 3 * nch));
     unsigned* ecount = reinterpret_cast<unsigned*>(carve(sizeof(unsigned) * nrun));
 
-    // Host buffers are pageable: HIP consumes them before hipMemcpyAsync returns.
-    auto up = [&](void* dst, const void* src, size_t bytes) {
-        return bytes == 0 || hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess;
-    };
-    if (!up(d_tiles, E.tiles.data(), sizeof(int4) * T) || !up(d_runs, E.runs.data(), sizeof(int4) * nrun) ||
-        !up(d_rows, E.rowstart.data(), sizeof(int) * E.rowstart.size()) ||
-        !up(d_chunks, E.chunks.data(), sizeof(int2) * nch) || !up(d_traps, traps, sizeof(cb_trap) * nrun))
-        return fail(CB_EHIP, "md_run: ensemble table upload failed");
+    HostUpload up;
+    up.add(d_tiles, E.tiles.data(), sizeof(int4) * T);
+    up.add(d_runs, E.runs.data(), sizeof(int4) * nrun);
+    up.add(d_rows, E.rowstart.data(), sizeof(int) * E.rowstart.size());
+    up.add(d_chunks, E.chunks.data(), sizeof(int2) * nch);
+    up.add(d_traps, traps, sizeof(cb_trap) * nrun);
+    if (cb_status urc = up.run(st, "md_run")) return urc;
 
     double* bufA[3] = {s->x, s->y, s->z};
     double* bufB[3] = {pos2, pos2 + ntot, pos2 + 2 * ntot};

@@ -4,6 +4,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 
 #include "coulomb.h"
 
@@ -55,6 +56,28 @@ cb_status fail(cb_status st, const char* fmt, ...);
 cb_status ok();
 cb_status check_launch(const char* what);
 unsigned* flags_ptr();
+
+// Host-to-device copies of tables a call builds on the host (run tables,
+// traps).  On a stream that is not capturing, each copy reads its source
+// directly (HIP consumes pageable sources before hipMemcpyAsync returns).
+// On a capturing stream the sources are first copied into one host block
+// that the graph under construction owns (a user object the graph retains,
+// freed after the graph is destroyed), so every replay copies the same
+// bytes again.  Sources must stay valid until run() returns.
+class HostUpload {
+  public:
+    void add(void* dst, const void* src, size_t bytes);
+    cb_status run(hipStream_t st, const char* what);
+
+  private:
+    struct Item {
+        void* dst;
+        const void* src;
+        size_t bytes;
+    };
+    Item items_[8];
+    int count_ = 0;
+};
 
 int n_bucket(int64_t n);
 LaunchCfg default_cfg(int op, int64_t n, int prec);

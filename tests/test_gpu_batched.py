@@ -344,28 +344,52 @@ def test_ensemble_zero_steps_and_softening(api, oracle, path):
             assert np.abs(got[blk, sl] - ref[blk]).max() <= 1e-11 * np.abs(ref[blk]).max(), (r, blk)
 
 
-@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")
-def test_ensemble_refuses_graph_capture(api):
-    """md_run with several runs copies its run tables from host memory, so
-    on a capturing stream it fails with CB_EUNSUPPORTED and enqueues
-    nothing; the same call runs eagerly afterwards."""
+@pytest.mark.parametrize("path,sizes", [(PERSISTENT, [100, 300, 700]), (STEPPED4, [100, 300, 700]),
+                                        (STEPPED8, [100, 300, 700]), (STEPPED8, [100, 300, 500])],
+                         ids=["persistent", "stepped-4-256", "stepped-8-512", "stepped-whole"])
+def test_ensemble_captured_in_a_hip_graph_replays_bitwise(api, path, sizes):
+    """md_run with several runs on a capturing stream: its run tables and
+    traps go into host memory that the graph owns, so every replay equals
+    the eager run bitwise (state and energy records), although the offsets
+    and trap arrays of the captured call are gone and an eager call on other
+    runs of the same total (other tables in the same workspace) runs
+    between replays.  Both paths, the stepped one with tiles and with every
+    run a single block."""
     import torch
     from _gpu_util import dev
-    trap = inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6)
-    sizes = [100, 200]
-    parts, offs, q, m = _ensemble(sizes, 41, trap)
+    trap0 = inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6)
+    traps = [inputs.pseudo_trap(1.0e6 * (1 + 0.1 * r), 1.0e6, 0.15e6 * (1 + 0.05 * r)) for r in range(len(sizes))]
+    parts, offs, q, m = _ensemble(sizes, 43, trap0)
     st = np.concatenate(parts, axis=1)
-    ts = [dev(st[k]) for k in range(9)]
+    ntot = int(offs[-1])
     qd, md = dev(q), dev(m)
-    api.md_run(ts, qd, md, [trap] * 2, 0.0, 1e-9, 2, offsets=offs)  # warm-up: workspace
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with pytest.raises(api.CoulombError) as err:
+    nsteps, every, dt = 12, 3, 1e-9
+    other_sizes = sizes[::-1]
+    oparts, ooffs, _, _ = _ensemble(other_sizes, 44, trap0)
+    ost = np.concatenate(oparts, axis=1)
+    with _path(api, ntot, "fp64", path):
+        eager = [dev(st[k]) for k in range(9)]
+        en_eager = api.md_run(eager, qd, md, traps, 0.0, dt, nsteps, offsets=offs, every=every,
+                              init_accel=True).clone()
+        ref = torch.stack(eager)
+        static = [dev(st[k]) for k in range(9)]
+        api.md_run(static, qd, md, traps, 0.0, dt, 2, offsets=offs, every=every)  # warm-up: workspace
+        torch.cuda.synchronize()
+        s0 = torch.stack([dev(st[k]) for k in range(9)])
+        for k in range(9):
+            static[k].copy_(s0[k])
+        g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            api.md_run(ts, qd, md, [trap] * 2, 0.0, 1e-9, 2, offsets=offs)
-    assert err.value.status == api.CB_EUNSUPPORTED
-    torch.cuda.synchronize()
-    ts2 = [dev(st[k]) for k in range(9)]
-    api.md_run(ts2, qd, md, [trap] * 2, 0.0, 1e-9, 2, offsets=offs)
-    torch.cuda.synchronize()
-    assert np.isfinite(np.stack([t.cpu().numpy() for t in ts2])).all()
+            en_static = api.md_run(static, qd, md, [dict(t) for t in traps], 0.0, dt, nsteps,
+                                   offsets=[int(o) for o in offs], every=every, init_accel=True)
+        for rep in range(3):
+            for k in range(9):
+                static[k].copy_(s0[k])
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(torch.stack(static), ref), rep
+            assert torch.equal(en_static, en_eager), rep
+            other = [dev(ost[k]) for k in range(9)]  # other tables in the same workspace
+            api.md_run(other, qd, md, trap0, 0.0, dt, 3, offsets=ooffs, init_accel=True)
+            torch.cuda.synchronize()
+            assert torch.isfinite(torch.stack(other)).all()
