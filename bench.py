@@ -370,8 +370,8 @@ def bench_md_single(args, which):
 
 def bench_kz(args):
     """kz512: 512 runs, N uniform in [64, 4096], ramp, in one md_run; FP64
-    and mixed on the default (stepped) ensemble path, and FP64 on the
-    persistent kernel for comparison.  --steps sets the steps per run (10000
+    and mixed on the default (stepped) ensemble path, FP64 captured in a HIP
+    graph and replayed, and FP64 on the persistent kernel for comparison.  --steps sets the steps per run (10000
     in the full workload)."""
     np, torch, api, inputs, dev = _setup()
     from paper_2106_11143_amd import drivers
@@ -408,7 +408,31 @@ def bench_kz(args):
         res[key] = {"ms": ms, "steps": k, "ms_per_step": ms / k, "runs_per_s": d["nrun"] / (ms * 1e-3),
                     "pairs_per_s": kp / (ms * 1e-3), "defects_mean": float(np.mean(defects)),
                     "finite": bool(np.isfinite(got).all())}
-    extra = {"mixed": res["mixed"], "fp64": res["fp64"], "fp64_persistent_kernel": res["fp64_persistent"],
+    # the default path captured in a HIP graph (at most 1000 steps: two
+    # launches per step), replayed once, against the same steps run eagerly
+    k = min(nsteps, 1000)
+    ts_eager = [dev(st0[c]) for c in range(9)]
+    api.md_run(ts_eager, q, m, d["traps"], 0.0, d["dt"], k, offsets=offs)
+    ts_g = [dev(st0[c]) for c in range(9)]
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        api.md_run(ts_g, q, m, d["traps"], 0.0, d["dt"], k, offsets=offs)
+    for c in range(9):
+        ts_g[c].copy_(dev(st0[c]))
+    torch.cuda.synchronize()
+    e0, e1 = _timer(torch)
+    e0.record()
+    graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    res["fp64_graph"] = {"ms": ms, "steps": k, "ms_per_step": ms / k,
+                         "pairs_per_s": pairs / nsteps * k / (ms * 1e-3),
+                         "bitwise_equal_eager": bool(torch.equal(torch.stack(ts_g), torch.stack(ts_eager)))}
+    del graph
+    extra = {"mixed": res["mixed"], "fp64": res["fp64"], "fp64_graph_replay": res["fp64_graph"],
+             "fp64_persistent_kernel": res["fp64_persistent"],
              "path": "stepped (p = 4, JL = 256, the default shape)", "nrun": d["nrun"],
              "nsteps_per_run": nsteps,
              "sum_N2": float((ns.astype(np.float64) ** 2).sum()),
