@@ -6,8 +6,8 @@
 //      run, one wave per tile, longest tiles first.  A tile entry holds its
 //      run's first ion and size, the slot of its partials, and its row and
 //      segment.
-//      Each row's first tile is its diagonal block (the ordered pairs inside
-//      the i-block, evaluated directly).
+//      Each row's first tiles are its diagonal block (the ordered pairs
+//      inside the i-block, evaluated directly) cut into j-ranges of 128.
 //   2. k_ens_step: per 64 ions of one run, the finish of the force (the i
 //      sums of its row and the reactions from the rows above, each summed in
 //      a fixed order) fused with the trap, the kick and the next drift.  The drift writes the other of two
@@ -34,24 +34,33 @@
 
 namespace cb {
 
-// Diagonal tile of row I: the ordered pairs inside i-block I (ions b0 ..
-// b1-1; a run's last block may be short) evaluated directly, the self pair
-// skipped, into the i sums Pi[t] (q_i q_j d r^-3, as the row's other tiles).
+// Diagonal sub-tile d of row I: the ordered pairs (i, j) inside i-block I
+// (ions b0 .. b1-1; a run's last block may be short) with j in the d-th
+// range of DL, evaluated directly, the self pair skipped, into the i sums
+// Pi[t] (q_i q_j d r^-3, as the row's other tiles).  In a small launch a
+// block's diagonal is split (DL < IB) so that it takes several waves, not
+// one long one; in a large one it stays whole (DL = IB).
 // The j data of the next group of 4 are requested before the current group
 // is evaluated; at most 4 rows per lane are held at a time, so the tile fits
 // the register budget of the symmetric tiles it shares a kernel with.  Lanes beyond the block compute on a clamped ion and their
 // sums are never read.
+constexpr int kDiagLen = 128;        // j's per diagonal sub-tile when a block's diagonal is split
+constexpr int kDiagSplitMax = 4096;  // split only below this many off-diagonal tiles
+constexpr int kDiagSeg = 0xffff;     // segment field of diagonal sub-tile d: kDiagSeg - d
+constexpr int kDiagMax = 8;          // sub-tiles per block at most (IB <= 1024)
+
 template <int PREC, int P>
 __device__ __forceinline__ void diag_tile(int n, const double* __restrict__ x, const double* __restrict__ y,
                                           const double* __restrict__ z, const double* __restrict__ q, double eps2,
-                                          int I, int t, double* __restrict__ Pi) {
+                                          int I, int d, int DL, int t, double* __restrict__ Pi) {
     constexpr int IB = 64 * P;
     constexpr int H = P < 4 ? P : 4;  // i rows held per pass: the block in P / H passes over its j's
     const int lane = threadIdx.x;
     const int b0 = I * IB, b1 = min(n, b0 + IB);
+    const int j0 = b0 + d * DL, j1 = min(b1, j0 + DL);  // this sub-tile's j's
     double* Pt = Pi + (size_t)t * 3 * IB;
     const SeriesK K;
-    const int full = b0 + (b1 - b0) / kGroupJ * kGroupJ;
+    const int full = j0 + (j1 - j0) / kGroupJ * kGroupJ;
 #pragma unroll 1
     for (int h = 0; h < P / H; ++h) {
         double xi[H], yi[H], zi[H], qi[H], ia[H][3];
@@ -85,7 +94,7 @@ __device__ __forceinline__ void diag_tile(int n, const double* __restrict__ x, c
                 for (int p = 0; p < H; ++p) asm volatile("" : "+v"(ia[p][0]), "+v"(ia[p][1]), "+v"(ia[p][2]));
             }
         };
-        int jg = b0;
+        int jg = j0;
         if (jg < full) {
             JGroup cur;
             load_group<false>(cur, jg, 0, x, y, z, q);
@@ -98,10 +107,10 @@ __device__ __forceinline__ void diag_tile(int n, const double* __restrict__ x, c
                 cur = nxt;
             }
         }
-        if (jg < b1) {
+        if (jg < j1) {
             JGroup tail;
-            load_group<true>(tail, jg, b1 - jg - 1, x, y, z, q);
-            group(tail, jg, b1 - jg);
+            load_group<true>(tail, jg, j1 - jg - 1, x, y, z, q);
+            group(tail, jg, j1 - jg);
         }
 #pragma unroll
         for (int p = 0; p < H; ++p)
@@ -110,23 +119,22 @@ __device__ __forceinline__ void diag_tile(int n, const double* __restrict__ x, c
     }
 }
 
-constexpr int kDiagSeg = 0xffff;  // segment field of a diagonal tile
-
 template <int PREC, int P>
 __global__ void __launch_bounds__(64, (sym_waves<PREC, P>())) k_pair_sym_ens(const double* __restrict__ x,
                                                                      const double* __restrict__ y,
                                                                      const double* __restrict__ z,
                                                                      const double* __restrict__ q, double eps2,
-                                                                     int JL, const int4* __restrict__ tiles,
+                                                                     int JL, int DL, const int4* __restrict__ tiles,
                                                                      double* __restrict__ Pi,
                                                                      double* __restrict__ R) {
     __shared__ __align__(16) double red_buf[12 * kRedStride];
     const int4 tl = tiles[blockIdx.x];  // first ion, ions, slot, row << 16 | segment
     const int o = tl.x;
-    if ((tl.w & 0xffff) == kDiagSeg)
-        diag_tile<PREC, P>(tl.y, x + o, y + o, z + o, q + o, eps2, tl.w >> 16, tl.z, Pi);
+    const int sg = tl.w & 0xffff;
+    if (sg > kDiagSeg - kDiagMax)
+        diag_tile<PREC, P>(tl.y, x + o, y + o, z + o, q + o, eps2, tl.w >> 16, kDiagSeg - sg, DL, tl.z, Pi);
     else
-        sym_tile<PREC, P, 1>(tl.y, x + o, y + o, z + o, q + o, eps2, JL, tl.w >> 16, tl.w & 0xffff, tl.z, red_buf,
+        sym_tile<PREC, P, 1>(tl.y, x + o, y + o, z + o, q + o, eps2, JL, tl.w >> 16, sg, tl.z, red_buf,
                              Pi, R);
 }
 
@@ -143,6 +151,7 @@ struct EnsParams {
     const double* m;
     double *vx, *vy, *vz, *ax, *ay, *az;
     int IB, JL, lgJL;
+    int ndiag;  // diagonal sub-tiles (slots) at the head of every full row, 0 without tiles
     double eps2, t0, dt;
     long long step;     // the trap is taken at step_time(t0, dt, step)
     unsigned mode;      // EPI_ACCEL, EPI_KICK, EPI_DRIFT, EPI_ENERGY
@@ -361,7 +370,7 @@ __global__ void __launch_bounds__(64 * PARTS) k_ens_step(EnsParams P) {
         else if (need_f) direct_range<PREC, true, false>(lo, hi, kc, xk, yk, zk, X, Y, Z, Q, P.eps2, K, f, u);
         else if (need_p) direct_range<PREC, false, true>(lo, hi, kc, xk, yk, zk, X, Y, Z, Q, P.eps2, K, f, u);
     } else {
-        // (the pairs inside the ion's own i-block come from the row's diagonal tile)
+        // (the pairs inside the ion's own i-block come from the row's diagonal sub-tiles)
         if (need_p) {  // potential over the whole run
             int lo, hi;
             part_of<PARTS>(0, n, w, lo, hi);
@@ -372,7 +381,7 @@ __global__ void __launch_bounds__(64 * PARTS) k_ens_step(EnsParams P) {
     v[1] = f[1];
     v[2] = f[2];
     v[kPot] = u;
-    if (!WHOLE && need_f) {  // i sums of the ion's row (diagonal tile first), reactions from the rows above
+    if (!WHOLE && need_f) {  // i sums of the ion's row (diagonal sub-tiles first), reactions from the rows above
         const int IB = P.IB, JL = P.JL, lgJL = P.lgJL;
         const int Ik = k0 / IB;
         const int off = kc - Ik * IB;
@@ -407,7 +416,7 @@ __global__ void __launch_bounds__(64 * PARTS) k_ens_step(EnsParams P) {
             for (int u = 0; u < U; ++u) {
                 const int rel = kc - (min(I + u, hi - 1) + 1) * IB;
                 const int sI = rel >> lgJL;
-                const double* Rt = P.R + (size_t)(slot[u] + 1 + sI) * 3 * JL + (rel - (sI << lgJL));
+                const double* Rt = P.R + (size_t)(slot[u] + P.ndiag + sI) * 3 * JL + (rel - (sI << lgJL));
                 a[u][0] = Rt[0];
                 a[u][1] = Rt[JL];
                 a[u][2] = Rt[2 * JL];
@@ -549,6 +558,8 @@ struct EnsTables {
     std::vector<int4> tiles, runs;
     std::vector<int> rowstart;
     std::vector<int2> chunks;
+    int ndiag = 0;  // diagonal sub-tiles of a full row (0: no tiles)
+    int dl = 0;     // j's per diagonal sub-tile
     size_t bytes = 0;
 };
 
@@ -562,10 +573,18 @@ static EnsTables ens_tables(int nrun, const int64_t* offsets, int IB, int JL) {
     };
     std::vector<Tile> tl;
     int slot = 0;
-    // With any run longer than one i-block, every row gets a diagonal tile
-    // (its first slot); otherwise there are no tiles at all.
+    // With any run longer than one i-block, every row starts with its
+    // diagonal sub-tiles (one slot each, ceil(rows / DL) of them);
+    // otherwise there are no tiles at all.
     bool diag = false;
-    for (int r = 0; r < nrun; ++r) diag = diag || offsets[r + 1] - offsets[r] > IB;
+    size_t noff = 0;
+    for (int r = 0; r < nrun; ++r) {
+        const int n = (int)(offsets[r + 1] - offsets[r]);
+        diag = diag || n > IB;
+        for (int I = 0; I * IB < n; ++I) noff += sym_nseg(n, IB, JL, I);
+    }
+    E.dl = noff < (size_t)kDiagSplitMax ? std::min(IB, kDiagLen) : IB;
+    E.ndiag = diag ? (IB + E.dl - 1) / E.dl : 0;
     E.runs.resize(nrun);
     for (int r = 0; r < nrun; ++r) {
         const int o = (int)offsets[r], n = (int)(offsets[r + 1] - offsets[r]);
@@ -574,8 +593,12 @@ static EnsTables ens_tables(int nrun, const int64_t* offsets, int IB, int JL) {
         for (int I = 0; I < nI; ++I) {
             E.rowstart.push_back(slot);
             if (diag) {
-                tl.push_back({make_int4(o, n, slot, (I << 16) | kDiagSeg), std::min(IB, n - I * IB)});
-                ++slot;
+                const int rows = std::min(IB, n - I * IB);
+                for (int d = 0; d * E.dl < rows; ++d) {
+                    tl.push_back({make_int4(o, n, slot, (I << 16) | (kDiagSeg - d)),
+                                  std::min(E.dl, rows - d * E.dl)});
+                    ++slot;
+                }
             }
             const int ns = sym_nseg(n, IB, JL, I);
             for (int sg = 0; sg < ns; ++sg) {
@@ -603,15 +626,18 @@ static int whole_ib(int64_t nmax) { return (int)((nmax + 63) / 64 * 64); }
 
 // Upper bound of ens_tables(...).bytes over every ensemble of ntot ions in
 // nrun runs of at most kMaxBatchIons, for every allowed (P, JL).  A run of n
-// ions has at most n^2 / (2 IB JL) + n / IB off-diagonal tiles and
-// ceil(n / IB) <= n / IB + 1 diagonal ones.
+// ions has at most n^2 / (2 IB JL) + n / IB off-diagonal tiles and, over
+// its ceil(n / IB) <= n / IB + 1 rows, at most n / kDiagLen + n / IB + 1
+// diagonal sub-tiles.
 size_t ens_ws_bound(int64_t ntot, int32_t nrun) {
     size_t best = 0;
     const double N = (double)ntot;
     for (int P : {4, 8})
         for (int JL : {256, 512}) {
             const int IB = 64 * P;
-            const size_t T = (size_t)std::ceil(N * (0.5 * kMaxBatchIons / ((double)IB * JL) + 2.0 / IB)) + 2 * (size_t)nrun;
+            const size_t T =
+                (size_t)std::ceil(N * (0.5 * kMaxBatchIons / ((double)IB * JL) + 2.0 / IB + 1.0 / kDiagLen)) +
+                3 * (size_t)nrun;
             const size_t rows = (size_t)std::ceil(N / IB) + 2 * (size_t)nrun;
             const size_t nch = (size_t)std::ceil(N / 64) + nrun;
             const size_t b = al(sizeof(int4) * (T + 1)) + al(sizeof(int4) * nrun) + al(sizeof(int) * rows) +
@@ -625,15 +651,15 @@ size_t ens_ws_bound(int64_t ntot, int32_t nrun) {
 
 template <int PREC, int P>
 static void go_ens_pair(unsigned T, const double* x, const double* y, const double* z, const double* q, double eps2,
-                        int JL, const int4* tiles, double* Pi, double* R, hipStream_t st) {
-    k_pair_sym_ens<PREC, P><<<T, 64, 0, st>>>(x, y, z, q, eps2, JL, tiles, Pi, R);
+                        int JL, int DL, const int4* tiles, double* Pi, double* R, hipStream_t st) {
+    k_pair_sym_ens<PREC, P><<<T, 64, 0, st>>>(x, y, z, q, eps2, JL, DL, tiles, Pi, R);
 }
 
 template <int PREC>
 static void go_ens_pair_p(int P, unsigned T, const double* x, const double* y, const double* z, const double* q,
-                          double eps2, int JL, const int4* tiles, double* Pi, double* R, hipStream_t st) {
-    if (P == 8) go_ens_pair<PREC, 8>(T, x, y, z, q, eps2, JL, tiles, Pi, R, st);
-    else go_ens_pair<PREC, 4>(T, x, y, z, q, eps2, JL, tiles, Pi, R, st);
+                          double eps2, int JL, int DL, const int4* tiles, double* Pi, double* R, hipStream_t st) {
+    if (P == 8) go_ens_pair<PREC, 8>(T, x, y, z, q, eps2, JL, DL, tiles, Pi, R, st);
+    else go_ens_pair<PREC, 4>(T, x, y, z, q, eps2, JL, DL, tiles, Pi, R, st);
 }
 
 cb_status md_run_ensemble(int32_t nrun, const int64_t* offsets, const cb_state* s, const double* q,
@@ -699,6 +725,7 @@ cb_status md_run_ensemble(int32_t nrun, const int64_t* offsets, const cb_state* 
     int lgJL = 0;
     while ((1 << lgJL) < JL) ++lgJL;
     EP.lgJL = lgJL;
+    EP.ndiag = E.ndiag;
     EP.eps2 = eps2;
     EP.t0 = t0;
     EP.dt = dt;
@@ -718,10 +745,10 @@ cb_status md_run_ensemble(int32_t nrun, const int64_t* offsets, const cb_state* 
     auto pair_stage = [&]() -> cb_status {
         if (T == 0) return CB_OK;
         switch (prec) {
-            case CB_FP64: go_ens_pair_p<PREC_FP64>(P, (unsigned)T, cur[0], cur[1], cur[2], q, eps2, JL, d_tiles, Pi, R, st); break;
-            case CB_MIXED: go_ens_pair_p<PREC_MIXED>(P, (unsigned)T, cur[0], cur[1], cur[2], q, eps2, JL, d_tiles, Pi, R, st); break;
-            case CB_FP64_IEEE: go_ens_pair_p<PREC_IEEE>(P, (unsigned)T, cur[0], cur[1], cur[2], q, eps2, JL, d_tiles, Pi, R, st); break;
-            default: go_ens_pair_p<PREC_FP32>(P, (unsigned)T, cur[0], cur[1], cur[2], q, eps2, JL, d_tiles, Pi, R, st); break;
+            case CB_FP64: go_ens_pair_p<PREC_FP64>(P, (unsigned)T, cur[0], cur[1], cur[2], q, eps2, JL, E.dl, d_tiles, Pi, R, st); break;
+            case CB_MIXED: go_ens_pair_p<PREC_MIXED>(P, (unsigned)T, cur[0], cur[1], cur[2], q, eps2, JL, E.dl, d_tiles, Pi, R, st); break;
+            case CB_FP64_IEEE: go_ens_pair_p<PREC_IEEE>(P, (unsigned)T, cur[0], cur[1], cur[2], q, eps2, JL, E.dl, d_tiles, Pi, R, st); break;
+            default: go_ens_pair_p<PREC_FP32>(P, (unsigned)T, cur[0], cur[1], cur[2], q, eps2, JL, E.dl, d_tiles, Pi, R, st); break;
         }
         return check_launch("k_pair_sym_ens");
     };

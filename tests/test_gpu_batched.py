@@ -232,15 +232,18 @@ def test_stepped_ensemble_block_edges_and_traps(api, oracle, prec, path):
     assert api.poll_flags() == 0
 
 
-@pytest.mark.parametrize("path", [STEPPED4, STEPPED8], ids=lambda p: "-".join(map(str, p)))
-def test_stepped_equals_persistent_and_is_deterministic(api, path):
-    """A Kibble-Zurek-shaped ensemble (40 runs, N uniform in [64, 4096], the
-    ramp) on both paths: trajectories agree to rounding (different summation
-    orders), and the stepped path repeats bit for bit.  Also without
-    CB_INIT_ACCEL (the state's a is used as a_0)."""
+@pytest.mark.parametrize("path,nrun", [(STEPPED4, 40), (STEPPED8, 40), (STEPPED4, 120)],
+                         ids=["stepped-4-256-40", "stepped-8-512-40", "stepped-4-256-120"])
+def test_stepped_equals_persistent_and_is_deterministic(api, path, nrun):
+    """A Kibble-Zurek-shaped ensemble (N uniform in [64, 4096], the ramp) on
+    both paths: trajectories agree to rounding (different summation orders),
+    and the stepped path repeats bit for bit.  Also without CB_INIT_ACCEL
+    (the state's a is used as a_0).  40 runs make a launch of fewer than
+    4096 off-diagonal tiles (each block's diagonal split into sub-tiles of
+    128 j's); 120 runs at 256-ion blocks make more (whole diagonals)."""
     import torch
     from _gpu_util import dev
-    d = inputs.kz512(nrun=40, nmin=64, nmax=4096, nsteps=6)
+    d = inputs.kz512(nrun=nrun, nmin=64, nmax=4096, nsteps=6)
     st = inputs.state9(d)
     q, m, offs = dev(d["q"]), dev(d["m"]), d["offsets"]
     runs = {}
