@@ -198,8 +198,8 @@ WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec) {
         L.ppot = off;
         if (op == CB_OP_ENERGY || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN)
             off += al(sizeof(double) * (size_t)kMaxSplits * N);
-        L.eblk = off;
-        off += al(sizeof(double) * 3 * (N / kEpiBlock + 2));
+        L.eblk = off;  // two sets of block partials (md_run alternates them) and a counter
+        off += al(sizeof(double) * 6 * (N / kEpiBlock + 2));
         L.aux = off;
         if (op == CB_OP_ADJOINT) off += al(sizeof(double) * 3 * N);
     } else {

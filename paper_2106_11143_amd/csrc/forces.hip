@@ -116,13 +116,30 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
     cb_status rc;
     const bool rec0 = energies && every > 0;
     const bool init = (flags & CB_INIT_ACCEL) != 0;
-    // arrival counter of the epilogue's final energy sum: after the block
-    // partials (whose region has room for it), zeroed once here
-    E.ecount = reinterpret_cast<unsigned*>(eblk + 3 * ((size_t)n / kEpiBlock + 1));
-    if (rec0) {
-        k_zero_u32<<<1, 1, 0, st>>>(E.ecount);
-        if ((rc = check_launch("k_zero_u32"))) return rc;
-    }
+    // Energy records: a recording epilogue leaves its block partials in one
+    // of two buffers (alternating), and the next epilogue launch sums them
+    // with one extra block (stream order makes them complete); a record on
+    // the last launch is summed by k_energy_final.
+    const size_t nbuf = 3 * ((size_t)n / kEpiBlock + 1);
+    double* ebuf[2] = {eblk, eblk + nbuf};
+    int parity = 0;
+    const double* pend = nullptr;
+    double* pend_out = nullptr;
+    E.efinal = nullptr;
+    E.ecount = nullptr;
+    auto epilogue = [&](double* rec_out) -> cb_status {
+        E.eblk = ebuf[parity];
+        E.eprev = pend;
+        E.eprev_out = pend_out;
+        E.nprev = nb;
+        k_epilogue<<<nb + (pend ? 1 : 0), kEpiThreads, 0, st>>>(E);
+        cb_status r = check_launch("k_epilogue");
+        if (r) return r;
+        pend = rec_out ? ebuf[parity] : nullptr;
+        pend_out = rec_out;
+        if (rec_out) parity ^= 1;
+        return CB_OK;
+    };
 
     bool prescaled_now = false;
     // Force (and potential) pair launch: the potential needs the direct kernel;
@@ -148,19 +165,17 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
     E.step = 0;
     E.mode = (init ? EPI_ACCEL : 0u) | (rec0 ? EPI_ENERGY : 0u) | (nsteps > 0 ? EPI_DRIFT : 0u);
     if (prescaled_now) E.mode |= EPI_PRESCALED;
-    E.efinal = rec0 ? energies : nullptr;
-    if (E.mode) {
-        k_epilogue<<<nb, kEpiThreads, 0, st>>>(E);
-        if ((rc = check_launch("k_epilogue"))) return rc;
-    }
+    if (E.mode && (rc = epilogue(rec0 ? energies : nullptr))) return rc;
     for (int64_t k = 1; k <= nsteps; ++k) {
         const bool rec = rec0 && (k % every == 0);
         if ((rc = pairs(true, rec))) return rc;
         E.step = k;
         E.mode = EPI_KICK | (rec ? EPI_ENERGY : 0u) | (k < nsteps ? EPI_DRIFT : 0u) | (prescaled_now ? EPI_PRESCALED : 0u);
-        E.efinal = rec ? energies + 4 * (k / every) : nullptr;
-        k_epilogue<<<nb, kEpiThreads, 0, st>>>(E);
-        if ((rc = check_launch("k_epilogue"))) return rc;
+        if ((rc = epilogue(rec ? energies + 4 * (k / every) : nullptr))) return rc;
+    }
+    if (pend) {
+        k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, pend, pend_out, 0);
+        if ((rc = check_launch("k_energy_final"))) return rc;
     }
     return ok();
 }

@@ -29,11 +29,47 @@ struct EpiParams {
     // is zero at launch and is left zero.
     double* efinal;
     unsigned* ecount;
+    // Deferred finish of an earlier energy record (md_run; not together
+    // with efinal): with eprev set, one extra block after the ions' blocks
+    // sums the nprev block partials at eprev, written by an earlier launch
+    // on the stream and so complete, in block order into eprev_out (K, U_C,
+    // U_trap, E).  The sum is the one the last-arriving block would form.
+    const double* eprev;
+    double* eprev_out;
+    int nprev;
 };
+
+// Sums nb block partials [nb][3] in a fixed order into out: with uc_only,
+// out[0] = U_C; otherwise out[0..3] = K, U_C, U_trap, K + U_C + U_trap.
+// Called by every thread of one block.
+__device__ __forceinline__ void sum_record(int nb, const double* __restrict__ eblk, double* __restrict__ out,
+                                           int uc_only) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int k = threadIdx.x; k < nb; k += kEpiThreads) {
+        a += eblk[k * 3 + 0];
+        b += eblk[k * 3 + 1];
+        c += eblk[k * 3 + 2];
+    }
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) {
+        if (uc_only) {
+            out[0] = b;
+        } else {
+            out[0] = a;
+            out[1] = b;
+            out[2] = c;
+            out[3] = a + b + c;
+        }
+    }
+}
 
 __global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 
 __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
+    if (P.eprev && blockIdx.x == gridDim.x - 1) {  // the extra block: an earlier record's sum
+        sum_record(P.nprev, P.eprev, P.eprev_out, 0);
+        return;
+    }
     const int i = blockIdx.x * kEpiThreads + threadIdx.x;
     double eK = 0.0, eC = 0.0, eT = 0.0;
     const unsigned mode = P.mode;
@@ -161,27 +197,10 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
     }
 }
 
-// Sums nb block partials [nb][3] in a fixed order into out: with uc_only,
-// out[0] = U_C; otherwise out[0..3] = K, U_C, U_trap, K + U_C + U_trap.
+// One block: sum_record of nb block partials.
 __global__ void __launch_bounds__(kEpiThreads) k_energy_final(int nb, const double* __restrict__ eblk,
                                                              double* __restrict__ out, int uc_only) {
-    double a = 0.0, b = 0.0, c = 0.0;
-    for (int k = threadIdx.x; k < nb; k += kEpiThreads) {
-        a += eblk[k * 3 + 0];
-        b += eblk[k * 3 + 1];
-        c += eblk[k * 3 + 2];
-    }
-    block_sum3(a, b, c);
-    if (threadIdx.x == 0) {
-        if (uc_only) {
-            out[0] = b;
-        } else {
-            out[0] = a;
-            out[1] = b;
-            out[2] = c;
-            out[3] = a + b + c;
-        }
-    }
+    sum_record(nb, eblk, out, uc_only);
 }
 
 }  // namespace cb
