@@ -622,6 +622,11 @@ static EnsTables ens_tables(int nrun, const int64_t* offsets, int IB, int JL) {
     return E;
 }
 
+// From this many 64-ion chunks on, the finish gives each chunk 2 waves
+// instead of 4 (kz512, 16 700 chunks: 1.31-1.34 against 1.33-1.37 ms per
+// step; 1 wave measured the same as 2, 8 waves 1.41).
+constexpr unsigned kFinishTwoWaves = 4096;
+
 static int whole_ib(int64_t nmax) { return (int)((nmax + 63) / 64 * 64); }
 
 // Upper bound of ens_tables(...).bytes over every ensemble of ntot ions in
@@ -773,12 +778,19 @@ cb_status md_run_ensemble(int32_t nrun, const int64_t* offsets, const cb_state* 
                 case CB_FP64_IEEE: k_ens_step<PREC_IEEE, 16, true><<<g, 1024, 0, st>>>(EP); break;
                 default: k_ens_step<PREC_FP32, 16, true><<<g, 1024, 0, st>>>(EP); break;
             }
-        } else {
+        } else if (g < kFinishTwoWaves) {  // few chunks: 4 waves share each
             switch (prec) {
                 case CB_FP64: k_ens_step<PREC_FP64, 4, false><<<g, 256, 0, st>>>(EP); break;
                 case CB_MIXED: k_ens_step<PREC_MIXED, 4, false><<<g, 256, 0, st>>>(EP); break;
                 case CB_FP64_IEEE: k_ens_step<PREC_IEEE, 4, false><<<g, 256, 0, st>>>(EP); break;
                 default: k_ens_step<PREC_FP32, 4, false><<<g, 256, 0, st>>>(EP); break;
+            }
+        } else {  // many chunks fill the chip with 2 waves each
+            switch (prec) {
+                case CB_FP64: k_ens_step<PREC_FP64, 2, false><<<g, 128, 0, st>>>(EP); break;
+                case CB_MIXED: k_ens_step<PREC_MIXED, 2, false><<<g, 128, 0, st>>>(EP); break;
+                case CB_FP64_IEEE: k_ens_step<PREC_IEEE, 2, false><<<g, 128, 0, st>>>(EP); break;
+                default: k_ens_step<PREC_FP32, 2, false><<<g, 128, 0, st>>>(EP); break;
             }
         }
         cb_status rc = check_launch("k_ens_step");

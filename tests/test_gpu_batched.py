@@ -240,7 +240,8 @@ def test_stepped_equals_persistent_and_is_deterministic(api, path, nrun):
     and the stepped path repeats bit for bit.  Also without CB_INIT_ACCEL
     (the state's a is used as a_0).  40 runs make a launch of fewer than
     4096 off-diagonal tiles (each block's diagonal split into sub-tiles of
-    128 j's); 120 runs at 256-ion blocks make more (whole diagonals)."""
+    128 j's); 120 runs at 256-ion blocks make more (whole diagonals) and
+    more than 4096 64-ion chunks (2 finishing waves per chunk, not 4)."""
     import torch
     from _gpu_util import dev
     d = inputs.kz512(nrun=nrun, nmin=64, nmax=4096, nsteps=6)
