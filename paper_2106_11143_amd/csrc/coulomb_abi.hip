@@ -127,7 +127,11 @@ LaunchCfg default_cfg(int op, int64_t n, int prec) {
     if (hv || small) c.wg = 256;
     int64_t s = ((hv ? 3072 : (small ? 4096 : 65536)) + waves - 1) / waves;
     s = std::max<int64_t>(1, std::min<int64_t>(s, kMaxSplits));
-    s = std::min<int64_t>(s, std::max<int64_t>(1, n / 64));
+    // j-ranges of at least 64, or 32 for the force kernel up to 1024 ions:
+    // md_run at 1024 ions with energies every step took 16.5 us per step at
+    // 32 splits of 32 j's, 17.2 at 16 splits and 21 at 64; at 2048 and 3000
+    // ions 64 splits were slower than 32 and 46 (measured on MI355X)
+    s = std::min<int64_t>(s, std::max<int64_t>(1, n / (hv || n > 1024 ? 64 : 32)));
     c.splits = (int)s;
     return c;
 }
