@@ -71,8 +71,10 @@ __global__ void __launch_bounds__(kEpiThreads) k_hvp_epi(int n, int S, int nv, c
     const size_t stride = (size_t)nv * 3 * n;
     for (int b = 0; b < nv; ++b) {
         double s[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) s[d] = split_sum(part + ((size_t)b * 3 + d) * n + i, stride, S);
+        const double* ps[3] = {part + ((size_t)b * 3) * n + i, part + ((size_t)b * 3 + 1) * n + i,
+                               part + ((size_t)b * 3 + 2) * n + i};
+        const size_t st[3] = {stride, stride, stride};
+        split_sums<3>(ps, st, S, s);  // the vector's three components' loads together
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             double h = c * s[d];
@@ -120,8 +122,9 @@ __global__ void __launch_bounds__(kEpiThreads) k_adj_post(int n, int S, const do
             const double kk[3] = {k.kx, k.ky, k.kz};
             const double cq = kCoulomb * q[i];
             double ss[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) ss[c] = split_sum(part + (size_t)c * n + i, 3 * (size_t)n, S);
+            const double* ps[3] = {part + i, part + (size_t)n + i, part + 2 * (size_t)n + i};
+            const size_t st[3] = {3 * (size_t)n, 3 * (size_t)n, 3 * (size_t)n};
+            split_sums<3>(ps, st, S, ss);  // the three components' loads together
             for (int c = 0; c < 3; ++c) {
                 const double s = ss[c];
                 const size_t e = (size_t)c * n + i;

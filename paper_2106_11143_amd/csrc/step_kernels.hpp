@@ -78,12 +78,27 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
         double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
         const bool need_f = (mode & (EPI_FORCES | EPI_ACCEL | EPI_KICK)) != 0;
         const bool need_p = (mode & EPI_ENERGY) && P.ppot != nullptr;
-        if (need_f) {
-            sx = split_sum(P.part + i, 3 * (size_t)n, P.S);
-            sy = split_sum(P.part + n + i, 3 * (size_t)n, P.S);
-            sz = split_sum(P.part + 2 * (size_t)n + i, 3 * (size_t)n, P.S);
+        const size_t n3 = 3 * (size_t)n;
+        if (need_f && need_p) {  // the four arrays' loads together
+            const double* ps[4] = {P.part + i, P.part + n + i, P.part + 2 * (size_t)n + i, P.ppot + i};
+            const size_t st[4] = {n3, n3, n3, (size_t)n};
+            double o[4];
+            split_sums<4>(ps, st, P.S, o);
+            sx = o[0];
+            sy = o[1];
+            sz = o[2];
+            sp = o[3];
+        } else if (need_f) {
+            const double* ps[3] = {P.part + i, P.part + n + i, P.part + 2 * (size_t)n + i};
+            const size_t st[3] = {n3, n3, n3};
+            double o[3];
+            split_sums<3>(ps, st, P.S, o);
+            sx = o[0];
+            sy = o[1];
+            sz = o[2];
+        } else if (need_p) {
+            sp = split_sum(P.ppot + i, (size_t)n, P.S);
         }
-        if (need_p) sp = split_sum(P.ppot + i, (size_t)n, P.S);
         const double c = kCoulomb * P.q[i];
         const double cf = (mode & EPI_PRESCALED) ? 1.0 : c;
         const double Fx = cf * sx, Fy = cf * sy, Fz = cf * sz;
