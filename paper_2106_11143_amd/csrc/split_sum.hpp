@@ -25,12 +25,11 @@ __device__ __forceinline__ double split_sum(const double* __restrict__ p, size_t
 }
 
 // The same sum for NA arrays at once, out[a] = sum_{s < S} p[a][s * stride[a]]:
-// the loads of 8 splits of every array are issued before their sums, so NA
+// the loads of U splits of every array are issued before their sums, so NA
 // arrays cost the round trips of one.  Each sum is in split order, as above.
-template <int NA>
+template <int NA, int U = 8>
 __device__ __forceinline__ void split_sums(const double* const (&p)[NA], const size_t (&stride)[NA], int S,
                                            double (&out)[NA]) {
-    constexpr int U = 8;
 #pragma unroll
     for (int c = 0; c < NA; ++c) out[c] = 0.0;
     int s = 0;

@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
             const double* ps[4] = {P.part + i, P.part + n + i, P.part + 2 * (size_t)n + i, P.ppot + i};
             const size_t st[4] = {n3, n3, n3, (size_t)n};
             double o[4];
-            split_sums<4>(ps, st, P.S, o);
+            split_sums<4, 16>(ps, st, P.S, o);
             sx = o[0];
             sy = o[1];
             sz = o[2];
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
             const double* ps[3] = {P.part + i, P.part + n + i, P.part + 2 * (size_t)n + i};
             const size_t st[3] = {n3, n3, n3};
             double o[3];
-            split_sums<3>(ps, st, P.S, o);
+            split_sums<3, 16>(ps, st, P.S, o);
             sx = o[0];
             sy = o[1];
             sz = o[2];
