@@ -531,8 +531,9 @@ __global__ void __launch_bounds__(64) k_small_step(EnsParams P) {
     __threadfence();  // every part of this chunk is visible
     double t[4];
     const double* pc = P.spart + (size_t)c * S * 4 * 64 + lane;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) t[v] = split_sum(pc + v * 64, 4 * 64, S);
+    const double* ps[4] = {pc, pc + 64, pc + 128, pc + 192};
+    const size_t st[4] = {4 * 64, 4 * 64, 4 * 64, 4 * 64};
+    split_sums<4>(ps, st, S, t);  // the four sums' loads together, each in part order
     if (lane == 0) P.scount[c] = 0u;
     double eK = 0.0, eC = 0.0, eT = 0.0;
     if (k < n) {
