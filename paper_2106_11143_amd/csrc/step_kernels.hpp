@@ -79,6 +79,23 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
         const bool need_f = (mode & (EPI_FORCES | EPI_ACCEL | EPI_KICK)) != 0;
         const bool need_p = (mode & EPI_ENERGY) && P.ppot != nullptr;
         const size_t n3 = 3 * (size_t)n;
+        // the ion's state, requested before the partials so that both
+        // round trips overlap (only this thread touches ion i)
+        const bool need_s = (mode & (EPI_ACCEL | EPI_KICK | EPI_DRIFT | EPI_ENERGY)) && !(mode & EPI_UC_ONLY);
+        double x = 0.0, y = 0.0, z = 0.0, vx = 0.0, vy = 0.0, vz = 0.0, ax = 0.0, ay = 0.0, az = 0.0, mi = 1.0;
+        if (need_s) {
+            x = P.x[i];
+            y = P.y[i];
+            z = P.z[i];
+            vx = P.vx[i];
+            vy = P.vy[i];
+            vz = P.vz[i];
+            ax = P.ax[i];
+            ay = P.ay[i];
+            az = P.az[i];
+            mi = P.m[i];
+        }
+        const double qi = P.q[i];
         if (need_f && need_p) {  // the four arrays' loads together
             const double* ps[4] = {P.part + i, P.part + n + i, P.part + 2 * (size_t)n + i, P.ppot + i};
             const size_t st[4] = {n3, n3, n3, (size_t)n};
@@ -99,7 +116,7 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
         } else if (need_p) {
             sp = split_sum(P.ppot + i, (size_t)n, P.S);
         }
-        const double c = kCoulomb * P.q[i];
+        const double c = kCoulomb * qi;
         const double cf = (mode & EPI_PRESCALED) ? 1.0 : c;
         const double Fx = cf * sx, Fy = cf * sy, Fz = cf * sz;
         bool ok = true;
@@ -113,10 +130,6 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
             eC = 0.5 * c * sp;
             ok = ok && __builtin_isfinite(eC);
         } else if (mode & (EPI_ACCEL | EPI_KICK | EPI_DRIFT | EPI_ENERGY)) {
-            double x = P.x[i], y = P.y[i], z = P.z[i];
-            double vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
-            double ax = P.ax[i], ay = P.ay[i], az = P.az[i];
-            const double mi = P.m[i];
             const double t = step_time(P.t0, P.dt, P.step);
             const TrapK k = trap_k(P.trap, t);
             if (mode & (EPI_ACCEL | EPI_KICK)) {
