@@ -39,6 +39,38 @@ struct EpiParams {
     int nprev;
 };
 
+// a, b, c summed over the block (every thread gets the sums): a butterfly of
+// cross-lane exchanges within each wave (lanes exchanging the same two values
+// add them in either order to the same result), then the waves' sums in wave
+// order.  One barrier pair instead of a tree through LDS.
+__device__ __forceinline__ void block_sum3_waves(double& a, double& b, double& c) {
+    constexpr int kWaves = kEpiThreads / 64;
+    __shared__ double sh[3][kWaves];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+        c += __shfl_xor(c, o);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][w] = a;
+        sh[1][w] = b;
+        sh[2][w] = c;
+    }
+    __syncthreads();
+    a = sh[0][0];
+    b = sh[1][0];
+    c = sh[2][0];
+#pragma unroll
+    for (int k = 1; k < kWaves; ++k) {
+        a += sh[0][k];
+        b += sh[1][k];
+        c += sh[2][k];
+    }
+    __syncthreads();  // sh may be reused by a later call
+}
+
 // Sums nb block partials [nb][3] in a fixed order into out: with uc_only,
 // out[0] = U_C; otherwise out[0..3] = K, U_C, U_trap, K + U_C + U_trap.
 // Called by every thread of one block.
@@ -50,7 +82,7 @@ __device__ __forceinline__ void sum_record(int nb, const double* __restrict__ eb
         b += eblk[k * 3 + 1];
         c += eblk[k * 3 + 2];
     }
-    block_sum3(a, b, c);
+    block_sum3_waves(a, b, c);
     if (threadIdx.x == 0) {
         if (uc_only) {
             out[0] = b;
@@ -187,7 +219,7 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
         if (!ok) atomicOr(P.flags, 1u);
     }
     if (mode & EPI_ENERGY) {
-        block_sum3(eK, eC, eT);
+        block_sum3_waves(eK, eC, eT);
         if (threadIdx.x == 0) {
             P.eblk[blockIdx.x * 3 + 0] = eK;
             P.eblk[blockIdx.x * 3 + 1] = eC;
@@ -208,7 +240,7 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
                     b += P.eblk[k * 3 + 1];
                     c += P.eblk[k * 3 + 2];
                 }
-                block_sum3(a, b, c);
+                block_sum3_waves(a, b, c);
                 if (threadIdx.x == 0) {
                     if (mode & EPI_UC_ONLY) {
                         P.efinal[0] = b;
