@@ -92,9 +92,10 @@ LaunchCfg default_cfg(int op, int64_t n, int prec) {
     const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
     if ((op == CB_OP_MD_STEP || op == CB_OP_MD_RUN) && n <= kSmallRunDefault) {
         // One launch per step: for a few hundred ions the two-launch step is
-        // bound by the latency of its second launch (measured on MI355X: 8.3
-        // against 12.9 us per step at 256 ions; from 1024 ions the two-launch
-        // step is faster).
+        // bound by the latency of its second launch (measured on MI355X with
+        // energy records every step: 10.2 against 10.6 us per step at 256
+        // ions, 12.2 against 12.7 at 384; at 512 ions the two-launch step is
+        // faster, 11.2 against 13.5).
         c.algo = ALGO_SMALL;
         c.p = 1;
         c.wg = 64;

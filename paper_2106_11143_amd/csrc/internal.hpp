@@ -124,7 +124,7 @@ cb_status md_run_ensemble(int32_t nrun, const int64_t* offsets, const cb_state* 
 // (ensemble.hip), with S j-parts per 64 ions (1..kSmallPartsMax): workspace
 // bytes, the default S and the driver.
 constexpr int64_t kSmallRunMax = 8192;
-constexpr int64_t kSmallRunDefault = 512;  // largest run that takes it by default
+constexpr int64_t kSmallRunDefault = 384;  // largest run that takes it by default
 constexpr int kSmallPartsMax = 32;
 size_t md_small_ws_bytes(int64_t n, int S);
 int small_parts(int64_t n);

@@ -257,7 +257,7 @@ def test_energy_records_next_to_the_state_are_not_aliases(api, nrun):
 def test_small_run_path_matches_two_launch_path_and_oracle(api, oracle, n):
     """Runs of at most 8192 ions can take one launch per step (algorithm 3:
     every pair of the run evaluated directly by one wave per 64 ions and
-    j-part, then trap, kick and drift; the default up to 512 ions) or the
+    j-part, then trap, kick and drift; the default up to 384 ions) or the
     two-launch step (algorithm 0).  Both agree to rounding, with and without
     CB_INIT_ACCEL, on an RF trap with friction, energies every other step;
     small runs also against the oracle."""
