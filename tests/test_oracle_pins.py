@@ -197,8 +197,8 @@ def test_single_ion_harmonic_matches_exact_discrete_solution(oracle):
     assert abs(th / (trap["wx"] * dt) - 1.0 - (trap["wx"] * dt) ** 2 / 24.0) < 1e-9
 
 
-def _rf_monodromy(oracle, q, omega_hz, steps):
-    trap = inputs.rf_trap(0.0, q, omega_hz, 0.1e6)
+def _rf_monodromy(oracle, q, omega_hz, steps, a=0.0, phase=0.0):
+    trap = inputs.rf_trap(a, q, omega_hz, 0.1e6, phase=phase)
     dt = 1.0 / omega_hz / steps
     cols = []
     for x0, v0 in ((1e-6, 0.0), (0.0, 1.0)):
@@ -236,6 +236,69 @@ def test_rf_drive_matches_mathieu_equation(oracle):
     for a, b in zip(errs, errs[1:]):
         assert 3.0 < a / b < 5.0
     assert errs[-1] < 1e-4
+
+
+def _mathieu_monodromy_scaled(a, q, W, phase, sign):
+    """Monodromy over one RF period of u'' = -sign (a W^2/4 + q W^2/2 cos(W t + phase)) u,
+    solved by DOP853 in the scaled variables (u, u'/W); sign = +1 is the x
+    axis of the drive and -1 the y axis."""
+    from scipy.integrate import solve_ivp
+
+    def rhs(tau, s):  # tau = W t
+        return [s[1], -sign * (a / 4.0 + q / 2.0 * math.cos(tau + phase)) * s[0]]
+
+    cols = [solve_ivp(rhs, (0.0, TWO_PI), s0, method="DOP853", rtol=1e-13, atol=1e-15).y[:, -1]
+            for s0 in ([1.0, 0.0], [0.0, 1.0])]
+    return np.array(cols).T
+
+
+@pytest.mark.parametrize("a,phase", [(0.02, 0.7), (-0.03, 2.5), (0.0, -1.1)])
+def test_rf_drive_a_term_and_phase_match_mathieu_equation(oracle, a, phase):
+    """The RF drive with a DC term a and a phase: a_x = -(a W^2/4 + q W^2/2
+    cos(W t + phase)) x and the opposite sign on y.  The oracle's one-period
+    map on each axis converges at second order, entry by entry, to the
+    Mathieu monodromy solved independently (the trace alone would not see
+    the phase: it is invariant under a shift of the start)."""
+    q, f = 0.3, 10.0e6
+    W = TWO_PI * f
+    refs = {s: _mathieu_monodromy_scaled(a, q, W, phase, s) for s in (+1, -1)}
+    errs = []
+    for steps in (20, 40, 80, 160):
+        Mx, My = _rf_monodromy(oracle, q, f, steps, a=a, phase=phase)
+        e = 0.0
+        for M, sign in ((Mx, +1), (My, -1)):
+            assert abs(np.linalg.det(M) - 1.0) < 1e-11  # velocity-Verlet is symplectic
+            S = np.array([[M[0, 0], M[0, 1] * W], [M[1, 0] / W, M[1, 1]]])  # in (u, u'/W)
+            e = max(e, np.abs(S - refs[sign]).max())
+        errs.append(e)
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 3.0 < e1 / e2 < 5.0, errs
+    assert errs[-1] < 1e-3
+    # the phase and the DC term change the map (the test is not vacuous)
+    M0, _ = _rf_monodromy(oracle, q, f, 160)
+    assert abs(M0[0, 0] - Mx[0, 0]) > 100 * errs[-1]
+
+
+@pytest.mark.parametrize("trap,t", [
+    (inputs.rf_trap(0.02, 0.3, 10e6, 0.1e6, phase=0.7), 3.7e-8),
+    (inputs.rf_trap(-0.03, 0.25, 7e6, 0.2e6, phase=-2.0), 1.1e-7),
+    (inputs.ramp_trap(1.5e6, 0.6e6, 0.15e6, 0.0, 20e-6), 7e-6),
+    (inputs.pseudo_trap(1.0e6, 0.8e6, 0.2e6), 0.0),
+])
+def test_trap_acceleration_is_minus_trap_energy_gradient(oracle, trap, t):
+    """One ion (no Coulomb force): m a_trap = -dU_trap/dr by central
+    differences of the trap energy (exact up to rounding: U is quadratic)."""
+    r = np.array([3e-6, -2e-6, 5e-6])
+    m = [M40]
+    a = oracle.accel([r[0]], [r[1]], [r[2]], [E], m, trap, t)[:, 0]
+    for c in range(3):
+        h = 1e-3 * abs(r[c])
+        rp, rm = r.copy(), r.copy()
+        rp[c] += h
+        rm[c] -= h
+        du = oracle.trap_energy(*rp[:, None], m, trap, t) - oracle.trap_energy(*rm[:, None], m, trap, t)
+        grad = du / (2 * h)
+        assert abs(-grad - M40 * a[c]) <= 1e-9 * abs(M40 * a[c]) + 1e-40, (c, -grad, M40 * a[c])
 
 
 def test_rf_secular_frequency_low_q_limit(oracle):
