@@ -97,6 +97,29 @@ def test_batched_ramp_matches_oracle_run_by_run(api, oracle, prec, path):
 
 
 @pytest.mark.parametrize("path", PATHS, ids=lambda p: "-".join(map(str, p)))
+def test_batched_rf_drive_with_a_term_and_phase_matches_oracle(api, oracle, path):
+    """Runs of one ensemble, each with its own RF drive with a DC term and a
+    phase (a != 0, phi != 0), against the oracle run by run, on both ensemble
+    paths."""
+    from _gpu_util import dev
+    sizes = [64, 300, 1000, 257]
+    traps = [inputs.rf_trap(0.02, 0.3, 10e6, 0.15e6, phase=0.7), inputs.rf_trap(-0.03, 0.25, 10e6, 0.2e6, phase=2.5),
+             inputs.rf_trap(0.01, 0.3, 8e6, 0.15e6, phase=-1.1), inputs.rf_trap(0.0, 0.2, 10e6, 0.1e6, phase=0.3)]
+    parts, offs, q, m = _ensemble(sizes, 17, inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6))
+    st = np.concatenate(parts, axis=1)
+    ts = [dev(st[k]) for k in range(9)]
+    dt, nsteps, every = 5e-9, 30, 10
+    with _path(api, offs[-1], "fp64", path):
+        en = api.md_run(ts, dev(q), dev(m), traps, 0.0, dt, nsteps, offsets=offs, every=every)
+    got = np.stack([t.cpu().numpy() for t in ts])
+    en = en.cpu().numpy()
+    for r in range(len(sizes)):
+        sl = slice(offs[r], offs[r + 1])
+        _check_run(oracle, parts[r], q[sl], m[sl], traps[r], dt, nsteps, got[:, sl], en[r], every, f"run{r}")
+    assert api.poll_flags() == 0
+
+
+@pytest.mark.parametrize("path", PATHS, ids=lambda p: "-".join(map(str, p)))
 def test_batched_equals_single_run_path(api, path):
     from _gpu_util import dev
     trap = inputs.pseudo_trap(1.0e6, 1.0e6, 0.15e6)

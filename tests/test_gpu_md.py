@@ -299,3 +299,42 @@ def test_small_run_path_matches_two_launch_path_and_oracle(api, oracle, n):
         for blk in (slice(0, 3), slice(3, 6), slice(6, 9)):
             assert np.abs(got[blk] - ref[blk]).max() <= 1e-11 * np.abs(ref[blk]).max(), (n, blk)
         assert np.abs(en - en_ref).max() <= 1e-11 * np.abs(en_ref).max()
+
+
+@pytest.mark.parametrize("n,algo", [(300, 3), (300, 0), (1000, 0), (20000, 2)])
+def test_rf_drive_with_a_term_and_phase_matches_oracle(api, oracle, n, algo):
+    """The explicit RF drive with a DC term and a phase (a != 0, phi != 0) on
+    every single-run path: the one-launch step (algorithm 3), the two-launch
+    step with the direct kernel (0) and with the Newton's-third-law stage (2),
+    against the oracle within its round-off envelope, energies included."""
+    from _gpu_util import dev, state_host, state_tensors
+    d = inputs.rf32768(n=n, seed=41)
+    trap = inputs.rf_trap(0.02, 0.3, 10e6, 0.1e6, phase=0.7)
+    st = inputs.state9(d)
+    g = np.random.Generator(np.random.PCG64(42))
+    st[3:6] = inputs.maxwell(g, n, 10e-3, M40)
+    nsteps, every = (24, 4) if n <= 1000 else (6, 3)
+    if algo == 3:
+        api.set_config("md_run", n, "fp64", p=1, wg=64, splits=4, algo=3)
+    elif algo == 0:
+        api.set_config("md_run", n, "fp64", p=1, wg=64, splits=max(1, n // 64), algo=0)
+    else:
+        api.set_config("md_run", n, "fp64", p=4, wg=4, splits=256, algo=2)
+    try:
+        ref, en_ref, alt, en_alt = _oracle_envelope(oracle, st, d["q"], d["m"], trap, d["dt"], nsteps, every)
+        ts = state_tensors(st)
+        en = api.md_run(ts, dev(d["q"]), dev(d["m"]), trap, 0.0, d["dt"], nsteps, every=every)
+        got = state_host(ts)
+    finally:
+        api.reset_config("md_run", n, "fp64")
+    for blk in (slice(0, 3), slice(3, 6), slice(6, 9)):
+        D = np.abs(alt[blk] - ref[blk]).max()
+        err = np.abs(got[blk] - ref[blk]).max()
+        print(f"[rf a,phi n={n} algo={algo}] block {blk}: err={err:.3e} envelope={D:.3e}", flush=True)
+        assert err <= 10 * D + 1e-13 * np.abs(ref[blk]).max(), (blk, err, D)
+    en = en.cpu().numpy()[0]
+    assert np.all(np.abs(en - en_ref) <= 10 * np.abs(en_alt - en_ref) + 1e-12 * np.abs(en_ref).max(axis=0))
+    # the DC term and the phase change the trajectory (the test is not vacuous)
+    plain, _, _ = oracle.md_run(st, d["q"], d["m"], inputs.rf_trap(0.0, 0.3, 10e6, 0.1e6), 0.0, d["dt"], nsteps)
+    assert np.abs(plain[6:9] - ref[6:9]).max() > 1e3 * np.abs(got[6:9] - ref[6:9]).max()
+    assert api.poll_flags() == 0
