@@ -68,7 +68,11 @@ typedef enum {
  *  CB_FP64      FP32 hardware estimate of the FP32-rounded r^2, refined to
  *               full double precision by a second-order correction of
  *               q r^-3 (one order beyond the Newton-Raphson step of
- *               section 4); FP64 throughout.  The default.
+ *               section 4); all arithmetic but the estimate is FP64.  The
+ *               default.  Like CB_MIXED it requires r^2 + eps2 inside the
+ *               FP32 normal range (1.2e-38 .. 3.4e38 m^2; ion spacings from
+ *               1.1e-19 m to 1.8e19 m), which every trapped-ion geometry
+ *               meets; CB_FP64_IEEE has no such limit.
  *  CB_MIXED     FP32 hardware estimate of the FP32-rounded r^2 followed by ONE
  *               FP64 Newton-Raphson step on the FP64 r^2 (the analogue of the
  *               paper's "RSQRT14 + 1 N-W"); displacements, r^2, the force
@@ -95,9 +99,11 @@ typedef enum {
 
 /* Operation codes for cb_workspace_size / cb_autotune.  CB_OP_MD_ENSEMBLE
  * only keys the launch configuration of md_run with nrun > 1
- * (cb_get_config / cb_set_config); its workspace is that of CB_OP_MD_RUN. */
+ * (cb_get_config / cb_set_config); its workspace is that of CB_OP_MD_RUN.
+ * CB_OP_GRAD only sizes the workspace of coulomb_trap_grad (whose launches
+ * follow the CB_OP_FORCES and CB_OP_ENERGY configurations). */
 typedef enum { CB_OP_FORCES = 0, CB_OP_ENERGY = 1, CB_OP_MD_STEP = 2, CB_OP_MD_RUN = 3,
-               CB_OP_HVP = 4, CB_OP_ADJOINT = 5, CB_OP_MD_ENSEMBLE = 6 } cb_op;
+               CB_OP_HVP = 4, CB_OP_ADJOINT = 5, CB_OP_MD_ENSEMBLE = 6, CB_OP_GRAD = 7 } cb_op;
 
 /* md_run flags. */
 #define CB_INIT_ACCEL 1u /* compute a(r_0, t0) before the first step instead of using s->a* */
@@ -175,6 +181,30 @@ cb_status coulomb_pair_stage(int64_t n, const double* x, const double* y, const 
  * fixed order (deterministic). */
 cb_status coulomb_energy(int64_t n, const double* x, const double* y, const double* z, const double* q,
                          double eps2, int32_t prec, double* u_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Gradient and value of the potential energy of eq. (1) at time t,
+ *   U = U_C + U_trap(t),   g_i = dU/dr_i = -F_i + m_i k(t) r_i,
+ * with F the Coulomb forces of coulomb_forces and k(t) the trap's spring
+ * constants per unit mass (cb_trap_k).  m NULL: the Coulomb part alone
+ * (trap ignored).  gx, gy, gz: outputs (device, n doubles each), all three
+ * or none; u_out: output (device, one double: U in J) or NULL; at least one
+ * of the two is requested.  Outputs must not alias inputs or each other.
+ * The gradient alone takes the configured force stage (CB_OP_FORCES); with
+ * the energy, the all-pairs kernel evaluates forces and potentials in one
+ * pass (CB_OP_ENERGY's configuration).  The trap terms are added in the same
+ * element-wise pass that finishes the Coulomb sums.  Workspace:
+ * cb_workspace_size(CB_OP_GRAD, n, 1, 1, prec).  (Used by the autograd
+ * functions and the minimiser, so that no trap arithmetic runs outside the
+ * library.) */
+cb_status coulomb_trap_grad(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                            const double* m, const cb_trap* trap, double t, double eps2, int32_t prec, double* gx,
+                            double* gy, double* gz, double* u_out, void* ws, size_t ws_bytes, void* stream);
+
+/* The trap's spring constants per unit mass at time t into k_out[3] (host),
+ * so that the trap acceleration is -(kx x, ky y, kz z) (eq. (1); see
+ * cb_trap for the pseudo-potential, its ramp and the RF drive in Mathieu
+ * form).  The same function the kernels evaluate.  Host only; no GPU work. */
+cb_status cb_trap_k(const cb_trap* trap, double t, double k_out[3]);
 
 /* One velocity-Verlet step from time t (section 2): s holds (r_n, v_n, a_n)
  * on entry and (r_{n+1}, v_{n+1}, a_{n+1}) on return, with a_{n+1} taken at

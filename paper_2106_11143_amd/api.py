@@ -23,13 +23,13 @@ LIB_PATH = os.path.join(_HERE, "libcoulomb_mi355x.so")
 CB_OK, CB_EINVAL, CB_EHIP, CB_ENOWS, CB_ENONFINITE, CB_EUNSUPPORTED = range(6)
 STATUS_NAMES = {0: "CB_OK", 1: "CB_EINVAL", 2: "CB_EHIP", 3: "CB_ENOWS", 4: "CB_ENONFINITE", 5: "CB_EUNSUPPORTED"}
 PRECISIONS = {"fp64": 0, "mixed": 1, "ieee": 2, "fp32": 3, "mixed_f32d": 4}
-OPS = {"forces": 0, "energy": 1, "md_step": 2, "md_run": 3, "hvp": 4, "adjoint": 5, "md_ensemble": 6}
+OPS = {"forces": 0, "energy": 1, "md_step": 2, "md_run": 3, "hvp": 4, "adjoint": 5, "md_ensemble": 6, "grad": 7}
 CB_INIT_ACCEL = 1
 CB_ADJ_FINAL = 1
 
-EXPORTS = ("cb_workspace_size", "coulomb_forces", "coulomb_forces_range", "coulomb_pair_stage", "coulomb_energy", "md_step", "md_run", "coulomb_hvp",
-           "md_adjoint_step", "cb_poll_flags", "cb_last_error", "cb_autotune", "cb_load_tuning", "cb_get_config",
-           "cb_set_config")
+EXPORTS = ("cb_workspace_size", "coulomb_forces", "coulomb_forces_range", "coulomb_pair_stage", "coulomb_energy",
+           "coulomb_trap_grad", "cb_trap_k", "md_step", "md_run", "coulomb_hvp", "md_adjoint_step", "cb_poll_flags",
+           "cb_last_error", "cb_autotune", "cb_load_tuning", "cb_get_config", "cb_set_config")
 
 
 class CoulombError(RuntimeError):
@@ -78,6 +78,9 @@ def lib() -> C.CDLL:
                 L.coulomb_forces.argtypes = [i64, _P, _P, _P, _P, d, i32, _P, _P, _P, _P, sz, _P]
                 L.coulomb_forces_range.argtypes = [i64, i64, i64, _P, _P, _P, _P, d, i32, _P, _P, _P, _P, sz, _P]
                 L.coulomb_energy.argtypes = [i64, _P, _P, _P, _P, d, i32, _P, _P, sz, _P]
+                L.coulomb_trap_grad.argtypes = [i64, _P, _P, _P, _P, _P, C.POINTER(Trap), d, d, i32, _P, _P, _P, _P,
+                                                _P, sz, _P]
+                L.cb_trap_k.argtypes = [C.POINTER(Trap), d, C.POINTER(C.c_double)]
                 L.coulomb_pair_stage.argtypes = [i64, _P, _P, _P, _P, d, i32, C.POINTER(C.c_int32), _P, sz, _P]
                 L.md_step.argtypes = [i64, C.POINTER(State), _P, _P, C.POINTER(Trap), d, d, d, i32, _P, sz, _P]
                 L.md_run.argtypes = [i32, C.POINTER(C.c_int64), C.POINTER(State), _P, _P, C.POINTER(Trap), d, d,
@@ -225,6 +228,42 @@ def coulomb_energy(x, y, z, q, eps2: float = 0.0, prec="fp64", out=None):
     _check(lib().coulomb_energy(n, x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(), float(eps2), _prec(prec),
                                 u.data_ptr(), ws.data_ptr(), ws.numel(), _stream()), "coulomb_energy")
     return u
+
+
+def trap_k(trap: dict | None, t: float = 0.0):
+    """The trap's spring constants per unit mass (kx, ky, kz) at time t, from
+    the library (cb_trap_k); (0, 0, 0) for no trap."""
+    if trap is None:
+        return (0.0, 0.0, 0.0)
+    tr = make_trap(trap)
+    k = (C.c_double * 3)()
+    _check(lib().cb_trap_k(C.byref(tr), float(t), k), "cb_trap_k")
+    return (k[0], k[1], k[2])
+
+
+def coulomb_trap_grad(x, y, z, q, m=None, trap: dict | None = None, t: float = 0.0, eps2: float = 0.0,
+                      prec="fp64", grad: bool = True, energy: bool = False, out=None):
+    """Gradient g = dU/dr = -F + m k(t) r (a (3, n) tensor) and/or the energy
+    U = U_C + U_trap(t) (a one-element tensor) of the Coulomb + trap
+    potential; m = None gives the Coulomb part alone.  Returns (g or None,
+    U or None).  out: an optional contiguous (3, n) float64 tensor for g."""
+    dev = _dev_f64(x, y, z, q, m)
+    n = x.numel()
+    g = None
+    if grad:
+        g = out if out is not None else torch.empty((3, n), dtype=torch.float64, device=dev)
+        _dev_f64(g)
+        if tuple(g.shape) != (3, n):
+            raise ValueError("out must have shape (3, n)")
+    u = torch.empty(1, dtype=torch.float64, device=dev) if energy else None
+    tr = make_trap(trap)
+    ws = _workspace("grad", n, prec=prec, device=dev)
+    gp = [g[c].data_ptr() for c in range(3)] if g is not None else [None, None, None]
+    _check(lib().coulomb_trap_grad(n, x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(),
+                                   m.data_ptr() if m is not None else None, C.byref(tr), float(t), float(eps2),
+                                   _prec(prec), *gp, u.data_ptr() if u is not None else None, ws.data_ptr(),
+                                   ws.numel(), _stream()), "coulomb_trap_grad")
+    return g, u
 
 
 def _state(st) -> State:

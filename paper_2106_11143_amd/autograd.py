@@ -10,33 +10,12 @@ include/coulomb.h); with m = None only the Coulomb part is used.
 """
 from __future__ import annotations
 
-import math
-
 import torch
 
 from . import api
 
-
-def trap_k(trap: dict | None, t: float = 0.0):
-    """Trap spring constants per unit mass (kx, ky, kz) at time t."""
-    if trap is None:
-        return (0.0, 0.0, 0.0)
-    if int(trap.get("kind", 0)) == 1:
-        w2 = trap["rf_omega"] ** 2
-        kx = trap.get("rf_a", 0.0) * w2 / 4.0 + trap["rf_q"] * w2 / 2.0 * math.cos(
-            trap["rf_omega"] * t + trap.get("rf_phase", 0.0))
-        return (kx, -kx, trap["wz"] ** 2)
-    wx, wy = trap["wx"], trap["wy"]
-    t0, t1 = trap.get("t_ramp0", 0.0), trap.get("t_ramp1", 0.0)
-    if t1 > t0:
-        s = min(max((t - t0) / (t1 - t0), 0.0), 1.0)
-        wx = wx + s * (trap["wx1"] - wx)
-        wy = wy + s * (trap["wy1"] - wy)
-    return (wx * wx, wy * wy, trap["wz"] ** 2)
-
-
-def _k_tensor(trap, t, like):
-    return torch.tensor(trap_k(trap, t), dtype=like.dtype, device=like.device).reshape(3, 1)
+# the trap's spring constants per unit mass (kx, ky, kz) at time t, from the library
+trap_k = api.trap_k
 
 
 class CoulombTrapGrad(torch.autograd.Function):
@@ -44,10 +23,8 @@ class CoulombTrapGrad(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, r, q, m, trap, t, eps2, prec):
-        fx, fy, fz = api.coulomb_forces(r[0].contiguous(), r[1].contiguous(), r[2].contiguous(), q, eps2, prec)
-        G = -torch.stack([fx, fy, fz])
-        if m is not None:
-            G = G + m.reshape(1, -1) * _k_tensor(trap, t, r) * r
+        G, _ = api.coulomb_trap_grad(r[0].contiguous(), r[1].contiguous(), r[2].contiguous(), q, m, trap, t, eps2,
+                                     prec)
         ctx.save_for_backward(r, q, m if m is not None else torch.empty(0))
         ctx.trap, ctx.t, ctx.eps2, ctx.prec, ctx.has_m = trap, t, eps2, prec, m is not None
         return G
@@ -66,9 +43,9 @@ class CoulombTrapEnergy(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, r, q, m, trap, t, eps2, prec):
-        u = api.coulomb_energy(r[0].contiguous(), r[1].contiguous(), r[2].contiguous(), q, eps2, prec)[0]
-        if m is not None:
-            u = u + 0.5 * (m.reshape(1, -1) * _k_tensor(trap, t, r) * r * r).sum()
+        _, u = api.coulomb_trap_grad(r[0].contiguous(), r[1].contiguous(), r[2].contiguous(), q, m, trap, t, eps2,
+                                     prec, grad=False, energy=True)
+        u = u[0]
         ctx.save_for_backward(r, q, m if m is not None else torch.empty(0))
         ctx.args = (trap, t, eps2, prec, m is not None)
         return u

@@ -14,6 +14,7 @@
 
 #include "coulomb.h"
 #include "internal.hpp"
+#include "step_common.hpp"
 
 __device__ unsigned int g_cb_flags;
 
@@ -186,6 +187,7 @@ WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec) {
     const size_t N = (size_t)n;
     const size_t nv = (size_t)std::max(1, (int)nvec);
     size_t off = 0;
+    if (op == CB_OP_GRAD) op = CB_OP_MD_STEP;  // the same buffers: force stage, potential partials, energy blocks
     const bool batched = (op == CB_OP_MD_RUN && nrun > 1);
     const bool hv = (op == CB_OP_HVP || op == CB_OP_ADJOINT);
     if (!batched) {
@@ -253,7 +255,7 @@ extern "C" {
 const char* cb_last_error(void) { return t_err.c_str(); }
 
 size_t cb_workspace_size(int32_t op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec) {
-    if (n < 1 || op < 0 || op > CB_OP_ADJOINT || prec < 0 || prec > CB_MIXED_F32D) return 0;
+    if (n < 1 || op < 0 || op == CB_OP_MD_ENSEMBLE || op > CB_OP_GRAD || prec < 0 || prec > CB_MIXED_F32D) return 0;
     if (op == CB_OP_HVP && (nvec < 1 || nvec > kMaxVec)) return 0;
     return ws_layout(op, n, nrun, nvec).total;
 }
@@ -281,6 +283,18 @@ cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t algo, int32
         return fail(CB_EINVAL, "cb_set_config: unsupported configuration algo=%d p=%d wg=%d splits=%d", algo, p, wg,
                     splits);
     put_cfg(op, n, prec, c);
+    return ok();
+}
+
+cb_status cb_trap_k(const cb_trap* trap, double t, double k_out[3]) {
+    cb_status st;
+    if (!k_out) return fail(CB_EINVAL, "cb_trap_k: k_out is NULL");
+    if (!trap_ok(trap, "cb_trap_k", &st)) return st;
+    if (!std::isfinite(t)) return fail(CB_EINVAL, "cb_trap_k: t must be finite");
+    const TrapK k = trap_k(*trap, t);
+    k_out[0] = k.kx;
+    k_out[1] = k.ky;
+    k_out[2] = k.kz;
     return ok();
 }
 

@@ -174,7 +174,7 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
         if ((rc = epilogue(rec ? energies + 4 * (k / every) : nullptr))) return rc;
     }
     if (pend) {
-        k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, pend, pend_out, 0);
+        k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, pend, pend_out, REC_ALL);
         if ((rc = check_launch("k_energy_final"))) return rc;
     }
     return ok();
@@ -335,8 +335,74 @@ cb_status coulomb_energy(int64_t n, const double* x, const double* y, const doub
     const int nb = (int)((n + kEpiThreads - 1) / kEpiThreads);
     k_epilogue<<<nb, kEpiThreads, 0, st>>>(E);
     if ((rc = check_launch("k_epilogue"))) return rc;
-    k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, eblk, u_out, 1);
+    k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, eblk, u_out, REC_UC);
     if ((rc = check_launch("k_energy_final"))) return rc;
+    return ok();
+}
+
+cb_status coulomb_trap_grad(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                            const double* m, const cb_trap* trap, double t, double eps2, int32_t prec, double* gx,
+                            double* gy, double* gz, double* u_out, void* ws, size_t ws_bytes, void* stream) {
+    const WsLayout L = ws_layout(CB_OP_GRAD, n > 0 ? n : 1, 1, 1);
+    cb_status rc = check_common("coulomb_trap_grad", n, prec, eps2, ws, ws_bytes, L.total);
+    if (rc) return rc;
+    if (prec == CB_MIXED_F32D) return fail(CB_EUNSUPPORTED, "coulomb_trap_grad: CB_MIXED_F32D is for the forces only");
+    if (!x || !y || !z || !q) return fail(CB_EINVAL, "coulomb_trap_grad: NULL input array");
+    const bool want_g = gx || gy || gz;
+    if (want_g && !(gx && gy && gz)) return fail(CB_EINVAL, "coulomb_trap_grad: gx, gy, gz must all be set or all NULL");
+    if (!want_g && !u_out) return fail(CB_EINVAL, "coulomb_trap_grad: nothing to compute (no gradient, no energy)");
+    if (m && !trap_ok(trap, "coulomb_trap_grad", &rc)) return rc;
+    if (!std::isfinite(t)) return fail(CB_EINVAL, "coulomb_trap_grad: t must be finite");
+    const void* in[5] = {x, y, z, q, m};
+    double* outs[3] = {gx, gy, gz};
+    for (auto o : outs)
+        for (auto i : in)
+            if (overlaps(o, i, n)) return fail(CB_EINVAL, "coulomb_trap_grad: output aliases an input");
+    if (want_g && (overlaps(gx, gy, n) || overlaps(gx, gz, n) || overlaps(gy, gz, n)))
+        return fail(CB_EINVAL, "coulomb_trap_grad: outputs overlap");
+    for (auto o : outs)
+        if (u_out && overlaps2(o, n, u_out, 1)) return fail(CB_EINVAL, "coulomb_trap_grad: u_out aliases an output");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    EpiParams E{};
+    E.n = (int)n;
+    E.q = q;
+    E.m = m;
+    E.x = const_cast<double*>(x);  // read only in these modes
+    E.y = const_cast<double*>(y);
+    E.z = const_cast<double*>(z);
+    if (m) E.trap = *trap;
+    E.t0 = t;
+    E.fx = gx;
+    E.fy = gy;
+    E.fz = gz;
+    E.eblk = at(ws, L.eblk);
+    E.flags = flags_ptr();
+    if (!E.flags) return fail(CB_EHIP, "coulomb_trap_grad: device flag symbol not found");
+    E.mode = (want_g ? EPI_GRAD : 0u) | (u_out ? (EPI_ENERGY | EPI_UPOT) : 0u);
+    if (u_out) {
+        // the potential needs the direct kernel (forces and potentials in one pass)
+        const PairRun pr = plan(CB_OP_ENERGY, n, prec);
+        E.S = pr.S;
+        E.part = at(ws, L.part);
+        E.ppot = at(ws, L.ppot);
+        if ((rc = launch_pair(prec, pr.cfg, want_g, true, (int)n, x, y, z, q, eps2, pr.jlen,
+                              want_g ? at(ws, L.part) : nullptr, at(ws, L.ppot), st)))
+            return rc;
+    } else {
+        int S = 0;
+        bool prescaled = false;
+        if ((rc = force_stage(CB_OP_FORCES, prec, n, x, y, z, q, eps2, ws, L, st, &S, &prescaled))) return rc;
+        E.S = S;
+        E.part = at(ws, L.part);
+        if (prescaled) E.mode |= EPI_PRESCALED;
+    }
+    const int nb = (int)((n + kEpiThreads - 1) / kEpiThreads);
+    k_epilogue<<<nb, kEpiThreads, 0, st>>>(E);
+    if ((rc = check_launch("k_epilogue"))) return rc;
+    if (u_out) {
+        k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, E.eblk, u_out, REC_UPOT);
+        if ((rc = check_launch("k_energy_final"))) return rc;
+    }
     return ok();
 }
 

@@ -166,29 +166,6 @@ __global__ void __launch_bounds__(kEpiThreads) k_adj_final(int nb, const double*
     }
 }
 
-static TrapK host_trap_k(const cb_trap& tr, double t) {
-    TrapK k;
-    if (tr.kind == 1) {
-        const double w2 = tr.rf_omega * tr.rf_omega;
-        const double kx = tr.rf_a * w2 * 0.25 + tr.rf_q * w2 * 0.5 * std::cos(tr.rf_omega * t + tr.rf_phase);
-        k.kx = kx;
-        k.ky = -kx;
-        k.kz = tr.wz * tr.wz;
-        return k;
-    }
-    double wx = tr.wx, wy = tr.wy;
-    if (tr.t_ramp1 > tr.t_ramp0) {
-        double s = (t - tr.t_ramp0) / (tr.t_ramp1 - tr.t_ramp0);
-        s = std::min(std::max(s, 0.0), 1.0);
-        wx = tr.wx + s * (tr.wx1 - tr.wx);
-        wy = tr.wy + s * (tr.wy1 - tr.wy);
-    }
-    k.kx = wx * wx;
-    k.ky = wy * wy;
-    k.kz = tr.wz * tr.wz;
-    return k;
-}
-
 static bool overl(const void* a, const void* b, size_t bytes_a, size_t bytes_b) {
     if (!a || !b) return false;
     const char* pa = static_cast<const char*>(a);
@@ -237,7 +214,7 @@ cb_status coulomb_hvp(int64_t n, const double* x, const double* y, const double*
     const LaunchCfg cfg = get_cfg(CB_OP_HVP, n, prec);
     const int jlen = split_len(n, cfg.splits);
     const int S = n_splits(n, jlen);
-    const TrapK k = m ? host_trap_k(*trap, t) : TrapK{0.0, 0.0, 0.0};
+    const TrapK k = m ? trap_k(*trap, t) : TrapK{0.0, 0.0, 0.0};
     double* part = at(ws, L.part);
     // vectors in passes of 4, 2, 1 (eight per pass need too many registers)
     for (int b0 = 0; b0 < nvec;) {
@@ -275,7 +252,7 @@ cb_status md_adjoint_step(int64_t n, const double* x, const double* y, const dou
     if (!fl) return fail(CB_EHIP, "md_adjoint_step: device flag symbol not found");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int nb = (int)((n + kEpiThreads - 1) / kEpiThreads);
-    const TrapK k = host_trap_k(*trap, 0.0);
+    const TrapK k = trap_k(*trap, 0.0);
     double* part = at(ws, L.part);
     double* eblk = at(ws, L.eblk);
     double* u = at(ws, L.aux);

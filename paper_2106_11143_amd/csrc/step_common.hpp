@@ -22,16 +22,24 @@ enum : unsigned {
     EPI_KICK = 4u,     // a_new = F/m + trap; v += dt/2 (a + a_new); a <- a_new
     EPI_DRIFT = 8u,    // r += v dt + a dt^2/2 (after any kick)
     EPI_ENERGY = 16u,  // per-block sums of K, U_C, U_trap of the resulting state
-    EPI_UC_ONLY = 32u,   // energy: only U_C (no m, v, trap)
-    EPI_PRESCALED = 64u  // part holds finished forces [3][n] (S = 1), not sums to scale by k_C q_i
+    EPI_UC_ONLY = 32u,    // energy: only U_C (no m, v, trap)
+    EPI_PRESCALED = 64u,  // part holds finished forces [3][n] (S = 1), not sums to scale by k_C q_i
+    EPI_GRAD = 128u,      // write g = -F + m k(t0) r (m NULL: -F) to fx, fy, fz
+    EPI_UPOT = 256u       // energy: U_C and U_trap(t0) only (no velocities; U_trap = 0 when m is NULL)
 };
+
+// What sum_record writes: the whole record, U_C alone, or U_C + U_trap alone.
+enum : int { REC_ALL = 0, REC_UC = 1, REC_UPOT = 2 };
 
 struct TrapK {
     double kx, ky, kz;
 };
 
-// Spring constants per unit mass of the trap at time t (see cb_trap).
-__device__ __forceinline__ TrapK trap_k(const cb_trap& tr, double t) {
+// Spring constants per unit mass of the trap at time t (see cb_trap): the
+// pseudo-potential's (wx^2, wy^2, wz^2), linearly ramped in (wx, wy); or the
+// RF drive of eq. (1) in Mathieu form.  Host and device use this one
+// function (cb_trap_k exports the host side).
+__host__ __device__ __forceinline__ TrapK trap_k(const cb_trap& tr, double t) {
     TrapK k;
     if (tr.kind == 1) {
         const double w2 = tr.rf_omega * tr.rf_omega;

@@ -71,11 +71,12 @@ __device__ __forceinline__ void block_sum3_waves(double& a, double& b, double& c
     __syncthreads();  // sh may be reused by a later call
 }
 
-// Sums nb block partials [nb][3] in a fixed order into out: with uc_only,
-// out[0] = U_C; otherwise out[0..3] = K, U_C, U_trap, K + U_C + U_trap.
-// Called by every thread of one block.
+// Sums nb block partials [nb][3] in a fixed order into out: with what =
+// REC_UC, out[0] = U_C; with REC_UPOT, out[0] = U_C + U_trap; with REC_ALL,
+// out[0..3] = K, U_C, U_trap, K + U_C + U_trap.  Called by every thread of
+// one block.
 __device__ __forceinline__ void sum_record(int nb, const double* __restrict__ eblk, double* __restrict__ out,
-                                           int uc_only) {
+                                           int what) {
     double a = 0.0, b = 0.0, c = 0.0;
     for (int k = threadIdx.x; k < nb; k += kEpiThreads) {
         a += eblk[k * 3 + 0];
@@ -84,8 +85,10 @@ __device__ __forceinline__ void sum_record(int nb, const double* __restrict__ eb
     }
     block_sum3_waves(a, b, c);
     if (threadIdx.x == 0) {
-        if (uc_only) {
+        if (what == REC_UC) {
             out[0] = b;
+        } else if (what == REC_UPOT) {
+            out[0] = b + c;
         } else {
             out[0] = a;
             out[1] = b;
@@ -99,7 +102,7 @@ __global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 
 __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
     if (P.eprev && blockIdx.x == gridDim.x - 1) {  // the extra block: an earlier record's sum
-        sum_record(P.nprev, P.eprev, P.eprev_out, 0);
+        sum_record(P.nprev, P.eprev, P.eprev_out, REC_ALL);
         return;
     }
     const int i = blockIdx.x * kEpiThreads + threadIdx.x;
@@ -108,12 +111,13 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
     if (i < P.n) {
         const int n = P.n;
         double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
-        const bool need_f = (mode & (EPI_FORCES | EPI_ACCEL | EPI_KICK)) != 0;
+        const bool need_f = (mode & (EPI_FORCES | EPI_ACCEL | EPI_KICK | EPI_GRAD)) != 0;
         const bool need_p = (mode & EPI_ENERGY) && P.ppot != nullptr;
         const size_t n3 = 3 * (size_t)n;
         // the ion's state, requested before the partials so that both
         // round trips overlap (only this thread touches ion i)
-        const bool need_s = (mode & (EPI_ACCEL | EPI_KICK | EPI_DRIFT | EPI_ENERGY)) && !(mode & EPI_UC_ONLY);
+        const bool need_s =
+            (mode & (EPI_ACCEL | EPI_KICK | EPI_DRIFT | EPI_ENERGY)) && !(mode & (EPI_UC_ONLY | EPI_UPOT | EPI_GRAD));
         double x = 0.0, y = 0.0, z = 0.0, vx = 0.0, vy = 0.0, vz = 0.0, ax = 0.0, ay = 0.0, az = 0.0, mi = 1.0;
         if (need_s) {
             x = P.x[i];
@@ -158,7 +162,33 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
             P.fz[i] = Fz;
             ok = finite3(Fx, Fy, Fz);
         }
-        if (mode & EPI_UC_ONLY) {
+        if (mode & (EPI_GRAD | EPI_UPOT)) {
+            // gradient of U_C + U_trap(t0) and/or those two energies: the
+            // trap enters only through m (none when m is NULL)
+            double xi = 0.0, yi = 0.0, zi = 0.0, mi = 0.0;
+            TrapK k{0.0, 0.0, 0.0};
+            if (P.m) {
+                xi = P.x[i];
+                yi = P.y[i];
+                zi = P.z[i];
+                mi = P.m[i];
+                k = trap_k(P.trap, P.t0);
+            }
+            if (mode & EPI_GRAD) {
+                const double gx = __builtin_fma(mi * k.kx, xi, -Fx);
+                const double gy = __builtin_fma(mi * k.ky, yi, -Fy);
+                const double gz = __builtin_fma(mi * k.kz, zi, -Fz);
+                P.fx[i] = gx;
+                P.fy[i] = gy;
+                P.fz[i] = gz;
+                ok = finite3(gx, gy, gz);
+            }
+            if (mode & EPI_ENERGY) {
+                eC = 0.5 * c * sp;
+                eT = 0.5 * mi * (k.kx * xi * xi + k.ky * yi * yi + k.kz * zi * zi);
+                ok = ok && __builtin_isfinite(eC) && __builtin_isfinite(eT);
+            }
+        } else if (mode & EPI_UC_ONLY) {
             eC = 0.5 * c * sp;
             ok = ok && __builtin_isfinite(eC);
         } else if (mode & (EPI_ACCEL | EPI_KICK | EPI_DRIFT | EPI_ENERGY)) {
@@ -259,8 +289,8 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
 
 // One block: sum_record of nb block partials.
 __global__ void __launch_bounds__(kEpiThreads) k_energy_final(int nb, const double* __restrict__ eblk,
-                                                             double* __restrict__ out, int uc_only) {
-    sum_record(nb, eblk, out, uc_only);
+                                                             double* __restrict__ out, int what) {
+    sum_record(nb, eblk, out, what);
 }
 
 }  // namespace cb

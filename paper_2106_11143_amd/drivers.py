@@ -21,7 +21,6 @@ import numpy as np
 import torch
 
 from . import api
-from .autograd import trap_k
 
 
 def _rows(r):
@@ -29,14 +28,13 @@ def _rows(r):
 
 
 def total_force(r, q, m, trap, t=0.0, eps2=0.0, prec="fp64"):
-    """Coulomb + trap force (3, n)."""
-    F = torch.stack(api.coulomb_forces(*_rows(r), q, eps2, prec))
-    k = torch.tensor(trap_k(trap, t), dtype=r.dtype, device=r.device).reshape(3, 1)
-    return F - m.reshape(1, -1) * k * r
+    """Coulomb + trap force (3, n): minus the gradient the library computes."""
+    g, _ = api.coulomb_trap_grad(*_rows(r), q, m, trap, t, eps2, prec)
+    return g.neg_()
 
 
 def _force_scale(m, trap):
-    k = trap_k(trap, 0.0)
+    k = api.trap_k(trap, 0.0)
     wmax = math.sqrt(max(k))
     e2kc = 2.307077552e-28  # k_C e^2 (J m), only for the stopping scale
     a = (3.0 * e2kc / (float(m.mean()) * wmax * wmax)) ** (1.0 / 3.0)
@@ -61,7 +59,7 @@ def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, max_iter=100000, method="l
     g = -total_force(r, q, m, trap, 0.0, eps2)
     it = 0
     if method == "damped":
-        k = trap_k(trap, 0.0)
+        k = api.trap_k(trap, 0.0)
         wmin = math.sqrt(min(k))
         damped = dict(trap, gamma=2.0 * wmin * float(m.mean()))
         dt = 0.05 / wmax
@@ -98,9 +96,7 @@ def minimise(r, q, m, trap, eps2=0.0, ftol_rel=1e-10, max_iter=100000, method="l
             r = r + dt * v
             g = -total_force(r, q, m, trap, 0.0, eps2)
     else:
-        k = torch.tensor(trap_k(trap, 0.0), dtype=r.dtype, device=r.device).reshape(3, 1)
-        mk = m.reshape(1, -1) * k  # trap stiffness per ion and axis, kept on the device
-        grad = lambda r: mk * r - torch.stack(api.coulomb_forces(*_rows(r), q, eps2, "fp64"))
+        grad = lambda r: api.coulomb_trap_grad(*_rows(r), q, m, trap, 0.0, eps2, "fp64")[0]
         mem = LbfgsMemory(g.shape, memory, g.device, g.dtype)
         mem.set_gradient(g)
         h0 = 1.0 / (float(m.mean()) * wmax * wmax)

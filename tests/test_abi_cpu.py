@@ -6,6 +6,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -266,3 +267,51 @@ def test_ensemble_config_validation_and_workspace(api):
     for ntot, nrun in ((1_070_000, 512), (8192, 2), (5000, 100)):
         ws = api.workspace_size("md_run", ntot, nrun=nrun)
         assert 400 * ntot <= ws <= 1000 * ntot + (1 << 24), (ntot, nrun, ws)
+
+
+def test_trap_constants_match_oracle(api, oracle):
+    """cb_trap_k (host; the same function the kernels evaluate) against the
+    oracle's trap constants: RF drive with a DC term and a phase, a ramp
+    before, inside and after its ramp, a static trap."""
+    cases = [(dict(kind=1, rf_a=0.02, rf_q=0.3, rf_omega=6.283e7, rf_phase=0.7, wz=6.283e5), t)
+             for t in (0.0, 3.7e-8, 1.01e-6)]
+    ramp = dict(kind=0, wx=9.42e6, wy=9.0e6, wz=9.42e5, wx1=3.77e6, wy1=3.5e6, t_ramp0=1e-6, t_ramp1=21e-6)
+    cases += [(ramp, t) for t in (0.0, 1e-6, 7.3e-6, 21e-6, 1.0)]
+    cases += [(dict(kind=0, wx=6.283e6, wy=5.0e6, wz=1.2566e6), 0.0), (dict(kind=1, rf_q=0.25, rf_omega=4.4e7,
+                                                                            rf_phase=-2.0, wz=1e6), 2.2e-7)]
+    for trap, t in cases:
+        k = np.array(api.trap_k(trap, t))
+        ref = oracle.trap_k(trap, t)
+        assert np.all(np.abs(k - ref) <= 4 * 2.0 ** -53 * np.abs(ref)), (trap, t, k, ref)
+    with pytest.raises(api.CoulombError):
+        api.trap_k(dict(kind=2), 0.0)
+    with pytest.raises(api.CoulombError):
+        api.trap_k(dict(kind=0, wx=float("nan")), 0.0)
+
+
+def test_trap_grad_argument_errors(api):
+    L = api.lib()
+    big = 1 << 40
+    P = C.c_void_p(1 << 21)
+    x, y, z, q, m = (C.c_void_p((k + 1) << 24) for k in range(5))
+    g1, g2, g3, u = (C.c_void_p((k + 8) << 24) for k in range(4))
+    tr = api.make_trap(dict(kind=0, wx=1e6, wy=1e6, wz=1e5))
+    call = lambda *a: L.coulomb_trap_grad(*a)
+    assert L.cb_workspace_size(7, 1000, 1, 1, 0) >= L.cb_workspace_size(1, 1000, 1, 1, 0)
+    assert call(0, x, y, z, q, m, C.byref(tr), 0.0, 0.0, 0, g1, g2, g3, u, _ws(), big, None) == api.CB_EINVAL
+    assert call(10, None, y, z, q, m, C.byref(tr), 0.0, 0.0, 0, g1, g2, g3, u, _ws(), big, None) == api.CB_EINVAL
+    # the gradient's three rows together or not at all, and something to do
+    assert call(10, x, y, z, q, m, C.byref(tr), 0.0, 0.0, 0, g1, None, g3, u, _ws(), big, None) == api.CB_EINVAL
+    assert call(10, x, y, z, q, m, C.byref(tr), 0.0, 0.0, 0, None, None, None, None, _ws(), big, None) == api.CB_EINVAL
+    assert "nothing" in api.last_error()
+    # with m the trap is checked; without it the trap is ignored
+    bad = api.make_trap(dict(kind=5))
+    assert call(10, x, y, z, q, m, C.byref(bad), 0.0, 0.0, 0, g1, g2, g3, u, _ws(), big, None) == api.CB_EINVAL
+    assert call(10, x, y, z, q, m, None, 0.0, 0.0, 0, g1, g2, g3, u, _ws(), big, None) == api.CB_EINVAL
+    assert call(10, x, y, z, q, m, C.byref(tr), float("inf"), 0.0, 0, g1, g2, g3, u, _ws(), big, None) == api.CB_EINVAL
+    # aliasing, precision, workspace
+    assert call(10, x, y, z, q, m, C.byref(tr), 0.0, 0.0, 0, x, g2, g3, u, _ws(), big, None) == api.CB_EINVAL
+    assert call(10, x, y, z, q, m, C.byref(tr), 0.0, 0.0, 0, g1, g2, g3, C.c_void_p((8 << 24) + 16), _ws(), big,
+                None) == api.CB_EINVAL
+    assert call(10, x, y, z, q, m, C.byref(tr), 0.0, 0.0, 4, g1, g2, g3, u, _ws(), big, None) == api.CB_EUNSUPPORTED
+    assert call(10, x, y, z, q, m, C.byref(tr), 0.0, 0.0, 0, g1, g2, g3, u, _ws(), 100, None) == api.CB_ENOWS
