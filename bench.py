@@ -2,15 +2,19 @@
 
 One step = one md step of the whole hot path on the N = 100000 workload
 (cloud100k: Gaussian cloud, 1% of ions at +2e, static pseudo-potential trap,
-dt = 1 ns): the all-pairs force kernel (j-split partial sums), then the fixed
-order sum over splits fused with the trap, the velocity-Verlet kick and the
-next drift.  ``value`` is pair interactions per second, N^2 per step.
+dt = 1 ns): the force stage (by default each unordered pair once, applied to
+both ions), then the fixed-order finish fused with the trap, the
+velocity-Verlet kick and the next drift.  ``value`` is pair interactions per
+second, N^2 per step (the paper's loop count).
 
-Prints one JSON line with the contract fields plus ``roofline`` (the
-all-pairs kernel against the FP64 vector peak, 20 FLOPs per pair),
-``cpu_baseline`` (the oracle's plain double loop timed on this host on a
-bounded sample) and ``mixed`` (the FP32-seeded one-Newton-step path: speed and
-its force error).
+Prints one JSON line with the contract fields plus ``roofline`` (the force
+stage against the FP64 vector peak at the method's own FLOP count: 27 per
+unordered pair on the default Newton's-third-law stage, 20 per ordered pair on
+the direct kernel), ``cpu_baseline`` (the oracle's plain double loop timed on
+this host on a bounded sample), ``mixed`` (the FP32-seeded one-Newton-step
+path: speed and its force error), ``mixed_f32d_ablation`` (FP32 displacements:
+speed and error) and ``after_200_steps`` (the workload's 200-step run and the
+force errors at its final positions).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu]
 """
@@ -26,7 +30,35 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOPS_PER_PAIR = 20  # the paper's double loop with +,-,*,/,sqrt counted once each
+# Algorithmic FLOPs, counted on the paper's section 3 double loop with each +, -, *, /, sqrt
+# counted once and the softening add included:
+#  - 20 per ordered pair evaluated on its own (3 sub, r^2 + eps2 in 6, sqrt, divide, cube in 2,
+#    times q_j, 3 mul + 3 add into the sums);
+#  - 27 per unordered pair evaluated once for both ions by Newton's third law (the 20, plus the
+#    other ion's charge multiply and its 3 mul + 3 add).
+# A force evaluation of N ions is 20 N (N - 1) FLOPs on the direct kernel and 27 N (N - 1) / 2
+# on the Newton's-third-law stage: the work the kernel performs, not a dense-equivalent count.
+FLOPS_PER_PAIR = 20
+FLOPS_PER_SYM_PAIR = 27
+SYM_ALGOS = (1, 2)
+
+
+# Hessian-vector products, counted the same way, per ordered pair and B vectors: geometry and
+# scales 16 (d 3, r^2 + eps2 6, sqrt and divide 2, y^3 2, times q_j 1, 3 y^5 from y^3 and y^2 2),
+# and per vector 21 (u = v_i - v_j 3, d.u 5, its scale 1, 3 d c - u y^3 components 9,
+# accumulation 3).  Per unordered pair applied to both ions: 15 + 30 B (no q_j multiply in the
+# shared scales; per vector the 21 minus the one accumulation, plus 3 mul + 3 add into each ion).
+def hvp_eval_flops(n: int, nvec: int, sym: bool) -> float:
+    if sym:
+        return (15 + 30 * nvec) * n * (n - 1) / 2.0
+    return (16 + 21 * nvec) * float(n) * (n - 1)
+
+
+def force_eval_flops(n: int, algo: int) -> float:
+    """Algorithmic FLOPs of one force evaluation of n ions on the given path."""
+    if algo in SYM_ALGOS:
+        return FLOPS_PER_SYM_PAIR * n * (n - 1) / 2.0
+    return FLOPS_PER_PAIR * float(n) * (n - 1)
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
@@ -168,7 +200,8 @@ def main():
     pairs_step = float(n) * float(n)
     ms_per_step = ms_fp64 / args.steps
     value = pairs_step * args.steps / (ms_fp64 * 1e-3)
-    achieved = FLOPS_PER_PAIR * pairs_step / (kt64 * 1e-3) / 1e12
+    flops_eval = force_eval_flops(n, cfg["algo"])
+    achieved = flops_eval / (kt64 * 1e-3) / 1e12
     counters = stage_counters()
     traffic = counters.get("bytes_per_launch") if counters else None
     executed = counters.get("executed_fp64_flops_per_launch") if counters else None
@@ -195,6 +228,39 @@ def main():
     Fmx = torch.stack(api.coulomb_forces(x, y, z, q, prec="mixed")).cpu().numpy()
     emx = np.linalg.norm(Fmx - F64, axis=0) / np.linalg.norm(F64, axis=0)
 
+    # the literal FP32-displacement reading of the mixed path (ablation, direct kernel): time and error
+    api.coulomb_forces(x, y, z, q, prec="mixed_f32d")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        Ff = api.coulomb_forces(x, y, z, q, prec="mixed_f32d")
+    e1.record()
+    torch.cuda.synchronize()
+    ms_f32d = e0.elapsed_time(e1) / 3
+    Ff = torch.stack(Ff).cpu().numpy()
+    ef = np.linalg.norm(Ff - F64, axis=0) / np.linalg.norm(F64, axis=0)
+
+    # the workload's 200-step run (FP64 and mixed), then the forces at the final
+    # FP64 positions on both paths: the mixed path's force error after the run
+    nlong = d["nsteps"]
+    st_long = {}
+    for prec in ("fp64", "mixed"):
+        st = fresh_state()
+        api.md_run(st, q, m, trap, 0.0, dt, nlong, prec=prec, init_accel=True)
+        st_long[prec] = st
+    xl, yl, zl = st_long["fp64"][:3]
+    F64l = torch.stack(api.coulomb_forces(xl, yl, zl, q, prec="fp64")).cpu().numpy()
+    Fmxl = torch.stack(api.coulomb_forces(xl, yl, zl, q, prec="mixed")).cpu().numpy()
+    emxl = np.linalg.norm(Fmxl - F64l, axis=0) / np.linalg.norm(F64l, axis=0)
+    r64 = torch.stack(st_long["fp64"][:3]).cpu().numpy()
+    rmx = torch.stack(st_long["mixed"][:3]).cpu().numpy()
+    after = {"steps": nlong, "positions": "final positions of the FP64 run",
+             "mixed_vs_fp64": {"max_rel": float(emxl.max()), "rms_rel": float(np.sqrt(np.mean(emxl ** 2))),
+                               "ions": n},
+             "mixed_vs_fp64_trajectory_max_abs_m": float(np.abs(rmx - r64).max()),
+             "position_scale_m": float(np.abs(r64).max())}
+
     out = {
         "metric": "pair interactions/s (FP64, N=100000, one velocity-Verlet step per step)",
         "value": value,
@@ -211,7 +277,9 @@ def main():
         "config": {
             "workload": f"cloud100k: N={n} ions, Gaussian sigma=(150,150,800) um, 1% at +2e, static trap "
                         "2pi(1,1,0.2) MHz, dt=1 ns, FP64 all-pairs Coulomb + velocity-Verlet",
-            "n": n, "launch": cfg, "flops_per_pair": FLOPS_PER_PAIR,
+            "n": n, "launch": cfg,
+            "flops_per_unordered_pair": FLOPS_PER_SYM_PAIR if cfg["algo"] in SYM_ALGOS else None,
+            "flops_per_ordered_pair": FLOPS_PER_PAIR if cfg["algo"] not in SYM_ALGOS else None,
         },
         "roofline": {
             "bound": "alu",
@@ -223,9 +291,13 @@ def main():
             "frac_fp32_peak": achieved / PEAK_FP32_TFLOPS,
             "traffic": traffic,
             "kernel_ms": kt64,
-            "algorithmic_flops_per_launch": FLOPS_PER_PAIR * pairs_step,
-            "flop_convention": "algorithmic: 20 FLOP per ordered pair, N^2 ordered pairs per force evaluation; "
-                               "the Newton's-third-law stage evaluates each unordered pair once",
+            "algorithmic_flops_per_launch": flops_eval,
+            "flop_convention": ("the method's own work: 27 FLOP per unordered pair x N(N-1)/2 pairs (each pair "
+                                "evaluated once and applied to both ions)" if cfg["algo"] in SYM_ALGOS else
+                                "the method's own work: 20 FLOP per ordered pair x N(N-1) pairs"),
+            "dense_equivalent_tflops": FLOPS_PER_PAIR * pairs_step / (kt64 * 1e-3) / 1e12,
+            "dense_equivalent_note": "20 FLOP x N^2 ordered pairs per evaluation whatever the kernel does; "
+                                     "a throughput figure, not a fraction of peak",
             "executed_fp64_tflops": executed / (kt64 * 1e-3) / 1e12 if executed else None,
         },
         "one_gpu_share_of_8": share,
@@ -233,19 +305,30 @@ def main():
             "pairs_per_s": pairs_step * args.steps / (ms_mixed * 1e-3),
             "ms_per_step": ms_mixed / args.steps,
             "kernel_ms": kt_mixed,
-            "kernel_tflops": FLOPS_PER_PAIR * pairs_step / (kt_mixed * 1e-3) / 1e12,
+            "kernel_tflops": flops_eval / (kt_mixed * 1e-3) / 1e12,
             "speedup_vs_fp64_step": ms_fp64 / ms_mixed,
             "speedup_vs_fp64_kernel": kt64 / kt_mixed,
             "max_rel_force_err_vs_fp64": float(emx.max()),
             "rms_rel_force_err_vs_fp64": float(np.sqrt(np.mean(emx ** 2))),
         },
+        "mixed_f32d_ablation": {
+            "what": "mixed refinement on displacements rounded to FP32 (in r^2 and in the numerator); "
+                    "direct kernel, forces only",
+            "kernel_ms": ms_f32d, "speedup_vs_fp64_kernel": kt64 / ms_f32d,
+            "max_rel_force_err_vs_fp64": float(ef.max()),
+            "rms_rel_force_err_vs_fp64": float(np.sqrt(np.mean(ef ** 2))),
+        },
+        "after_200_steps": after,
     }
     if not args.no_cpu:
-        out["cpu_baseline"], out["oracle_error"] = cpu_leg(d, F64, Fmx, args.cpu_seconds)
+        out["cpu_baseline"], out["oracle_error"] = cpu_leg(d, F64, Fmx, args.cpu_seconds, Ff)
+        # the force error after the 200-step run, against the oracle at the same positions
+        _, err_l = cpu_leg(dict(d, x=r64[0], y=r64[1], z=r64[2]), F64l, Fmxl, 0.0, None, time_it=False)
+        after["oracle_error"] = err_l
     print(json.dumps(out), flush=True)
 
 
-def cpu_leg(d, F64, Fmx, seconds):
+def cpu_leg(d, F64, Fmx, seconds, Ff32d=None, time_it=True):
     """The oracle on this host: its plain double loop timed on a bounded sample
     of rows (all j for ions 0..k-1), and the GPU force errors against its
     compensated forces on a sample of ions."""
@@ -255,6 +338,23 @@ def cpu_leg(d, F64, Fmx, seconds):
 
     n = d["n"]
     args = (d["x"], d["y"], d["z"], d["q"])
+    base = None
+    if time_it:
+        base = _time_plain(O, n, args, seconds)
+    g = np.random.Generator(np.random.PCG64(5))
+    idx = np.sort(g.choice(n, min(n, 1000), replace=False))
+    ref = np.stack(O.forces(*args, idx=idx))
+    err = {}
+    for name, F in (("fp64", F64), ("mixed", Fmx), ("mixed_f32d", Ff32d)):
+        if F is None:
+            continue
+        e = np.linalg.norm(F[:, idx] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        err[name] = {"max_rel": float(e.max()), "rms_rel": float(np.sqrt(np.mean(e ** 2))), "ions": len(idx)}
+    return base, err
+
+
+def _time_plain(O, n, args, seconds):
+    """The plain double loop timed on a bounded sample of rows."""
     t0 = time.perf_counter()
     k0 = min(n, 2000)
     O.forces_plain_range(*args, 0, k0)
@@ -267,17 +367,9 @@ def cpu_leg(d, F64, Fmx, seconds):
         _, _, _, used = O.forces_plain_range(*args, 0, k)
     t = time.perf_counter() - t0
     pairs = float(reps) * k * (n - 1)
-    base = {"value": pairs / t, "unit": "pairs/s", "cores": int(used), "kind": "oracle",
+    return {"value": pairs / t, "unit": "pairs/s", "cores": int(used), "kind": "oracle",
             "sample": f"plain FP64 double loop (SQRT+DIV), rows 0..{k - 1} x all {n} ions, {reps} pass(es), "
                       f"{t:.1f} s"}
-    g = np.random.Generator(np.random.PCG64(5))
-    idx = np.sort(g.choice(n, min(n, 1000), replace=False))
-    ref = np.stack(O.forces(*args, idx=idx))
-    err = {}
-    for name, F in (("fp64", F64), ("mixed", Fmx)):
-        e = np.linalg.norm(F[:, idx] - ref, axis=0) / np.linalg.norm(ref, axis=0)
-        err[name] = {"max_rel": float(e.max()), "rms_rel": float(np.sqrt(np.mean(e ** 2))), "ions": len(idx)}
-    return base, err
 
 
 # ----------------------------------------------------------------------------
@@ -310,15 +402,19 @@ def _line(metric, value, unit, steps, warmup, ms_per_step, workload, extra, high
     return out
 
 
-def _roof(flops, seconds, what):
+def _roof(flops, seconds, what, convention):
     """Roofline object for a secondary workload: the whole timed region's
-    algorithmic FLOP rate against the FP64 vector peak (a lower bound on the
-    dominant kernel's own rate, since it includes the other kernels and the
-    launch gaps)."""
+    algorithmic FLOP rate (the method's own work, as `convention` states)
+    against the FP64 vector peak; a lower bound on the dominant kernel's own
+    rate, since it includes the other kernels and the launch gaps."""
     achieved = flops / seconds / 1e12
     return {"bound": "alu", "kernel": what, "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-            "flop_convention": "algorithmic, per ordered pair: 20 (force), 38 + 12 per extra vector (HVP)"}
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "flop_convention": convention}
+
+
+def _force_convention(algo):
+    return ("27 FLOP per unordered pair x n(n-1)/2 per force evaluation (Newton's third law)" if algo in SYM_ALGOS
+            else "20 FLOP per ordered pair x n(n-1) per force evaluation")
 
 
 def bench_md_single(args, which):
@@ -347,10 +443,12 @@ def bench_md_single(args, which):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     E = en[0, :, 3].cpu().numpy()
+    cfg = api.get_config("md_run", n, "fp64")
     extra = {"energy_rel_range": float((E.max() - E.min()) / abs(E[0])), "nsteps_per_run": nsteps,
-             "launch": api.get_config("md_run", n, "fp64"),
-             "roofline": _roof(FLOPS_PER_PAIR * float(n) * n * nsteps, ms * 1e-3,
-                               "whole md_run (force stage + fused epilogue per step, energies as recorded)")}
+             "launch": cfg,
+             "roofline": _roof(force_eval_flops(n, cfg["algo"]) * nsteps, ms * 1e-3,
+                               "whole md_run (force stage + fused epilogue per step, energies as recorded)",
+                               _force_convention(cfg["algo"]))}
     if not args.no_cpu:
         from oracle import oracle as O
 
@@ -436,8 +534,10 @@ def bench_kz(args):
              "path": "stepped (p = 4, JL = 256, the default shape)", "nrun": d["nrun"],
              "nsteps_per_run": nsteps,
              "sum_N2": float((ns.astype(np.float64) ** 2).sum()),
-             "roofline": _roof(FLOPS_PER_PAIR * pairs, res["fp64"]["ms"] * 1e-3,
-                               "whole md_run: per step k_pair_sym_ens<FP64> over every run's tiles + k_ens_step<FP64>")}
+             "roofline": _roof(FLOPS_PER_SYM_PAIR * float((ns.astype(np.float64) * (ns - 1) / 2).sum()) * nsteps,
+                               res["fp64"]["ms"] * 1e-3,
+                               "whole md_run: per step k_pair_sym_ens<FP64> over every run's tiles + k_ens_step<FP64>",
+                               "27 FLOP per unordered pair x sum over runs of n(n-1)/2 per step (Newton's third law)")}
     if not args.no_cpu:
         from oracle import oracle as O
 
@@ -515,8 +615,14 @@ def bench_crystal(args):
         tp[key] += h
         tm[key] -= h
         fd[key] = {"adjoint": float(g[c]), "central_fd": (loss(tp) - loss(tm)) / (2 * h)}
-    hvp_flops = (38 + 12 * 7) * float(n) * n
-    extra = {"roofline": _roof(hvp_flops, ms_hvp * 1e-3, "cb::k_hvp<FP64> + epilogue, 8 vectors per pass"),
+    hcfg = api.get_config("hvp", n, "fp64")
+    hsym = hcfg["algo"] in SYM_ALGOS
+    extra = {"roofline": _roof(hvp_eval_flops(n, 8, hsym), ms_hvp * 1e-3,
+                               "cb::k_hvp<FP64> + epilogue, 8 vectors" if not hsym else
+                               "cb::k_hvp_sym<FP64> + finish, 8 vectors",
+                               ("15 + 30 B FLOP per unordered pair (B = 8 vectors) x n(n-1)/2" if hsym else
+                                "16 + 21 B FLOP per ordered pair (B = 8 vectors) x n(n-1)")),
+             "hvp_launch": hcfg,
              "minimise_s": t_min, "minimise": info, "hvp_ms_8vec": ms_hvp, "lanczos_s": t_lan,
              "lowest_over_wz2": [float(v) for v in lam[:6] / wz2],
              "zero_mode_rel": float(abs(lam[0]) / wz2), "kohn_axial_rel": kohn,
