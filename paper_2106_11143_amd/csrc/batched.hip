@@ -471,7 +471,7 @@ cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s
         ec.splits = 256;
     }
     if (ec.algo == ALGO_SYM_LDS) {
-        const WsLayout LE = ws_layout(CB_OP_MD_RUN, offsets[nrun], nrun, 1);
+        const WsLayout LE = ws_layout(CB_OP_MD_RUN, offsets[nrun], nrun, 1, prec);
         return md_run_ensemble(nrun, offsets, s, q, m, traps, t0, dt, nsteps, eps2, prec, flags, energies, every, ec.p,
                                ec.splits, static_cast<char*>(ws) + LE.aux, ws_bytes - LE.aux, st);
     }
@@ -479,7 +479,7 @@ cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s
     if (!fl) return fail(CB_EHIP, "md_run: device flag symbol not found");
 
     // run table in the workspace: offsets, order, traps, queue counter
-    const WsLayout L = ws_layout(CB_OP_MD_RUN, offsets[nrun], nrun, 1);
+    const WsLayout L = ws_layout(CB_OP_MD_RUN, offsets[nrun], nrun, 1, prec);
     char* base = static_cast<char*>(ws) + L.batch;
     int64_t* d_off = reinterpret_cast<int64_t*>(base);
     int* d_order = reinterpret_cast<int*>(d_off + (nrun + 1));

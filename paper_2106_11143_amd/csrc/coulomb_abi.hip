@@ -115,6 +115,16 @@ LaunchCfg default_cfg(int op, int64_t n, int prec) {
         c.splits = n >= 32768 ? 512 : 256;
         return c;
     }
+    if (op == CB_OP_HVP && n >= kHvpSymMinN && n <= hvp_sym_max_n(2)) {
+        // Hessian-vector products by Newton's third law (hvp_sym.hpp): two
+        // ions per lane (the four-vector pass keeps 24 vector components and
+        // 24 sums per lane) and short segments, for enough tiles at 8192 ions
+        c.algo = ALGO_SYM_LDS;
+        c.wg = kSymGroup;
+        c.p = 2;
+        c.splits = 128;
+        return c;
+    }
     c.wg = 64;
     c.p = 1;
     const int64_t waves = (n + 64 * c.p - 1) / (64 * c.p);
@@ -163,7 +173,10 @@ bool valid_cfg(int op, const LaunchCfg& c) {
         return (c.algo == ALGO_DIRECT && c.p == kBatchP && c.wg == kBatchWG && c.splits == 1) ||
                (c.algo == ALGO_SYM_LDS && c.wg == kSymGroup && ens_cfg_ok(c.p, c.splits));
     const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
-    if (is_sym(c.algo)) return force_op && sym_cfg_ok(c.p, c.wg, c.splits);
+    const bool hv_op = (op == CB_OP_HVP || op == CB_OP_ADJOINT);
+    if (is_sym(c.algo))
+        return (force_op && sym_cfg_ok(c.p, c.wg, c.splits)) ||
+               (hv_op && c.algo == ALGO_SYM_LDS && c.wg == kSymGroup && hvp_sym_cfg_ok(c.p, c.splits));
     if (c.algo != ALGO_DIRECT) return false;
     const bool p_ok = (op == CB_OP_HVP || op == CB_OP_ADJOINT) ? (c.p == 1 || c.p == 2)
                                                                  : (c.p == 1 || c.p == 2 || c.p == 4);
@@ -182,11 +195,14 @@ int n_splits(int64_t n, int jlen) { return (int)((n + jlen - 1) / jlen); }
 // ------------------------------------------------------------- workspace
 static size_t al(size_t b) { return (b + 255) / 256 * 256; }
 
-WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec) {
+WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec) {
     WsLayout L{};
     const size_t N = (size_t)n;
     const size_t nv = (size_t)std::max(1, (int)nvec);
     size_t off = 0;
+    // the configuration whose Newton's-third-law partials the buffer must hold
+    // (coulomb_trap_grad's force stage follows the forces' configuration)
+    const int cfg_op = op == CB_OP_GRAD ? CB_OP_FORCES : op;
     if (op == CB_OP_GRAD) op = CB_OP_MD_STEP;  // the same buffers: force stage, potential partials, energy blocks
     const bool batched = (op == CB_OP_MD_RUN && nrun > 1);
     const bool hv = (op == CB_OP_HVP || op == CB_OP_ADJOINT);
@@ -194,13 +210,12 @@ WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec) {
         L.part = off;
         size_t part = sizeof(double) * (size_t)kMaxSplits * 3 * (hv ? nv : 1) * N;
         const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
-        if (force_op && n <= kSymMaxN) {
-            // room for the symmetric path: finished forces [3][n] then its tiles and partials
-            size_t sym = 0;
-            for (int p : kSymP)
-                for (int jl : kSymJL) sym = std::max(sym, sym_ws_bytes(n, p, jl));
-            part = std::max(part, al(sizeof(double) * 3 * N) + sym);
-        }
+        const LaunchCfg c = get_cfg(cfg_op, n, prec);
+        if (force_op && n <= kSymMaxN && is_sym(c.algo) && sym_cfg_ok(c.p, c.wg, c.splits))
+            // the configured symmetric stage: finished forces [3][n] then its tiles and partials
+            part = std::max(part, al(sizeof(double) * 3 * N) + sym_ws_bytes(n, c.p, c.splits));
+        if (hv && is_sym(c.algo) && hvp_sym_cfg_ok(c.p, c.splits))
+            part = std::max(part, hvp_sym_ws_bytes(n, c.p, c.splits));
         off += al(part);
         L.ppot = off;
         if (op == CB_OP_ENERGY || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN)
@@ -257,7 +272,7 @@ const char* cb_last_error(void) { return t_err.c_str(); }
 size_t cb_workspace_size(int32_t op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec) {
     if (n < 1 || op < 0 || op == CB_OP_MD_ENSEMBLE || op > CB_OP_GRAD || prec < 0 || prec > CB_MIXED_F32D) return 0;
     if (op == CB_OP_HVP && (nvec < 1 || nvec > kMaxVec)) return 0;
-    return ws_layout(op, n, nrun, nvec).total;
+    return ws_layout(op, n, nrun, nvec, prec).total;
 }
 
 cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]) {
@@ -278,8 +293,9 @@ cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t algo, int32
         return ok();
     }
     LaunchCfg c{p, wg, splits, 1, algo};
-    if (!valid_cfg(op, c) || (is_sym(algo) && op != CB_OP_MD_ENSEMBLE && n > kSymMaxN) ||
-        (algo == ALGO_SMALL && n > kSmallRunMax))
+    const bool hv_op = (op == CB_OP_HVP || op == CB_OP_ADJOINT);
+    if (!valid_cfg(op, c) || (is_sym(algo) && op != CB_OP_MD_ENSEMBLE && !hv_op && n > kSymMaxN) ||
+        (is_sym(algo) && hv_op && n > hvp_sym_max_n(p)) || (algo == ALGO_SMALL && n > kSmallRunMax))
         return fail(CB_EINVAL, "cb_set_config: unsupported configuration algo=%d p=%d wg=%d splits=%d", algo, p, wg,
                     splits);
     put_cfg(op, n, prec, c);

@@ -70,8 +70,8 @@ static cb_status force_stage(int op, int prec, int64_t n, const double* x, const
     if (is_sym(cfg.algo) && n <= kSymMaxN && prec != CB_MIXED_F32D) {
         *S_out = 1;
         *prescaled = true;
-        void* scratch = static_cast<char*>(ws) + L.part + al256(sizeof(double) * 3 * (size_t)n);
-        return launch_pair_sym(prec, cfg, (int)n, x, y, z, q, eps2, scratch, part, st);
+        void* tiles_ws = static_cast<char*>(ws) + L.part + al256(sizeof(double) * 3 * (size_t)n);
+        return launch_pair_sym(prec, cfg, (int)n, x, y, z, q, eps2, tiles_ws, part, st);
     }
     const PairRun pr = plan(op, n, prec);
     *S_out = pr.S;
@@ -83,7 +83,7 @@ static cb_status force_stage(int op, int prec, int64_t n, const double* x, const
 static cb_status md_single(int64_t n, const cb_state* s, const double* q, const double* m, const cb_trap* trap,
                            double t0, double dt, int64_t nsteps, double eps2, int32_t prec, uint32_t flags,
                            double* energies, int64_t every, void* ws, int op, hipStream_t st) {
-    const WsLayout L = ws_layout(op, n, 1, 1);
+    const WsLayout L = ws_layout(op, n, 1, 1, prec);
     // One launch per step (every pair direct, then trap, kick and drift) when
     // so configured: the default up to kSmallRunMax ions.
     const LaunchCfg sc = get_cfg(op, n, prec);
@@ -218,7 +218,7 @@ extern "C" {
 cb_status coulomb_forces(int64_t n, const double* x, const double* y, const double* z, const double* q,
                          double eps2, int32_t prec, double* fx, double* fy, double* fz, void* ws, size_t ws_bytes,
                          void* stream) {
-    const WsLayout L = ws_layout(CB_OP_FORCES, n > 0 ? n : 1, 1, 1);
+    const WsLayout L = ws_layout(CB_OP_FORCES, n > 0 ? n : 1, 1, 1, prec);
     cb_status rc = check_common("coulomb_forces", n, prec, eps2, ws, ws_bytes, L.total);
     if (rc) return rc;
     if (!x || !y || !z || !q || !fx || !fy || !fz) return fail(CB_EINVAL, "coulomb_forces: NULL array");
@@ -253,7 +253,7 @@ cb_status coulomb_forces(int64_t n, const double* x, const double* y, const doub
 cb_status coulomb_forces_range(int64_t n, int64_t i0, int64_t i1, const double* x, const double* y, const double* z,
                                const double* q, double eps2, int32_t prec, double* fx, double* fy, double* fz,
                                void* ws, size_t ws_bytes, void* stream) {
-    const WsLayout L = ws_layout(CB_OP_FORCES, n > 0 ? n : 1, 1, 1);
+    const WsLayout L = ws_layout(CB_OP_FORCES, n > 0 ? n : 1, 1, 1, prec);
     cb_status rc = check_common("coulomb_forces_range", n, prec, eps2, ws, ws_bytes, L.total);
     if (rc) return rc;
     if (i0 < 0 || i1 <= i0 || i1 > n)
@@ -297,7 +297,7 @@ cb_status coulomb_forces_range(int64_t n, int64_t i0, int64_t i1, const double* 
 cb_status coulomb_pair_stage(int64_t n, const double* x, const double* y, const double* z, const double* q,
                              double eps2, int32_t prec, int32_t* splits_out, void* ws, size_t ws_bytes,
                              void* stream) {
-    const WsLayout L = ws_layout(CB_OP_FORCES, n > 0 ? n : 1, 1, 1);
+    const WsLayout L = ws_layout(CB_OP_FORCES, n > 0 ? n : 1, 1, 1, prec);
     cb_status rc = check_common("coulomb_pair_stage", n, prec, eps2, ws, ws_bytes, L.total);
     if (rc) return rc;
     if (!x || !y || !z || !q || !splits_out) return fail(CB_EINVAL, "coulomb_pair_stage: NULL argument");
@@ -312,7 +312,7 @@ cb_status coulomb_pair_stage(int64_t n, const double* x, const double* y, const 
 
 cb_status coulomb_energy(int64_t n, const double* x, const double* y, const double* z, const double* q,
                          double eps2, int32_t prec, double* u_out, void* ws, size_t ws_bytes, void* stream) {
-    const WsLayout L = ws_layout(CB_OP_ENERGY, n > 0 ? n : 1, 1, 1);
+    const WsLayout L = ws_layout(CB_OP_ENERGY, n > 0 ? n : 1, 1, 1, prec);
     cb_status rc = check_common("coulomb_energy", n, prec, eps2, ws, ws_bytes, L.total);
     if (rc) return rc;
     if (prec == CB_MIXED_F32D) return fail(CB_EUNSUPPORTED, "coulomb_energy: CB_MIXED_F32D is for the forces only");
@@ -343,7 +343,7 @@ cb_status coulomb_energy(int64_t n, const double* x, const double* y, const doub
 cb_status coulomb_trap_grad(int64_t n, const double* x, const double* y, const double* z, const double* q,
                             const double* m, const cb_trap* trap, double t, double eps2, int32_t prec, double* gx,
                             double* gy, double* gz, double* u_out, void* ws, size_t ws_bytes, void* stream) {
-    const WsLayout L = ws_layout(CB_OP_GRAD, n > 0 ? n : 1, 1, 1);
+    const WsLayout L = ws_layout(CB_OP_GRAD, n > 0 ? n : 1, 1, 1, prec);
     cb_status rc = check_common("coulomb_trap_grad", n, prec, eps2, ws, ws_bytes, L.total);
     if (rc) return rc;
     if (prec == CB_MIXED_F32D) return fail(CB_EUNSUPPORTED, "coulomb_trap_grad: CB_MIXED_F32D is for the forces only");
@@ -408,7 +408,7 @@ cb_status coulomb_trap_grad(int64_t n, const double* x, const double* y, const d
 
 cb_status md_step(int64_t n, const cb_state* s, const double* q, const double* m, const cb_trap* trap, double t,
                   double dt, double eps2, int32_t prec, void* ws, size_t ws_bytes, void* stream) {
-    const WsLayout L = ws_layout(CB_OP_MD_STEP, n > 0 ? n : 1, 1, 1);
+    const WsLayout L = ws_layout(CB_OP_MD_STEP, n > 0 ? n : 1, 1, 1, prec);
     cb_status rc = check_common("md_step", n, prec, eps2, ws, ws_bytes, L.total);
     if (rc) return rc;
     if (prec == CB_MIXED_F32D) return fail(CB_EUNSUPPORTED, "md_step: CB_MIXED_F32D is for the forces only");
@@ -427,7 +427,7 @@ cb_status md_run(int32_t nrun, const int64_t* offsets, const cb_state* s, const 
     for (int r = 0; r < nrun; ++r)
         if (offsets[r + 1] <= offsets[r]) return fail(CB_EINVAL, "md_run: offsets must increase strictly");
     const int64_t n = offsets[nrun];
-    const WsLayout L = ws_layout(CB_OP_MD_RUN, n, nrun, 1);
+    const WsLayout L = ws_layout(CB_OP_MD_RUN, n, nrun, 1, prec);
     cb_status rc = check_common("md_run", n, prec, eps2, ws, ws_bytes, L.total);
     if (rc) return rc;
     if (prec == CB_MIXED_F32D) return fail(CB_EUNSUPPORTED, "md_run: CB_MIXED_F32D is for the forces only");

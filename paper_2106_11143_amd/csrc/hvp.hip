@@ -7,6 +7,7 @@
 #include <cmath>
 
 #include "hvp_kernels.hpp"
+#include "hvp_sym.hpp"
 #include "internal.hpp"
 #include "split_sum.hpp"
 #include "step_common.hpp"
@@ -55,6 +56,114 @@ cb_status launch_hvp(int prec, const LaunchCfg& c, int nvec, int n, const double
     }
     if (!okk) return fail(CB_EINVAL, "launch_hvp: unsupported precision %d / p %d / nvec %d", prec, c.p, nvec);
     return check_launch("k_hvp");
+}
+
+// ------------------------------------------- Newton's third law (hvp_sym.hpp)
+static size_t al256h(size_t b) { return (b + 255) / 256 * 256; }
+
+// tile table | Pi[T][4][3][IB] | R[T][4][3][JL] | packed j records [n][16]
+size_t hvp_sym_ws_bytes(int64_t n, int p, int jl) {
+    const int IB = 64 * p;
+    const int64_t T = sym_tiles(n, IB, jl);
+    return sym_plan_bytes(n, IB, jl) + al256h(sizeof(double) * 12 * (size_t)IB * (T + 1)) +
+           al256h(sizeof(double) * 12 * (size_t)jl * (T + 1)) + al256h(sizeof(double) * kHvpRec * (size_t)n);
+}
+
+template <int PREC, int P, int NV>
+static void go_hvp_sym(int n, const SymPlan& pl, int JL, const double* x, const double* y, const double* z,
+                       const double* q, const double* v, const double* J, double eps2, double* Pi, double* R,
+                       hipStream_t st) {
+    k_hvp_sym<PREC, P, NV><<<(unsigned)pl.T, 64, 0, st>>>(n, x, y, z, q, v, J, eps2, JL, pl.tiles, Pi, R);
+}
+
+template <int PREC, int NV>
+static bool go_hvp_sym_p(int P, int n, const SymPlan& pl, int JL, const double* x, const double* y, const double* z,
+                         const double* q, const double* v, const double* J, double eps2, double* Pi, double* R,
+                         hipStream_t st) {
+    switch (P) {
+        case 1: go_hvp_sym<PREC, 1, NV>(n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st); return true;
+        case 2: go_hvp_sym<PREC, 2, NV>(n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st); return true;
+        case 4: go_hvp_sym<PREC, 4, NV>(n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st); return true;
+        default: return false;
+    }
+}
+
+template <int PREC>
+static bool go_hvp_sym_nv(int nv, int P, int n, const SymPlan& pl, int JL, const double* x, const double* y,
+                          const double* z, const double* q, const double* v, const double* J, double eps2, double* Pi,
+                          double* R, hipStream_t st) {
+    switch (nv) {
+        case 1: return go_hvp_sym_p<PREC, 1>(P, n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st);
+        case 2: return go_hvp_sym_p<PREC, 2>(P, n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st);
+        case 4: return go_hvp_sym_p<PREC, 4>(P, n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st);
+        default: return false;
+    }
+}
+
+template <int PREC>
+static bool go_hvp_fin(int nv, unsigned nb, int n, int IB, int JL, int lgJL, const double* x, const double* y,
+                       const double* z, const double* q, const double* v, double eps2, const int* rowstart,
+                       const double* Pi, const double* R, const double* m, TrapK k, double* hv, unsigned* fl,
+                       hipStream_t st) {
+    const dim3 g(nb), b(64 * kFinishParts);
+    switch (nv) {
+        case 1: k_hvp_sym_finish<PREC, 1><<<g, b, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, v, eps2, rowstart, Pi, R, m, k, hv, fl); return true;
+        case 2: k_hvp_sym_finish<PREC, 2><<<g, b, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, v, eps2, rowstart, Pi, R, m, k, hv, fl); return true;
+        case 4: k_hvp_sym_finish<PREC, 4><<<g, b, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, v, eps2, rowstart, Pi, R, m, k, hv, fl); return true;
+        default: return false;
+    }
+}
+
+// nvec products in passes of 4, 2, 1 vectors: per pass the j records are
+// packed, the tiles evaluated and each ion finished (trap term included).
+static cb_status launch_hvp_sym(int prec, const LaunchCfg& c, int nvec, int n, const double* x, const double* y,
+                                const double* z, const double* q, const double* v, const double* m, TrapK k,
+                                double eps2, void* ws, double* hv, unsigned* fl, hipStream_t st) {
+    const int P = c.p, JL = c.splits, IB = 64 * P;
+    if (!hvp_sym_cfg_ok(P, JL) || n > hvp_sym_max_n(P))
+        return fail(CB_EINVAL, "coulomb_hvp: bad Newton's-third-law configuration p %d / JL %d at n = %d", P, JL, n);
+    SymPlan pl;
+    cb_status rc = sym_plan(n, IB, JL, ws, &pl, st);
+    if (rc) return rc;
+    char* base = static_cast<char*>(ws) + pl.bytes;
+    double* Pi = reinterpret_cast<double*>(base);
+    base += al256h(sizeof(double) * 12 * (size_t)IB * (pl.T + 1));
+    double* R = reinterpret_cast<double*>(base);
+    base += al256h(sizeof(double) * 12 * (size_t)JL * (pl.T + 1));
+    double* J = reinterpret_cast<double*>(base);
+    int lgJL = 0;
+    while ((1 << lgJL) < JL) ++lgJL;
+    const unsigned nb = (unsigned)((n + 63) / 64);
+    for (int b0 = 0; b0 < nvec;) {
+        const int left = nvec - b0;
+        const int nv = left >= 4 ? 4 : left >= 2 ? 2 : 1;
+        const double* vb = v + (size_t)b0 * 3 * n;
+        double* hb = hv + (size_t)b0 * 3 * n;
+        k_hvp_pack<<<(n + 255) / 256, 256, 0, st>>>(n, nv, x, y, z, q, vb, J);
+        if ((rc = check_launch("k_hvp_pack"))) return rc;
+        bool okk = false;
+        if (pl.T > 0) {
+            switch (prec) {
+                case PREC_FP64: okk = go_hvp_sym_nv<PREC_FP64>(nv, P, n, pl, JL, x, y, z, q, vb, J, eps2, Pi, R, st); break;
+                case PREC_MIXED: okk = go_hvp_sym_nv<PREC_MIXED>(nv, P, n, pl, JL, x, y, z, q, vb, J, eps2, Pi, R, st); break;
+                case PREC_IEEE: okk = go_hvp_sym_nv<PREC_IEEE>(nv, P, n, pl, JL, x, y, z, q, vb, J, eps2, Pi, R, st); break;
+                case PREC_FP32: okk = go_hvp_sym_nv<PREC_FP32>(nv, P, n, pl, JL, x, y, z, q, vb, J, eps2, Pi, R, st); break;
+                default: break;
+            }
+            if (!okk) return fail(CB_EINVAL, "coulomb_hvp: unsupported precision %d / p %d", prec, P);
+            if ((rc = check_launch("k_hvp_sym"))) return rc;
+        }
+        switch (prec) {
+            case PREC_FP64: okk = go_hvp_fin<PREC_FP64>(nv, nb, n, IB, JL, lgJL, x, y, z, q, vb, eps2, pl.rowstart, Pi, R, m, k, hb, fl, st); break;
+            case PREC_MIXED: okk = go_hvp_fin<PREC_MIXED>(nv, nb, n, IB, JL, lgJL, x, y, z, q, vb, eps2, pl.rowstart, Pi, R, m, k, hb, fl, st); break;
+            case PREC_IEEE: okk = go_hvp_fin<PREC_IEEE>(nv, nb, n, IB, JL, lgJL, x, y, z, q, vb, eps2, pl.rowstart, Pi, R, m, k, hb, fl, st); break;
+            default: okk = go_hvp_fin<PREC_FP32>(nv, nb, n, IB, JL, lgJL, x, y, z, q, vb, eps2, pl.rowstart, Pi, R, m, k, hb, fl, st); break;
+        }
+        if (!okk) return fail(CB_EINVAL, "coulomb_hvp: unsupported vector count %d", nv);
+        if ((rc = check_launch("k_hvp_sym_finish"))) return rc;
+        b0 += nv;
+    }
+    return CB_OK;
 }
 
 // --------------------------------------------------------- element-wise
@@ -197,7 +306,7 @@ cb_status coulomb_hvp(int64_t n, const double* x, const double* y, const double*
                       const double* v, double* hv, const double* m, const cb_trap* trap, double t, double eps2,
                       int32_t prec, void* ws, size_t ws_bytes, void* stream) {
     if (nvec < 1 || nvec > kMaxVec) return fail(CB_EINVAL, "coulomb_hvp: nvec = %d out of range [1, %d]", nvec, kMaxVec);
-    const WsLayout L = ws_layout(CB_OP_HVP, n > 0 ? n : 1, 1, nvec);
+    const WsLayout L = ws_layout(CB_OP_HVP, n > 0 ? n : 1, 1, nvec, prec);
     cb_status rc = hvp_common("coulomb_hvp", n, prec, eps2, ws, ws_bytes, L.total);
     if (rc) return rc;
     if (!x || !y || !z || !q || !v || !hv) return fail(CB_EINVAL, "coulomb_hvp: NULL array");
@@ -212,10 +321,14 @@ cb_status coulomb_hvp(int64_t n, const double* x, const double* y, const double*
     if (!fl) return fail(CB_EHIP, "coulomb_hvp: device flag symbol not found");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const LaunchCfg cfg = get_cfg(CB_OP_HVP, n, prec);
-    const int jlen = split_len(n, cfg.splits);
-    const int S = n_splits(n, jlen);
     const TrapK k = m ? trap_k(*trap, t) : TrapK{0.0, 0.0, 0.0};
     double* part = at(ws, L.part);
+    if (is_sym(cfg.algo)) {
+        if ((rc = launch_hvp_sym(prec, cfg, nvec, (int)n, x, y, z, q, v, m, k, eps2, part, hv, fl, st))) return rc;
+        return ok();
+    }
+    const int jlen = split_len(n, cfg.splits);
+    const int S = n_splits(n, jlen);
     // vectors in passes of 4, 2, 1 (eight per pass need too many registers)
     for (int b0 = 0; b0 < nvec;) {
         const int left = nvec - b0;
@@ -233,7 +346,7 @@ cb_status coulomb_hvp(int64_t n, const double* x, const double* y, const double*
 cb_status md_adjoint_step(int64_t n, const double* x, const double* y, const double* z, const double* q,
                           const double* m, const cb_trap* trap, double dt, double eps2, int32_t prec, uint32_t flags,
                           double* lam, double* dldw, void* ws, size_t ws_bytes, void* stream) {
-    const WsLayout L = ws_layout(CB_OP_ADJOINT, n > 0 ? n : 1, 1, 1);
+    const WsLayout L = ws_layout(CB_OP_ADJOINT, n > 0 ? n : 1, 1, 1, prec);
     cb_status rc = hvp_common("md_adjoint_step", n, prec, eps2, ws, ws_bytes, L.total);
     if (rc) return rc;
     if (!x || !y || !z || !q || !m || !lam || !dldw) return fail(CB_EINVAL, "md_adjoint_step: NULL argument");

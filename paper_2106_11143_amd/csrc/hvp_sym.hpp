@@ -1,0 +1,307 @@
+// Hessian-vector products by Newton's third law: each unordered pair (i, j)
+// evaluated once for NV vectors.
+//
+// With d = r_i - r_j, u = v_i - v_j and y = (|d|^2 + eps2)^{-1/2}, ion i's
+// pair term is k_C q_i q_j T_ij with T_ij = 3 d (d . u) y^5 - u y^3, and
+// T_ji = -T_ij (d and u both change sign).  So, as for the force
+// (pair_sym.hpp), a tile of i-block I and j-segment s evaluates T once per
+// pair, adds q_i q_j T_ij to i's sums and the wave's sum over i of q_i T_ij
+// to j's reaction (the finish scales it by -k_C q_j).  The same tile table,
+// partial layout per vector and fixed-order finish as the force stage.
+//
+// Per lane: P i-particles with their NV vectors' components; per j (uniform,
+// one 16-double record of position, charge and vector components read by
+// scalar loads, the next j requested before the current is evaluated).  The
+// 3 NV reaction values of each j are kept for 4 / NV j's, i.e. 12 values,
+// and summed over the wave together by lds_reduce12.  Tiles of one charge per
+// side (ions grouped by species) drop q_i and q_j from the pair loop and
+// scale the partials when they are stored.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hvp_kernels.hpp"
+#include "pair_sym.hpp"
+#include "step_common.hpp"
+
+namespace cb {
+
+constexpr int kHvpRec = 16;  // doubles per packed j record: x, y, z, q, v[b][c] (b < 4)
+
+// J[i] = (x, y, z, q, v[0][0..2], ..., v[nv-1][0..2], 0 ...) for one pass of nv <= 4 vectors.
+__global__ void __launch_bounds__(256) k_hvp_pack(int n, int nv, const double* __restrict__ x,
+                                                  const double* __restrict__ y, const double* __restrict__ z,
+                                                  const double* __restrict__ q, const double* __restrict__ v,
+                                                  double* __restrict__ J) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double* r = J + (size_t)i * kHvpRec;
+    r[0] = x[i];
+    r[1] = y[i];
+    r[2] = z[i];
+    r[3] = q[i];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) r[4 + k] = (k / 3) < nv ? v[(size_t)k * n + i] : 0.0;
+}
+
+template <int NV>
+struct HvpJRec {
+    double x, y, z, q, v[NV][3];
+};
+
+template <int NV>
+__device__ __forceinline__ HvpJRec<NV> load_hvp_j(const double* __restrict__ J, int j) {
+    const double* r = J + (size_t)j * kHvpRec;
+    HvpJRec<NV> a;
+    a.x = r[0];
+    a.y = r[1];
+    a.z = r[2];
+    a.q = r[3];
+#pragma unroll
+    for (int b = 0; b < NV; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.v[b][c] = r[4 + 3 * b + c];
+    return a;
+}
+
+// Pairs of one j with the lane's P ions: i sums into ia[p][b][c] (q_i q_j T,
+// or T when UNI), this lane's share of j's reaction (sum over p of q_i T, or
+// T) into sh[b][c].
+template <int PREC, int P, int NV, bool UNI>
+__device__ __forceinline__ void hvp_sym_pair(const HvpJRec<NV>& J, double eps2, const double (&xi)[P],
+                                             const double (&yi)[P], const double (&zi)[P], const double (&qi)[P],
+                                             const double (&vi)[NV][3][P], double (&ia)[P][NV][3],
+                                             double (&sh)[NV][3], const SeriesK& K) {
+#pragma unroll
+    for (int b = 0; b < NV; ++b) sh[b][0] = sh[b][1] = sh[b][2] = 0.0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const double dx = xi[p] - J.x, dy = yi[p] - J.y, dz = zi[p] - J.z;
+        const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
+        double s3, s5;  // q_i y^3 and 3 q_i y^5 (y^3, 3 y^5 when UNI)
+        hvp_scales<PREC>(r2, UNI ? 1.0 : qi[p], K, s3, s5);
+#pragma unroll
+        for (int b = 0; b < NV; ++b) {
+            const double ux = vi[b][0][p] - J.v[b][0];
+            const double uy = vi[b][1][p] - J.v[b][1];
+            const double uz = vi[b][2][p] - J.v[b][2];
+            const double c = __builtin_fma(dx, ux, __builtin_fma(dy, uy, dz * uz)) * s5;
+            const double tx = __builtin_fma(dx, c, -(ux * s3));
+            const double ty = __builtin_fma(dy, c, -(uy * s3));
+            const double tz = __builtin_fma(dz, c, -(uz * s3));
+            if constexpr (UNI) {
+                ia[p][b][0] += tx;
+                ia[p][b][1] += ty;
+                ia[p][b][2] += tz;
+            } else {
+                ia[p][b][0] = __builtin_fma(J.q, tx, ia[p][b][0]);
+                ia[p][b][1] = __builtin_fma(J.q, ty, ia[p][b][1]);
+                ia[p][b][2] = __builtin_fma(J.q, tz, ia[p][b][2]);
+            }
+            sh[b][0] += tx;
+            sh[b][1] += ty;
+            sh[b][2] += tz;
+        }
+    }
+}
+
+// Waves per SIMD the register budget of k_hvp_sym is sized for (each lane
+// holds 6 NV + 4 doubles per i-particle and 3 NV sums; at these targets the
+// variants spill at most a few registers).
+template <int P, int NV>
+constexpr int hvp_sym_waves() {
+    return P == 1 ? 4 : (P == 2 ? (NV == 4 ? 3 : 4) : (NV == 1 ? 3 : 2));
+}
+
+// The j loop of tile t over [j0, j1) and the stores of its partials:
+// Pi[t][NV][3][IB] and R[t][NV][3][JL].
+template <int PREC, int P, int NV, bool UNI>
+__device__ __forceinline__ void hvp_sym_body(const double* __restrict__ J, double eps2, int JL, int j0, int j1, int t,
+                                             const double (&xi)[P], const double (&yi)[P], const double (&zi)[P],
+                                             const double (&qi)[P], const double (&vi)[NV][3][P], double qI,
+                                             double qJ, double* __restrict__ red, double* __restrict__ Pi,
+                                             double* __restrict__ R) {
+    constexpr int IB = 64 * P;
+    constexpr int GJ = 4 / NV;  // j's whose 3 NV reaction values make one 12-value wave sum
+    const int lane = threadIdx.x;
+    double ia[P][NV][3];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int b = 0; b < NV; ++b) ia[p][b][0] = ia[p][b][1] = ia[p][b][2] = 0.0;
+    const SeriesK K;
+    double* Rt = R + (size_t)t * NV * 3 * JL;
+    HvpJRec<NV> cur = load_hvp_j<NV>(J, j0);
+    for (int jg = j0; jg < j1; jg += GJ) {
+        const int live = min(GJ, j1 - jg);
+        double sh[GJ][NV][3];
+#pragma unroll
+        for (int g = 0; g < GJ; ++g) {
+            // the next j's record is requested before this j is evaluated
+            const HvpJRec<NV> nxt = load_hvp_j<NV>(J, min(jg + g + 1, j1 - 1));
+            __builtin_amdgcn_sched_barrier(0);
+            if (g < live) {
+                hvp_sym_pair<PREC, P, NV, UNI>(cur, eps2, xi, yi, zi, qi, vi, ia, sh[g], K);
+            } else {
+#pragma unroll
+                for (int b = 0; b < NV; ++b) sh[g][b][0] = sh[g][b][1] = sh[g][b][2] = 0.0;
+            }
+            cur = nxt;
+        }
+        // the empty asm keeps the i sums' updates ahead of the reduction (as in
+        // the force tiles: otherwise their operands stay live through it)
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int b = 0; b < NV; ++b) asm volatile("" : "+v"(ia[p][b][0]), "+v"(ia[p][b][1]), "+v"(ia[p][b][2]));
+        double v12[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v12[k] = sh[k / (3 * NV)][(k / 3) % NV][k % 3];
+        const double o = lds_reduce12(v12, red);
+        const int v = lane >> 2;  // value v = (g NV + b) 3 + c of quad v
+        if ((lane & 3) == 0 && v < 12) {
+            const int g = v / (3 * NV), b = (v / 3) % NV, c = v % 3;
+            if (g < live) Rt[(size_t)(b * 3 + c) * JL + (jg - j0) + g] = UNI ? o * qI : o;
+        }
+    }
+    const double sc = UNI ? qI * qJ : 1.0;
+    double* Pt = Pi + (size_t)t * NV * 3 * IB;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int b = 0; b < NV; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                Pt[(size_t)(b * 3 + c) * IB + p * 64 + lane] = UNI ? sc * ia[p][b][c] : ia[p][b][c];
+}
+
+// One wave per tile (row I, segment s) of the tile table.  v: [NV][3][n] of
+// this pass; J: its packed j records.
+template <int PREC, int P, int NV>
+__global__ void __launch_bounds__(64, (hvp_sym_waves<P, NV>())) k_hvp_sym(int n, const double* __restrict__ x,
+                                                                  const double* __restrict__ y,
+                                                                  const double* __restrict__ z,
+                                                                  const double* __restrict__ q,
+                                                                  const double* __restrict__ v,
+                                                                  const double* __restrict__ J, double eps2, int JL,
+                                                                  const int2* __restrict__ tiles,
+                                                                  double* __restrict__ Pi, double* __restrict__ R) {
+    __shared__ __align__(16) double red[12 * kRedStride];
+    constexpr int IB = 64 * P;
+    const int t = blockIdx.x;
+    const int2 tl = tiles[t];
+    const int lane = threadIdx.x;
+    double xi[P], yi[P], zi[P], qi[P], vi[NV][3][P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int i = tl.x * IB + p * 64 + lane;  // rows with tiles are full blocks
+        xi[p] = x[i];
+        yi[p] = y[i];
+        zi[p] = z[i];
+        qi[p] = q[i];
+#pragma unroll
+        for (int b = 0; b < NV; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vi[b][c][p] = v[(size_t)(b * 3 + c) * n + i];
+    }
+    const int j0 = (tl.x + 1) * IB + tl.y * JL;
+    const int j1 = min(n, j0 + JL);
+    double qI, qJ;
+    if (tile_charges<P>(qi, q, j0, j1, qI, qJ))
+        hvp_sym_body<PREC, P, NV, true>(J, eps2, JL, j0, j1, t, xi, yi, zi, qi, vi, qI, qJ, red, Pi, R);
+    else
+        hvp_sym_body<PREC, P, NV, false>(J, eps2, JL, j0, j1, t, xi, yi, zi, qi, vi, 1.0, 1.0, red, Pi, R);
+}
+
+// Per ion k (64 ions per workgroup, kFinishParts waves each taking a fixed
+// share of every sum): the pairs inside k's own i-block (direct, self pair
+// skipped), k's i sums over the tiles of its row, minus q_k times its
+// reactions from the rows above; hv[b][c][k] = k_C (those) + m_k kk_c v_k (m
+// may be NULL).  The waves' shares are added in wave order (deterministic).
+template <int PREC, int NV>
+__global__ void __launch_bounds__(64 * kFinishParts) k_hvp_sym_finish(
+    int n, int IB, int JL, int lgJL, const double* __restrict__ x, const double* __restrict__ y,
+    const double* __restrict__ z, const double* __restrict__ q, const double* __restrict__ v, double eps2,
+    const int* __restrict__ rowstart, const double* __restrict__ Pi, const double* __restrict__ R,
+    const double* __restrict__ m, TrapK kk, double* __restrict__ hv, unsigned* flags) {
+    __shared__ double red[kFinishParts][3 * NV][64];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int k0 = blockIdx.x * 64;
+    const int k = k0 + lane;
+    const int kc = min(k, n - 1);
+    const int Ik = k0 / IB;
+    const int b0 = Ik * IB, b1 = min(n, b0 + IB);
+    const double xk = x[kc], yk = y[kc], zk = z[kc], qk = q[kc];
+    double vk[NV][3];
+#pragma unroll
+    for (int b = 0; b < NV; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vk[b][c] = v[(size_t)(b * 3 + c) * n + kc];
+    const SeriesK K;
+    int lo, hi;
+    double d[NV][3], e[NV][3], s[NV][3];
+#pragma unroll
+    for (int b = 0; b < NV; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d[b][c] = e[b][c] = s[b][c] = 0.0;
+    share(b0, b1, w, lo, hi);
+    for (int j = lo; j < hi; ++j) {  // q_j T_kj over k's own block
+        const double dx = xk - x[j], dy = yk - y[j], dz = zk - z[j];
+        const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
+        double s3, s5;
+        hvp_scales<PREC>(r2, q[j], K, s3, s5);
+        if (j == kc) s3 = s5 = 0.0;
+#pragma unroll
+        for (int b = 0; b < NV; ++b) {
+            const double ux = vk[b][0] - v[(size_t)(b * 3 + 0) * n + j];
+            const double uy = vk[b][1] - v[(size_t)(b * 3 + 1) * n + j];
+            const double uz = vk[b][2] - v[(size_t)(b * 3 + 2) * n + j];
+            const double c = __builtin_fma(dx, ux, __builtin_fma(dy, uy, dz * uz)) * s5;
+            d[b][0] += __builtin_fma(dx, c, -(ux * s3));
+            d[b][1] += __builtin_fma(dy, c, -(uy * s3));
+            d[b][2] += __builtin_fma(dz, c, -(uz * s3));
+        }
+    }
+    const int off = kc - b0;
+    share(rowstart[Ik], rowstart[Ik + 1], w, lo, hi);
+    for (int t = lo; t < hi; ++t) {  // k's i sums over the tiles of its row
+        const double* Pt = Pi + (size_t)t * NV * 3 * IB + off;
+#pragma unroll
+        for (int b = 0; b < NV; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s[b][c] += Pt[(size_t)(b * 3 + c) * IB];
+    }
+    share(0, Ik, w, lo, hi);
+    for (int I = lo; I < hi; ++I) {  // k's reactions from the rows above
+        const int rel = kc - (I + 1) * IB;
+        const int sI = rel >> lgJL;
+        const double* Rt = R + (size_t)(rowstart[I] + sI) * NV * 3 * JL + (rel - (sI << lgJL));
+#pragma unroll
+        for (int b = 0; b < NV; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) e[b][c] += Rt[(size_t)(b * 3 + c) * JL];
+    }
+#pragma unroll
+    for (int b = 0; b < NV; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) red[w][b * 3 + c][lane] = s[b][c] + qk * (d[b][c] - e[b][c]);
+    __syncthreads();
+    if (w != 0 || k >= n) return;
+    const double kc3[3] = {kk.kx, kk.ky, kk.kz};
+    const double mk = m ? m[k] : 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int b = 0; b < NV; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double a = red[0][b * 3 + c][lane];
+#pragma unroll
+            for (int u = 1; u < kFinishParts; ++u) a += red[u][b * 3 + c][lane];
+            const double h = __builtin_fma(mk * kc3[c], vk[b][c], kCoulomb * a);
+            hv[(size_t)(b * 3 + c) * n + k] = h;
+            ok = ok && __builtin_isfinite(h);
+        }
+    if (!ok) atomicOr(flags, 1u);
+}
+
+}  // namespace cb

@@ -33,6 +33,21 @@ constexpr int kSymP[] = {2, 3, 4, 5, 6, 8};
 constexpr int kSymGroup = 4;
 constexpr int kSymJL[] = {256, 512, 1024, 2048};
 
+// Newton's-third-law Hessian-vector products (hvp.hip): i-particles per
+// lane, segment lengths, the smallest n of the default, the largest n a
+// tile table holds, and the workspace of the configuration.
+constexpr int kHvpSymP[] = {1, 2, 4};
+constexpr int kHvpSymJL[] = {64, 128, 256, 512};
+constexpr int64_t kHvpSymMinN = 4096;
+constexpr bool hvp_sym_cfg_ok(int p, int jl) {
+    bool pk = false, jk = false;
+    for (int v : kHvpSymP) pk = pk || v == p;
+    for (int v : kHvpSymJL) jk = jk || v == jl;
+    return pk && jk;
+}
+constexpr int64_t hvp_sym_max_n(int p) { return int64_t(2048) * 64 * p; }
+size_t hvp_sym_ws_bytes(int64_t n, int p, int jl);
+
 constexpr bool sym_cfg_ok(int p, int g, int jl) {
     bool pk = false, jk = false;
     for (int v : kSymP) pk = pk || v == p;
@@ -87,9 +102,25 @@ void drop_cfg(int op, int64_t n, int prec);
 bool valid_cfg(int op, const LaunchCfg& c);
 int split_len(int64_t n, int splits);
 int n_splits(int64_t n, int jlen);
-WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec);
+// Workspace carve-up of an entry point; sized for the launch configuration
+// get_cfg picks for (op, n, prec) at the time of the call.
+WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec);
 
 bool trap_ok(const cb_trap* t, const char* who, cb_status* st);
+
+// Tile table of the Newton's-third-law kernels (pair_sym.hip): rows of
+// i-blocks of IB ions, each cut into j-segments of JL.  sym_plan carves
+// rowstart[nI+1] and tiles[T] from the start of ws (sym_plan_bytes of it)
+// and enqueues the kernel that fills them.
+struct SymPlan {
+    int* rowstart;
+    int2* tiles;
+    int64_t T;
+    size_t bytes;
+};
+int64_t sym_tiles(int64_t n, int IB, int JL);
+size_t sym_plan_bytes(int64_t n, int IB, int JL);
+cb_status sym_plan(int n, int IB, int JL, void* ws, SymPlan* out, hipStream_t st);
 
 // Symmetric (Newton's third law) force path (pair.hip): workspace bytes for
 // (n, p, JL), and the launch sequence ending with finished forces F[3][n].

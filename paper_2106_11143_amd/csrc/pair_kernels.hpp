@@ -54,9 +54,46 @@ struct Acc {
             if (POT) ph[p] += o.ph[p];
         }
     }
+    // this += c o (a chunk of one j charge c, summed without it)
+    __device__ __forceinline__ void add_scaled(const Acc& o, double c) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (FORCE) {
+                fx[p] = __builtin_fma(c, o.fx[p], fx[p]);
+                fy[p] = __builtin_fma(c, o.fy[p], fy[p]);
+                fz[p] = __builtin_fma(c, o.fz[p], fz[p]);
+            }
+            if (POT) ph[p] = __builtin_fma(c, o.ph[p], ph[p]);
+        }
+    }
 };
 
-// One pair (i, j): acc += q_j d / (r^2+eps2)^{3/2} and/or q_j / (r^2+eps2)^{1/2}.
+// Whether every ion of [j0, j1) carries one charge, and that charge (qJ):
+// the range's pairs then need no per-pair charge load or multiply (ions
+// grouped by species, the paper's split of species into separate N-body
+// sub-problems in section 2).  Wave-uniform; a non-finite charge makes it
+// false.  Every lane of the wave must call it.
+__device__ __forceinline__ bool range_charge(const double* __restrict__ q, int j0, int j1, double& qJ) {
+    double lo = 0.0, hi = 0.0;
+    bool fin = true;
+    if (j1 > j0) lo = hi = q[j0];
+    for (int j = j0 + (int)__lane_id(); j < j1; j += 64) {
+        const double v = q[j];
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+        fin = fin && __builtin_isfinite(v);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o));
+        hi = fmax(hi, __shfl_xor(hi, o));
+    }
+    qJ = lo;
+    return __builtin_amdgcn_ballot_w64(!fin) == 0 && lo == hi;
+}
+
+// One pair (i, j): acc += q_j d / (r^2+eps2)^{3/2} and/or q_j / (r^2+eps2)^{1/2}
+// (qj = 1 in ranges of one charge, which the caller applies per chunk).
 template <int PREC, int P, bool FORCE, bool POT, bool MASK>
 __device__ __forceinline__ void pair_j(const IBlock<P>& ib, Acc<P, FORCE, POT>& a, double xj, double yj,
                                        double zj, double qj, double eps2, int j, const SeriesK& K) {
@@ -86,11 +123,13 @@ __device__ __forceinline__ void pair_j(const IBlock<P>& ib, Acc<P, FORCE, POT>& 
     }
 }
 
-template <int PREC, int P, bool FORCE, bool POT, bool MASK>
+// UNI: every j of the range has charge qJ; the pairs are summed without it
+// and each chunk's sums are scaled by qJ.
+template <int PREC, int P, bool FORCE, bool POT, bool MASK, bool UNI>
 __device__ __forceinline__ void pair_range(const IBlock<P>& ib, Acc<P, FORCE, POT>& tot, int ja, int jb,
                                            const double* __restrict__ x, const double* __restrict__ y,
                                            const double* __restrict__ z, const double* __restrict__ q,
-                                           double eps2, const SeriesK& K) {
+                                           double eps2, double qJ, const SeriesK& K) {
     for (int jc = ja; jc < jb; jc += kChunk) {
         const int je = min(jb, jc + kChunk);
         Acc<P, FORCE, POT> a;
@@ -99,11 +138,28 @@ __device__ __forceinline__ void pair_range(const IBlock<P>& ib, Acc<P, FORCE, PO
         for (; j + kUnroll <= je; j += kUnroll) {
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u)
-                pair_j<PREC, P, FORCE, POT, MASK>(ib, a, x[j + u], y[j + u], z[j + u], q[j + u], eps2, j + u, K);
+                pair_j<PREC, P, FORCE, POT, MASK>(ib, a, x[j + u], y[j + u], z[j + u], UNI ? 1.0 : q[j + u], eps2,
+                                                  j + u, K);
         }
-        for (; j < je; ++j) pair_j<PREC, P, FORCE, POT, MASK>(ib, a, x[j], y[j], z[j], q[j], eps2, j, K);
-        tot.add(a);
+        for (; j < je; ++j) pair_j<PREC, P, FORCE, POT, MASK>(ib, a, x[j], y[j], z[j], UNI ? 1.0 : q[j], eps2, j, K);
+        if (UNI)
+            tot.add_scaled(a, qJ);
+        else
+            tot.add(a);
     }
+}
+
+// The j-split [j0, j1) of the wave at ibase: pairs before its own i-block,
+// the diagonal (self pair masked), and after.
+template <int PREC, int P, bool FORCE, bool POT, bool UNI>
+__device__ __forceinline__ void pair_split(const IBlock<P>& ib, Acc<P, FORCE, POT>& tot, int ibase, int j0, int j1,
+                                           const double* __restrict__ x, const double* __restrict__ y,
+                                           const double* __restrict__ z, const double* __restrict__ q,
+                                           double eps2, double qJ, const SeriesK& K) {
+    const int dlo = max(j0, ibase), dhi = min(j1, ibase + 64 * P);
+    pair_range<PREC, P, FORCE, POT, false, UNI>(ib, tot, j0, min(j1, ibase), x, y, z, q, eps2, qJ, K);
+    if (dlo < dhi) pair_range<PREC, P, FORCE, POT, true, UNI>(ib, tot, dlo, dhi, x, y, z, q, eps2, qJ, K);
+    pair_range<PREC, P, FORCE, POT, false, UNI>(ib, tot, max(j0, ibase + 64 * P), j1, x, y, z, q, eps2, qJ, K);
 }
 
 // part: [S][3][n] force partials (FORCE), ppot: [S][n] potential partials
@@ -138,10 +194,11 @@ __global__ void __launch_bounds__(256) k_pair(int n, int i0, int ni, const doubl
     Acc<P, FORCE, POT> tot;
     tot.zero();
     const SeriesK K;
-    const int dlo = max(j0, ibase), dhi = min(j1, ibase + 64 * P);
-    pair_range<PREC, P, FORCE, POT, false>(ib, tot, j0, min(j1, ibase), x, y, z, q, eps2, K);
-    if (dlo < dhi) pair_range<PREC, P, FORCE, POT, true>(ib, tot, dlo, dhi, x, y, z, q, eps2, K);
-    pair_range<PREC, P, FORCE, POT, false>(ib, tot, max(j0, ibase + 64 * P), j1, x, y, z, q, eps2, K);
+    double qJ;
+    if (range_charge(q, j0, j1, qJ))
+        pair_split<PREC, P, FORCE, POT, true>(ib, tot, ibase, j0, j1, x, y, z, q, eps2, qJ, K);
+    else
+        pair_split<PREC, P, FORCE, POT, false>(ib, tot, ibase, j0, j1, x, y, z, q, eps2, 1.0, K);
 
 #pragma unroll
     for (int p = 0; p < P; ++p) {

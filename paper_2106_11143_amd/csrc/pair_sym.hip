@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_sym_plan(int n, int IB, int JL
 
 static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
-static int64_t sym_tiles(int64_t n, int IB, int JL) {
+int64_t sym_tiles(int64_t n, int IB, int JL) {
     const int nI = (int)((n + IB - 1) / IB);
     int64_t T = 0;
     for (int I = 0; I < nI; ++I) T += sym_nseg((int)n, IB, JL, I);
@@ -64,10 +64,9 @@ static int64_t sym_tiles(int64_t n, int IB, int JL) {
 // Workspace carve-up: rowstart[nI+1] | tiles[T] | Pi[T][3][IB] | R[T][3][JL]
 size_t sym_ws_bytes(int64_t n, int p, int jl) {
     const int IB = 64 * p;
-    const int64_t nI = (n + IB - 1) / IB;
     const int64_t T = sym_tiles(n, IB, jl);
-    return al256(sizeof(int) * (nI + 1)) + al256(sizeof(int2) * (T + 1)) +
-           al256(sizeof(double) * 3 * IB * (T + 1)) + al256(sizeof(double) * 3 * (size_t)jl * (T + 1));
+    return sym_plan_bytes(n, IB, jl) + al256(sizeof(double) * 3 * IB * (T + 1)) +
+           al256(sizeof(double) * 3 * (size_t)jl * (T + 1));
 }
 
 template <int PREC, int P, int RED>
@@ -97,25 +96,39 @@ static bool go_sym_pr(int P, int red, int n, int JL, int64_t T, const double* x,
                : go_sym_p<PREC, 0>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st);
 }
 
+size_t sym_plan_bytes(int64_t n, int IB, int JL) {
+    const int64_t nI = (n + IB - 1) / IB;
+    return al256(sizeof(int) * (nI + 1)) + al256(sizeof(int2) * (sym_tiles(n, IB, JL) + 1));
+}
+
+cb_status sym_plan(int n, int IB, int JL, void* ws, SymPlan* out, hipStream_t st) {
+    const int nI = (n + IB - 1) / IB;
+    if (nI > kPlanMaxRows) return fail(CB_EINVAL, "sym_plan: n = %d is too large for the symmetric kernels", n);
+    out->T = sym_tiles(n, IB, JL);
+    char* base = static_cast<char*>(ws);
+    out->rowstart = reinterpret_cast<int*>(base);
+    base += al256(sizeof(int) * (nI + 1));
+    out->tiles = reinterpret_cast<int2*>(base);
+    out->bytes = sym_plan_bytes(n, IB, JL);
+    k_sym_plan<<<1, kPlanThreads, 0, st>>>(n, IB, JL, nI, out->rowstart, out->tiles);
+    return check_launch("k_sym_plan");
+}
+
 cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, const double* y, const double* z,
                           const double* q, double eps2, void* ws, double* F, hipStream_t st) {
     const int P = c.p, JL = c.splits, IB = 64 * P;
     if (!is_sym(c.algo) || !sym_cfg_ok(P, c.wg, JL)) return fail(CB_EINVAL, "launch_pair_sym: bad configuration");
     const int red = c.algo == ALGO_SYM_LDS ? 1 : 0;
-    const int nI = (n + IB - 1) / IB;
-    if (nI > kPlanMaxRows) return fail(CB_EINVAL, "launch_pair_sym: n = %d is too large for the symmetric kernel", n);
-    const int64_t T = sym_tiles(n, IB, JL);
-    char* base = static_cast<char*>(ws);
-    int* rowstart = reinterpret_cast<int*>(base);
-    base += al256(sizeof(int) * (nI + 1));
-    int2* tiles = reinterpret_cast<int2*>(base);
-    base += al256(sizeof(int2) * (T + 1));
+    SymPlan plan;
+    cb_status rc = sym_plan(n, IB, JL, ws, &plan, st);
+    if (rc) return rc;
+    const int64_t T = plan.T;
+    int* rowstart = plan.rowstart;
+    const int2* tiles = plan.tiles;
+    char* base = static_cast<char*>(ws) + plan.bytes;
     double* Pi = reinterpret_cast<double*>(base);
     base += al256(sizeof(double) * 3 * IB * (T + 1));
     double* R = reinterpret_cast<double*>(base);
-    k_sym_plan<<<1, kPlanThreads, 0, st>>>(n, IB, JL, nI, rowstart, tiles);
-    cb_status rc = check_launch("k_sym_plan");
-    if (rc) return rc;
     if (T > 0) {
         bool okk = false;
         switch (prec) {

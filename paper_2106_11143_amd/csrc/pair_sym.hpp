@@ -41,19 +41,22 @@ __device__ __forceinline__ double sym_s(double r2, double q, const SeriesK& K) {
     return s;
 }
 
-// Coordinates and charges of a group of 4 j's.  The j index is uniform over
-// the wave, so these are scalar loads into SGPRs (32 of them; two groups fit
-// beside the rest of the kernel's scalar registers, eight j's do not).
+// Coordinates (and charges, when WQ) of a group of 4 j's.  The j index is
+// uniform over the wave, so these are scalar loads into SGPRs (32 of them;
+// two groups fit beside the rest of the kernel's scalar registers, eight j's
+// do not).  Tiles of one charge on each side need no per-j charge (WQ false).
 constexpr int kGroupJ = 4;
 
-struct JGroup {
-    double x[kGroupJ], y[kGroupJ], z[kGroupJ], q[kGroupJ];
+template <bool WQ>
+struct JGroupT {
+    double x[kGroupJ], y[kGroupJ], z[kGroupJ], q[WQ ? kGroupJ : 1];
 };
+using JGroup = JGroupT<true>;
 
 // Loads j = jg + u for u < 4, with u clamped to last (last >= 0) so that a
 // partial group stays in bounds.
-template <bool CLAMP>
-__device__ __forceinline__ void load_group(JGroup& g, int jg, int last, const double* __restrict__ x,
+template <bool CLAMP, bool WQ>
+__device__ __forceinline__ void load_group(JGroupT<WQ>& g, int jg, int last, const double* __restrict__ x,
                                            const double* __restrict__ y, const double* __restrict__ z,
                                            const double* __restrict__ q) {
 #pragma unroll
@@ -62,8 +65,50 @@ __device__ __forceinline__ void load_group(JGroup& g, int jg, int last, const do
         g.x[u] = x[j];
         g.y[u] = y[j];
         g.z[u] = z[j];
-        g.q[u] = q[j];
+        if constexpr (WQ) g.q[u] = q[j];
     }
+}
+
+// Minimum and maximum of a and b over the wave (every lane gets them).
+__device__ __forceinline__ void wave_minmax(double& lo, double& hi) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o));
+        hi = fmax(hi, __shfl_xor(hi, o));
+    }
+}
+
+// Whether every ion of an i-block (the lane's P charges) and every ion of
+// the j range [j0, j1) carry one charge each, and those charges (qI, qJ):
+// the tile is then one of the paper's single-species N-body sub-problems
+// (section 2), and its pair loop needs no per-pair charge.  Wave-uniform.
+// A non-finite charge anywhere makes the answer false (the general loop then
+// carries it into the forces).
+template <int P>
+__device__ __forceinline__ bool tile_charges(const double (&qi)[P], const double* __restrict__ q, int j0, int j1,
+                                             double& qI, double& qJ) {
+    double ilo = qi[0], ihi = qi[0];
+    bool fin = __builtin_isfinite(qi[0]);
+#pragma unroll
+    for (int p = 1; p < P; ++p) {
+        ilo = fmin(ilo, qi[p]);
+        ihi = fmax(ihi, qi[p]);
+        fin = fin && __builtin_isfinite(qi[p]);
+    }
+    double jlo = qi[0], jhi = qi[0];  // any finite placeholder: j1 > j0 in every tile
+    if (j1 > j0) jlo = jhi = q[j0];
+    for (int j = j0 + (int)__lane_id(); j < j1; j += 64) {
+        const double v = q[j];
+        jlo = fmin(jlo, v);
+        jhi = fmax(jhi, v);
+        fin = fin && __builtin_isfinite(v);
+    }
+    wave_minmax(ilo, ihi);
+    wave_minmax(jlo, jhi);
+    const bool all_fin = __builtin_amdgcn_ballot_w64(!fin) == 0;
+    qI = ilo;
+    qJ = jlo;
+    return all_fin && ilo == ihi && jlo == jhi;
 }
 
 // The pairs of one group (only its first `live` j's when TAIL): i sums into
@@ -71,23 +116,28 @@ __device__ __forceinline__ void load_group(JGroup& g, int jg, int last, const do
 // per value to Rt[c][jg - j0 + u].
 // RED selects the wave reduction: 0 = cross-lane permutes and DPP, 1 = LDS
 // (red, one wave's buffer).
-template <int PREC, int P, int RED, bool TAIL>
-__device__ __forceinline__ void sym_group(const JGroup& jd, int jg, int live, int j0, int JL, double eps2,
+// UNI: a tile of one charge per side.  The pair term is then d r^-3 alone
+// (no charge load, no charge multiply); the i sums are scaled by qI qJ when
+// stored and the reactions by rscale = qI here, so that the partials hold
+// what the general loop stores.
+template <int PREC, int P, int RED, bool TAIL, bool UNI>
+__device__ __forceinline__ void sym_group(const JGroupT<!UNI>& jd, int jg, int live, int j0, int JL, double eps2,
                                           const double (&xi)[P], const double (&yi)[P], const double (&zi)[P],
                                           const double (&qi)[P], double (&ia)[P][3], const SeriesK& K,
-                                          double* __restrict__ Rt, double* __restrict__ red) {
+                                          double rscale, double* __restrict__ Rt, double* __restrict__ red) {
     double jv[3 * kGroupJ];  // this lane's share of each reaction: sum over its P ions of q_i d r^-3
 #pragma unroll
     for (int u = 0; u < kGroupJ; ++u) {
-        const double xj = jd.x[u], yj = jd.y[u], zj = jd.z[u], qj = jd.q[u];
+        const double xj = jd.x[u], yj = jd.y[u], zj = jd.z[u];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const double dx = xi[p] - xj, dy = yi[p] - yj, dz = zi[p] - zj;
             const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
-            double s = sym_s<PREC>(r2, qi[p], K);  // q_i r^-3
+            double s = sym_s<PREC>(r2, UNI ? 1.0 : qi[p], K);  // r^-3 (UNI) or q_i r^-3
             if (TAIL && u >= live) s = 0.0;
-            const double sq = s * qj;  // q_i q_j r^-3
+            double sq = s;
+            if constexpr (!UNI) sq = s * jd.q[u];  // q_i q_j r^-3
             ia[p][0] = __builtin_fma(dx, sq, ia[p][0]);
             ia[p][1] = __builtin_fma(dy, sq, ia[p][1]);
             ia[p][2] = __builtin_fma(dz, sq, ia[p][2]);
@@ -110,13 +160,16 @@ __device__ __forceinline__ void sym_group(const JGroup& jd, int jg, int live, in
         double o[3];
         reduce_scatter12(jv, o);
         const int g = lane >> 4, c = lane & 15;
-        if ((!TAIL || g < live) && c < 3)
-            Rt[(size_t)c * JL + (jg - j0) + g] = (c == 0) ? o[0] : ((c == 1) ? o[1] : o[2]);
+        if ((!TAIL || g < live) && c < 3) {
+            const double r = (c == 0) ? o[0] : ((c == 1) ? o[1] : o[2]);
+            Rt[(size_t)c * JL + (jg - j0) + g] = UNI ? r * rscale : r;
+        }
     } else {
         const double o = lds_reduce12(jv, red);
         const int v = lane >> 2;           // value 3 u + c of quad v (v < 12 stores)
         const int u = (v * 11) >> 5, c = v - 3 * u;  // v / 3 and v % 3 for v < 16
-        if ((lane & 3) == 0 && v < 12 && (!TAIL || u < live)) Rt[(size_t)c * JL + (jg - j0) + u] = o;
+        if ((lane & 3) == 0 && v < 12 && (!TAIL || u < live))
+            Rt[(size_t)c * JL + (jg - j0) + u] = UNI ? o * rscale : o;
     }
 }
 
@@ -127,28 +180,21 @@ constexpr int sym_waves() {
     return PREC == PREC_IEEE ? (P <= 4 ? 4 : (P <= 6 ? 3 : 2)) : (P <= 5 ? 4 : 3);
 }
 
-// Tile (row I, segment sg) of a run of n ions at x, y, z, q: i sums to
-// Pi[t][3][IB], reactions to R[t][3][JL].  red: the LDS reduction buffer.
-template <int PREC, int P, int RED>
-__device__ __forceinline__ void sym_tile(int n, const double* __restrict__ x, const double* __restrict__ y,
-                                         const double* __restrict__ z, const double* __restrict__ q, double eps2,
-                                         int JL, int I, int sg, int t, double* __restrict__ red,
-                                         double* __restrict__ Pi, double* __restrict__ R) {
+// The j loop of a tile over [j0, j1) and the store of its i sums (see
+// sym_tile); UNI: a tile of one charge per side, qI and qJ.
+template <int PREC, int P, int RED, bool UNI>
+__device__ __forceinline__ void sym_tile_body(const double* __restrict__ x, const double* __restrict__ y,
+                                              const double* __restrict__ z, const double* __restrict__ q,
+                                              double eps2, int JL, int j0, int j1, int t, const double (&xi)[P],
+                                              const double (&yi)[P], const double (&zi)[P], const double (&qi)[P],
+                                              double qI, double qJ, double* __restrict__ red,
+                                              double* __restrict__ Pi, double* __restrict__ R) {
     constexpr int IB = 64 * P;
     const int lane = threadIdx.x;
-    double xi[P], yi[P], zi[P], qi[P], ia[P][3];
+    double ia[P][3];
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const int i = I * IB + p * 64 + lane;  // rows with tiles are full blocks
-        xi[p] = x[i];
-        yi[p] = y[i];
-        zi[p] = z[i];
-        qi[p] = q[i];
-        ia[p][0] = ia[p][1] = ia[p][2] = 0.0;
-    }
+    for (int p = 0; p < P; ++p) ia[p][0] = ia[p][1] = ia[p][2] = 0.0;
     const SeriesK K;
-    const int j0 = (I + 1) * IB + sg * JL;
-    const int j1 = min(n, j0 + JL);
     const int jfull = j0 + (j1 - j0) / kGroupJ * kGroupJ;
     double* Rt = R + (size_t)t * 3 * JL;
     // Full groups, software-pipelined: the next group's j data is requested
@@ -156,27 +202,57 @@ __device__ __forceinline__ void sym_tile(int n, const double* __restrict__ x, co
     // arithmetic (the last group re-requests itself).
     int jg = j0;
     if (jg < jfull) {
-        JGroup cur;
+        JGroupT<!UNI> cur;
         load_group<false>(cur, jg, 0, x, y, z, q);
         for (; jg < jfull; jg += kGroupJ) {
-            JGroup nxt;
+            JGroupT<!UNI> nxt;
             const int jn = jg + kGroupJ;
             load_group<false>(nxt, jn < jfull ? jn : jg, 0, x, y, z, q);
             __builtin_amdgcn_sched_barrier(0);  // keep the requests ahead of the arithmetic
-            sym_group<PREC, P, RED, false>(cur, jg, kGroupJ, j0, JL, eps2, xi, yi, zi, qi, ia, K, Rt, red);
+            sym_group<PREC, P, RED, false, UNI>(cur, jg, kGroupJ, j0, JL, eps2, xi, yi, zi, qi, ia, K, qI, Rt, red);
             cur = nxt;
         }
     }
     if (jg < j1) {  // the last, partial group: j's from j1 on are masked
-        JGroup tail;
+        JGroupT<!UNI> tail;
         load_group<true>(tail, jg, j1 - jg - 1, x, y, z, q);
-        sym_group<PREC, P, RED, true>(tail, jg, j1 - jg, j0, JL, eps2, xi, yi, zi, qi, ia, K, Rt, red);
+        sym_group<PREC, P, RED, true, UNI>(tail, jg, j1 - jg, j0, JL, eps2, xi, yi, zi, qi, ia, K, qI, Rt, red);
     }
+    const double sc = UNI ? qI * qJ : 1.0;
     double* Pt = Pi + (size_t)t * 3 * IB;
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Pt[(size_t)c * IB + p * 64 + lane] = ia[p][c];
+        for (int c = 0; c < 3; ++c) Pt[(size_t)c * IB + p * 64 + lane] = UNI ? sc * ia[p][c] : ia[p][c];
+}
+
+// Tile (row I, segment sg) of a run of n ions at x, y, z, q: i sums to
+// Pi[t][3][IB], reactions to R[t][3][JL].  red: the LDS reduction buffer.
+// A tile whose i-block and j-segment each hold ions of one charge (ions
+// grouped by species) takes the charge-free pair loop.
+template <int PREC, int P, int RED>
+__device__ __forceinline__ void sym_tile(int n, const double* __restrict__ x, const double* __restrict__ y,
+                                         const double* __restrict__ z, const double* __restrict__ q, double eps2,
+                                         int JL, int I, int sg, int t, double* __restrict__ red,
+                                         double* __restrict__ Pi, double* __restrict__ R) {
+    constexpr int IB = 64 * P;
+    const int lane = threadIdx.x;
+    double xi[P], yi[P], zi[P], qi[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int i = I * IB + p * 64 + lane;  // rows with tiles are full blocks
+        xi[p] = x[i];
+        yi[p] = y[i];
+        zi[p] = z[i];
+        qi[p] = q[i];
+    }
+    const int j0 = (I + 1) * IB + sg * JL;
+    const int j1 = min(n, j0 + JL);
+    double qI, qJ;
+    if (tile_charges<P>(qi, q, j0, j1, qI, qJ))
+        sym_tile_body<PREC, P, RED, true>(x, y, z, q, eps2, JL, j0, j1, t, xi, yi, zi, qi, qI, qJ, red, Pi, R);
+    else
+        sym_tile_body<PREC, P, RED, false>(x, y, z, q, eps2, JL, j0, j1, t, xi, yi, zi, qi, 1.0, 1.0, red, Pi, R);
 }
 
 template <int PREC, int P, int RED>

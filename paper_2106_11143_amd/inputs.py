@@ -166,6 +166,20 @@ def crystal8192(n: int = 8192, seed: int | None = None) -> dict:
                  trap=trap, dt=1e-9, nsteps=2000, checkpoint_every=50, t0=0.0, eps2=0.0)
 
 
+def group_by_charge(d: dict) -> dict:
+    """The same ions relabelled so that equal charges are contiguous (a
+    stable sort by charge; for cloud100k the +2e ions come last): the same
+    physical system, ordered as the paper's split of species into separate
+    N-body sub-problems (section 2).  perm: grouped ion k is ion perm[k] of d."""
+    perm = np.argsort(d["q"], kind="stable")
+    out = dict(d)
+    for k in ("x", "y", "z", "vx", "vy", "vz", "q", "m"):
+        out[k] = np.ascontiguousarray(d[k][perm])
+    out["perm"] = perm
+    out["name"] = d.get("name", "") + "_grouped"
+    return out
+
+
 WORKLOADS = {1: cloud1024, 2: rf32768, 3: cloud100k, 4: kz512, 5: crystal8192}
 
 

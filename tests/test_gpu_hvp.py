@@ -52,6 +52,51 @@ def test_hvp_matches_oracle(api, oracle, n, nvec, with_trap):
         assert err.max() <= tol
 
 
+HVP_SYM_SHAPES = [(1, 64), (2, 128), (2, 512), (4, 256), (1, 256), (4, 64)]
+HVP_SIZES = [2, 65, 129, 130, 257, 1000, 2049, 4097]
+
+
+@pytest.mark.parametrize("p,jl", HVP_SYM_SHAPES)
+def test_hvp_symmetric_ragged_sizes(api, oracle, p, jl):
+    """The Newton's-third-law HVP (each unordered pair once, reactions summed
+    over the wave): i-blocks of 64 p, j-segments of jl, ragged blocks and
+    segments, 1, 3 and 8 vectors (passes of 4, 2 and 1), mixed charges and
+    ions grouped by species, with and without the trap term; every ion of
+    every vector against the oracle."""
+    from _gpu_util import dev, host
+    for k, n in enumerate(HVP_SIZES):
+        g = np.random.Generator(np.random.PCG64(700 + n))
+        pos = g.normal(0.0, 20e-6, size=(3, n))
+        if k % 2:
+            q = E * g.choice([1.0, 2.0, -1.0], size=n)
+        else:
+            q = np.full(n, E)
+            q[int(0.6 * n):] = 2.0 * E
+        nvec = (1, 3, 8)[k % 3]
+        v = g.normal(size=(nvec, 3, n))
+        m = np.full(n, M40)
+        trap = inputs.rf_trap(0.02, 0.3, 10e6, 0.1e6, phase=0.4) if k % 2 == 0 else None
+        eps2 = (1e-7) ** 2 if n % 2 else 0.0
+        ref = oracle.hvp(*pos, q, v, m=m if trap else None, trap=trap, t=1.3e-8, eps2=eps2)
+        for prec, tol in (("fp64", 1e-12), ("mixed", 1e-8)):
+            api.set_config("hvp", n, prec, p=p, wg=4, splits=jl, algo=2)
+            try:
+                hv = host(api.coulomb_hvp(dev(pos[0]), dev(pos[1]), dev(pos[2]), dev(q), dev(v),
+                                          dev(m) if trap else None, trap, 1.3e-8, eps2=eps2, prec=prec))
+            finally:
+                api.reset_config("hvp", n, prec)
+            err = np.linalg.norm(hv - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            assert err.max() <= tol, (p, jl, n, nvec, prec, err.max())
+    assert api.poll_flags() == 0
+    api.clear_workspace_cache()
+
+
+def test_hvp_default_launch_is_newtons_third_law_at_8192(api):
+    cfg = api.get_config("hvp", 8192, "fp64")
+    assert (cfg["algo"], cfg["p"], cfg["splits"]) == (2, 2, 128)
+    assert api.get_config("hvp", 4095, "fp64")["algo"] == 0
+
+
 def test_hvp_exact_identities(api, oracle):
     from _gpu_util import dev, host
     pos, q = _cloud(2000, 5, charges=(1.0, 2.0))
