@@ -153,6 +153,24 @@ cb_status coulomb_forces(int64_t n, const double* x, const double* y, const doub
                          double eps2, int32_t prec, double* fx, double* fy, double* fz,
                          void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * coulomb_forces without a workspace argument.  Same inputs, outputs,
+ * precisions and errors as coulomb_forces; the partial sums live in a static
+ * 64 MiB device array that the library holds on each GPU it runs on until the
+ * process ends, so this call allocates nothing (no hipMalloc, no hipFree, no
+ * allocating library routine).  n at most 2796202 (64 MiB over 24 bytes per
+ * ion); larger n returns CB_ENOWS.  The configured Newton's-third-law stage
+ * runs when its tiles fit in the array (up to about 32768 ions: the result
+ * is then bitwise that of coulomb_forces), otherwise the all-pairs kernel
+ * with as many j-splits as fit (the same forces up to summation order).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (other streams, other threads) race and give undefined results;
+ * calls ordered on one stream are safe.  Nothing in the array needs to start
+ * at zero: each call overwrites what it reads. */
+cb_status coulomb_forces_noalloc(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                                 double eps2, int32_t prec, double* fx, double* fy, double* fz, void* stream);
+
 /* Forces (N) on the ions i0 .. i1-1 only, from all n ions (the same sum as
  * coulomb_forces, eq. (1) and the section 3 double loop, restricted to a
  * contiguous range of i): the share of one GPU when a force evaluation is

@@ -28,7 +28,7 @@ CB_INIT_ACCEL = 1
 CB_ADJ_FINAL = 1
 
 EXPORTS = ("cb_workspace_size", "coulomb_forces", "coulomb_forces_range", "coulomb_pair_stage", "coulomb_energy",
-           "coulomb_trap_grad", "cb_trap_k", "md_step", "md_run", "coulomb_hvp", "md_adjoint_step", "cb_poll_flags",
+           "coulomb_trap_grad", "cb_trap_k", "coulomb_forces_noalloc", "md_step", "md_run", "coulomb_hvp", "md_adjoint_step", "cb_poll_flags",
            "cb_last_error", "cb_autotune", "cb_load_tuning", "cb_get_config", "cb_set_config")
 
 
@@ -76,6 +76,7 @@ def lib() -> C.CDLL:
                 L.cb_workspace_size.argtypes = [i32, i64, i32, i32, i32]
                 L.cb_workspace_size.restype = sz
                 L.coulomb_forces.argtypes = [i64, _P, _P, _P, _P, d, i32, _P, _P, _P, _P, sz, _P]
+                L.coulomb_forces_noalloc.argtypes = [i64, _P, _P, _P, _P, d, i32, _P, _P, _P, _P]
                 L.coulomb_forces_range.argtypes = [i64, i64, i64, _P, _P, _P, _P, d, i32, _P, _P, _P, _P, sz, _P]
                 L.coulomb_energy.argtypes = [i64, _P, _P, _P, _P, d, i32, _P, _P, sz, _P]
                 L.coulomb_trap_grad.argtypes = [i64, _P, _P, _P, _P, _P, C.POINTER(Trap), d, d, i32, _P, _P, _P, _P,
@@ -185,6 +186,19 @@ def coulomb_forces(x, y, z, q, eps2: float = 0.0, prec="fp64", out=None):
     _check(lib().coulomb_forces(n, x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(), float(eps2), _prec(prec),
                                 fx.data_ptr(), fy.data_ptr(), fz.data_ptr(), ws.data_ptr(), ws.numel(), _stream()),
            "coulomb_forces")
+    return fx, fy, fz
+
+
+def coulomb_forces_noalloc(x, y, z, q, eps2: float = 0.0, prec="fp64", out=None):
+    """Forces (N) on every ion without a workspace (the library's static
+    per-GPU scratch); returns (fx, fy, fz).  Pass `out` to allocate nothing."""
+    _dev_f64(x, y, z, q)
+    n = x.numel()
+    fx, fy, fz = out if out is not None else (torch.empty_like(x), torch.empty_like(x), torch.empty_like(x))
+    _dev_f64(fx, fy, fz)
+    _check(lib().coulomb_forces_noalloc(n, x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(), float(eps2),
+                                        _prec(prec), fx.data_ptr(), fy.data_ptr(), fz.data_ptr(), _stream()),
+           "coulomb_forces_noalloc")
     return fx, fy, fz
 
 

@@ -44,18 +44,19 @@ cb_status check_launch(const char* what) {
     return CB_OK;
 }
 
+// Device address of this GPU's flag word, looked up once per device (a fixed
+// table, so that no call allocates host memory for it).
 unsigned* flags_ptr() {
     static std::mutex mu;
-    static std::map<int, unsigned*> per_dev;
+    static unsigned* per_dev[kMaxDevices];
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
     std::lock_guard<std::mutex> lk(mu);
-    auto it = per_dev.find(dev);
-    if (it != per_dev.end()) return it->second;
+    if (per_dev[dev]) return per_dev[dev];
     void* p = nullptr;
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_cb_flags)) != hipSuccess) return nullptr;
     per_dev[dev] = static_cast<unsigned*>(p);
-    return static_cast<unsigned*>(p);
+    return per_dev[dev];
 }
 
 // ------------------------------------------------------- configurations

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "internal.hpp"
 #include "step_kernels.hpp"
@@ -77,6 +78,45 @@ static cb_status force_stage(int op, int prec, int64_t n, const double* x, const
     *S_out = pr.S;
     *prescaled = false;
     return launch_pair(prec, pr.cfg, true, false, (int)n, x, y, z, q, eps2, pr.jlen, part, nullptr, st);
+}
+
+// ------------------------------------------- allocation-free forces
+// coulomb_forces_noalloc keeps its partial sums in this array instead of a
+// caller's workspace.  Each GPU the library runs on holds its own copy (the
+// code object's static device memory) until the process ends.  In host code
+// `scratch` names a host-side stand-in: the device address comes from
+// scratch_addr() alone.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int64_t kNoallocMaxN = (int64_t)(kScratchBytes / (3 * sizeof(double)));  // one j-split of [3][n]
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of the current GPU's scratch array: looked up with
+// hipGetSymbolAddress on the first call on each device (with that device
+// current) and kept in a fixed per-device table.
+static void* scratch_addr(cb_status* rc) {
+    static std::mutex mu;
+    static void* per_dev[kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *rc = fail(CB_EHIP, "coulomb_forces_noalloc: no current device");
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        *rc = fail(CB_EUNSUPPORTED, "coulomb_forces_noalloc: device %d beyond the %d the library tracks", dev,
+                   kMaxDevices);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!per_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *rc = fail(CB_EHIP, "coulomb_forces_noalloc: scratch symbol lookup failed: %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        per_dev[dev] = p;
+    }
+    return per_dev[dev];
 }
 
 // Single-run velocity-Verlet driver shared by md_step and md_run.
@@ -245,6 +285,63 @@ cb_status coulomb_forces(int64_t n, const double* x, const double* y, const doub
     E.mode = EPI_FORCES | (prescaled ? EPI_PRESCALED : 0u);
     E.flags = flags_ptr();
     if (!E.flags) return fail(CB_EHIP, "coulomb_forces: device flag symbol not found");
+    k_epilogue<<<(int)((n + kEpiThreads - 1) / kEpiThreads), kEpiThreads, 0, st>>>(E);
+    if ((rc = check_launch("k_epilogue"))) return rc;
+    return ok();
+}
+
+cb_status coulomb_forces_noalloc(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                                 double eps2, int32_t prec, double* fx, double* fy, double* fz, void* stream) {
+    if (n < 1) return fail(CB_EINVAL, "coulomb_forces_noalloc: n = %lld < 1", (long long)n);
+    if (n > kNoallocMaxN)
+        return fail(CB_ENOWS, "coulomb_forces_noalloc: n = %lld exceeds the %lld ions its %zu-byte static scratch holds",
+                    (long long)n, (long long)kNoallocMaxN, kScratchBytes);
+    if (prec < CB_FP64 || prec > CB_MIXED_F32D) return fail(CB_EINVAL, "coulomb_forces_noalloc: unknown precision %d", prec);
+    if (!(eps2 >= 0.0) || !std::isfinite(eps2)) return fail(CB_EINVAL, "coulomb_forces_noalloc: eps2 must be finite and >= 0");
+    if (!x || !y || !z || !q || !fx || !fy || !fz) return fail(CB_EINVAL, "coulomb_forces_noalloc: NULL array");
+    const void* in[4] = {x, y, z, q};
+    const void* out[3] = {fx, fy, fz};
+    for (auto o : out)
+        for (auto i : in)
+            if (overlaps(o, i, n)) return fail(CB_EINVAL, "coulomb_forces_noalloc: output aliases an input");
+    if (overlaps(fx, fy, n) || overlaps(fx, fz, n) || overlaps(fy, fz, n))
+        return fail(CB_EINVAL, "coulomb_forces_noalloc: outputs overlap");
+    cb_status rc = CB_OK;
+    void* ws = scratch_addr(&rc);
+    if (!ws) return rc;
+    unsigned* fl = flags_ptr();
+    if (!fl) return fail(CB_EHIP, "coulomb_forces_noalloc: device flag symbol not found");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double* part = static_cast<double*>(ws);
+    // The configured Newton's-third-law stage when its tiles fit beside the
+    // finished forces (bitwise the result of coulomb_forces), else the direct
+    // kernel with no more j-splits than the scratch holds.
+    const LaunchCfg cfg = get_cfg(CB_OP_FORCES, n, prec);
+    const size_t fbytes = al256(sizeof(double) * 3 * (size_t)n);
+    const bool sym = is_sym(cfg.algo) && n <= kSymMaxN && prec != CB_MIXED_F32D &&
+                     fbytes + sym_ws_bytes(n, cfg.p, cfg.splits) <= kScratchBytes;
+    int S = 1;
+    if (sym) {
+        if ((rc = launch_pair_sym(prec, cfg, (int)n, x, y, z, q, eps2, static_cast<char*>(ws) + fbytes, part, st)))
+            return rc;
+    } else {
+        LaunchCfg c = cfg.algo == ALGO_DIRECT ? cfg : default_cfg(CB_OP_ENERGY, n, prec);
+        const int64_t smax = (int64_t)(kScratchBytes / (3 * sizeof(double) * (size_t)n));
+        c.splits = (int)std::max<int64_t>(1, std::min<int64_t>(c.splits, smax));
+        const int jlen = split_len(n, c.splits);
+        S = n_splits(n, jlen);  // <= c.splits, so [S][3][n] fits
+        if ((rc = launch_pair(prec, c, true, false, (int)n, x, y, z, q, eps2, jlen, part, nullptr, st))) return rc;
+    }
+    EpiParams E{};
+    E.n = (int)n;
+    E.S = S;
+    E.part = part;
+    E.q = q;
+    E.fx = fx;
+    E.fy = fy;
+    E.fz = fz;
+    E.mode = EPI_FORCES | (sym ? EPI_PRESCALED : 0u);
+    E.flags = fl;
     k_epilogue<<<(int)((n + kEpiThreads - 1) / kEpiThreads), kEpiThreads, 0, st>>>(E);
     if ((rc = check_launch("k_epilogue"))) return rc;
     return ok();

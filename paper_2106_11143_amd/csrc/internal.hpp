@@ -18,6 +18,7 @@ constexpr int kBatchWG = 512;        // threads per workgroup of the persistent 
 constexpr int kBatchP = 4;           // ions per thread and register group in that kernel
 constexpr int kEpiBlock = 256;       // threads per element-wise block
 constexpr int64_t kSymMaxN = int64_t(1) << 18;  // largest n for the symmetric kernel (partials grow as n^2)
+constexpr int kMaxDevices = 64;      // GPUs per process the per-device symbol tables hold
 
 // ALGO_SYM and ALGO_SYM_LDS differ only in how the per-j reactions are summed
 // over the wave (cross-lane permutes and DPP, or LDS).

@@ -315,3 +315,20 @@ def test_trap_grad_argument_errors(api):
                 None) == api.CB_EINVAL
     assert call(10, x, y, z, q, m, C.byref(tr), 0.0, 0.0, 4, g1, g2, g3, u, _ws(), big, None) == api.CB_EUNSUPPORTED
     assert call(10, x, y, z, q, m, C.byref(tr), 0.0, 0.0, 0, g1, g2, g3, u, _ws(), 100, None) == api.CB_ENOWS
+
+
+def test_noalloc_argument_errors(api):
+    """coulomb_forces_noalloc validates before it touches a device: sizes
+    beyond its static scratch, bad n, precision, eps2, NULL and aliasing."""
+    L = api.lib()
+    P = C.c_void_p(1 << 21)
+    o1, o2, o3 = C.c_void_p(1 << 23), C.c_void_p(1 << 24), C.c_void_p(1 << 25)
+    assert L.coulomb_forces_noalloc(2796203, P, P, P, P, 0.0, 0, o1, o2, o3, None) == api.CB_ENOWS
+    assert "scratch" in api.last_error()
+    assert L.coulomb_forces_noalloc(0, P, P, P, P, 0.0, 0, o1, o2, o3, None) == api.CB_EINVAL
+    assert L.coulomb_forces_noalloc(10, P, P, P, P, 0.0, 9, o1, o2, o3, None) == api.CB_EINVAL
+    assert L.coulomb_forces_noalloc(10, P, P, P, P, -1.0, 0, o1, o2, o3, None) == api.CB_EINVAL
+    assert L.coulomb_forces_noalloc(10, None, P, P, P, 0.0, 0, o1, o2, o3, None) == api.CB_EINVAL
+    assert L.coulomb_forces_noalloc(10, o1, P, P, P, 0.0, 0, o1, o2, o3, None) == api.CB_EINVAL
+    assert "alias" in api.last_error()
+    assert L.coulomb_forces_noalloc(10, P, P, P, P, 0.0, 0, o1, o1, o3, None) == api.CB_EINVAL
