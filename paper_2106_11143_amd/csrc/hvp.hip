@@ -105,7 +105,7 @@ static bool go_hvp_fin(int nv, unsigned nb, int n, int IB, int JL, int lgJL, con
                        const double* z, const double* q, const double* v, double eps2, const int* rowstart,
                        const double* Pi, const double* R, const double* m, TrapK k, double* hv, unsigned* fl,
                        hipStream_t st) {
-    const dim3 g(nb), b(64 * kFinishParts);
+    const dim3 g(nb, nv), b(64 * kFinishParts);
     switch (nv) {
         case 1: k_hvp_sym_finish<PREC, 1><<<g, b, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, v, eps2, rowstart, Pi, R, m, k, hv, fl); return true;
         case 2: k_hvp_sym_finish<PREC, 2><<<g, b, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, v, eps2, rowstart, Pi, R, m, k, hv, fl); return true;

@@ -212,38 +212,34 @@ __global__ void __launch_bounds__(64, (hvp_sym_waves<P, NV>())) k_hvp_sym(int n,
         hvp_sym_body<PREC, P, NV, false>(J, eps2, JL, j0, j1, t, xi, yi, zi, qi, vi, 1.0, 1.0, red, Pi, R);
 }
 
-// Per ion k (64 ions per workgroup, kFinishParts waves each taking a fixed
-// share of every sum): the pairs inside k's own i-block (direct, self pair
-// skipped), k's i sums over the tiles of its row, minus q_k times its
-// reactions from the rows above; hv[b][c][k] = k_C (those) + m_k kk_c v_k (m
-// may be NULL).  The waves' shares are added in wave order (deterministic).
+// Per ion k and vector b = blockIdx.y (64 ions per workgroup, kFinishParts
+// waves each taking a fixed share of every sum): the pairs inside k's own
+// i-block (direct, self pair skipped), k's i sums over the tiles of its row,
+// minus q_k times its reactions from the rows above; hv[b][c][k] = k_C (those)
+// + m_k kk_c v_k (m may be NULL).  The waves' shares are added in wave order
+// (deterministic).  One vector per workgroup spreads the partial reads of a
+// pass over NV times the workgroups.
 template <int PREC, int NV>
 __global__ void __launch_bounds__(64 * kFinishParts) k_hvp_sym_finish(
     int n, int IB, int JL, int lgJL, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ q, const double* __restrict__ v, double eps2,
     const int* __restrict__ rowstart, const double* __restrict__ Pi, const double* __restrict__ R,
     const double* __restrict__ m, TrapK kk, double* __restrict__ hv, unsigned* flags) {
-    __shared__ double red[kFinishParts][3 * NV][64];
+    __shared__ double red[kFinishParts][3][64];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int b = blockIdx.y;
     const int k0 = blockIdx.x * 64;
     const int k = k0 + lane;
     const int kc = min(k, n - 1);
     const int Ik = k0 / IB;
     const int b0 = Ik * IB, b1 = min(n, b0 + IB);
     const double xk = x[kc], yk = y[kc], zk = z[kc], qk = q[kc];
-    double vk[NV][3];
-#pragma unroll
-    for (int b = 0; b < NV; ++b)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) vk[b][c] = v[(size_t)(b * 3 + c) * n + kc];
+    const double* vb = v + (size_t)b * 3 * n;
+    const double vk[3] = {vb[kc], vb[n + kc], vb[2 * (size_t)n + kc]};
     const SeriesK K;
     int lo, hi;
-    double d[NV][3], e[NV][3], s[NV][3];
-#pragma unroll
-    for (int b = 0; b < NV; ++b)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) d[b][c] = e[b][c] = s[b][c] = 0.0;
+    double d[3] = {0.0, 0.0, 0.0}, e[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
     share(b0, b1, w, lo, hi);
     for (int j = lo; j < hi; ++j) {  // q_j T_kj over k's own block
         const double dx = xk - x[j], dy = yk - y[j], dz = zk - z[j];
@@ -251,56 +247,47 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_hvp_sym_finish(
         double s3, s5;
         hvp_scales<PREC>(r2, q[j], K, s3, s5);
         if (j == kc) s3 = s5 = 0.0;
-#pragma unroll
-        for (int b = 0; b < NV; ++b) {
-            const double ux = vk[b][0] - v[(size_t)(b * 3 + 0) * n + j];
-            const double uy = vk[b][1] - v[(size_t)(b * 3 + 1) * n + j];
-            const double uz = vk[b][2] - v[(size_t)(b * 3 + 2) * n + j];
-            const double c = __builtin_fma(dx, ux, __builtin_fma(dy, uy, dz * uz)) * s5;
-            d[b][0] += __builtin_fma(dx, c, -(ux * s3));
-            d[b][1] += __builtin_fma(dy, c, -(uy * s3));
-            d[b][2] += __builtin_fma(dz, c, -(uz * s3));
-        }
+        const double ux = vk[0] - vb[j], uy = vk[1] - vb[n + j], uz = vk[2] - vb[2 * (size_t)n + j];
+        const double c = __builtin_fma(dx, ux, __builtin_fma(dy, uy, dz * uz)) * s5;
+        d[0] += __builtin_fma(dx, c, -(ux * s3));
+        d[1] += __builtin_fma(dy, c, -(uy * s3));
+        d[2] += __builtin_fma(dz, c, -(uz * s3));
     }
     const int off = kc - b0;
     share(rowstart[Ik], rowstart[Ik + 1], w, lo, hi);
+#pragma unroll 4
     for (int t = lo; t < hi; ++t) {  // k's i sums over the tiles of its row
-        const double* Pt = Pi + (size_t)t * NV * 3 * IB + off;
-#pragma unroll
-        for (int b = 0; b < NV; ++b)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) s[b][c] += Pt[(size_t)(b * 3 + c) * IB];
+        const double* Pt = Pi + ((size_t)t * NV + b) * 3 * IB + off;
+        s[0] += Pt[0];
+        s[1] += Pt[IB];
+        s[2] += Pt[2 * IB];
     }
     share(0, Ik, w, lo, hi);
+#pragma unroll 4
     for (int I = lo; I < hi; ++I) {  // k's reactions from the rows above
         const int rel = kc - (I + 1) * IB;
         const int sI = rel >> lgJL;
-        const double* Rt = R + (size_t)(rowstart[I] + sI) * NV * 3 * JL + (rel - (sI << lgJL));
-#pragma unroll
-        for (int b = 0; b < NV; ++b)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) e[b][c] += Rt[(size_t)(b * 3 + c) * JL];
+        const double* Rt = R + ((size_t)(rowstart[I] + sI) * NV + b) * 3 * JL + (rel - (sI << lgJL));
+        e[0] += Rt[0];
+        e[1] += Rt[JL];
+        e[2] += Rt[2 * JL];
     }
 #pragma unroll
-    for (int b = 0; b < NV; ++b)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) red[w][b * 3 + c][lane] = s[b][c] + qk * (d[b][c] - e[b][c]);
+    for (int c = 0; c < 3; ++c) red[w][c][lane] = s[c] + qk * (d[c] - e[c]);
     __syncthreads();
     if (w != 0 || k >= n) return;
     const double kc3[3] = {kk.kx, kk.ky, kk.kz};
     const double mk = m ? m[k] : 0.0;
     bool ok = true;
 #pragma unroll
-    for (int b = 0; b < NV; ++b)
+    for (int c = 0; c < 3; ++c) {
+        double a = red[0][c][lane];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double a = red[0][b * 3 + c][lane];
-#pragma unroll
-            for (int u = 1; u < kFinishParts; ++u) a += red[u][b * 3 + c][lane];
-            const double h = __builtin_fma(mk * kc3[c], vk[b][c], kCoulomb * a);
-            hv[(size_t)(b * 3 + c) * n + k] = h;
-            ok = ok && __builtin_isfinite(h);
-        }
+        for (int u = 1; u < kFinishParts; ++u) a += red[u][c][lane];
+        const double h = __builtin_fma(mk * kc3[c], vk[c], kCoulomb * a);
+        hv[((size_t)b * 3 + c) * n + k] = h;
+        ok = ok && __builtin_isfinite(h);
+    }
     if (!ok) atomicOr(flags, 1u);
 }
 

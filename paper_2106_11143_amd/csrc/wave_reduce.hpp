@@ -1,6 +1,6 @@
 // Wave-wide reduce-scatter of 12 doubles per lane on gfx950 (wave64), two
 // ways: through cross-lane permutes and DPP (reduce_scatter12), or through LDS
-// (lds_reduce12).
+// (lds_reduce12, for workgroups of one wave).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -69,22 +69,32 @@ __device__ __forceinline__ void reduce_scatter12(const double (&v)[12], double (
 }
 
 // The same sums through LDS, for a workgroup of one wave.  Every lane writes
-// its 12 values value-major into red (row v of kRedStride doubles holds value
-// v of lanes 0-63); then lane L reads value v = min(L / 4, 11) of lanes
-// 16 (L % 4) .. 16 (L % 4) + 15 as eight 16-byte loads, adds them in a fixed
-// tree, and the four lanes of each quad add their partial sums by DPP.  The
-// result, the sum over all 64 lanes of value v, is returned in every lane of
-// quad v (lanes 48-63 repeat value 11).  red holds 12 kRedStride doubles,
-// 16-byte aligned; the row stride puts the 12 rows in different banks.
-constexpr int kRedStride = 66;
+// its 12 values value-major into red: row k of kRedStride doubles holds value
+// k of lanes 0-63, each run of 16 lanes followed by 2 doubles of padding.
+// Lane L then reads value vi = min(L / 4, 11) of lanes 16 g .. 16 g + 15
+// (g = L % 4, one contiguous run) as eight 16-byte loads, adds them in a
+// fixed tree, and the four lanes of each quad add their partial sums by DPP.
+// The result, the sum over all 64 lanes of value vi, is returned in every
+// lane of quad vi (lanes 48-63 repeat value 11).  The padding puts the four
+// runs a quad reads 144 bytes apart (distinct banks) and the row stride of
+// 576 bytes puts neighbouring quads' rows half a bank cycle apart, so the
+// loads are free of bank conflicts.
+// One wave's LDS instructions are performed in issue order, so the reads see
+// the writes and the next call's writes follow these reads without a
+// barrier; the wavefront-scope fences only keep the compiler from moving the
+// accesses across each other.  red holds 12 kRedStride doubles, 16-byte
+// aligned, and is used by one wave only.
+constexpr int kRedStride = 72;
 
 __device__ __forceinline__ double lds_reduce12(const double (&v)[12], double* __restrict__ red) {
     const int lane = __lane_id();
+    const int wpos = lane + 2 * (lane >> 4);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) red[k * kRedStride + lane] = v[k];
-    __syncthreads();
+    for (int k = 0; k < 12; ++k) red[k * kRedStride + wpos] = v[k];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int vi = min(lane >> 2, 11);
-    const double2* src = reinterpret_cast<const double2*>(red + vi * kRedStride + (lane & 3) * 16);
+    const double2* src = reinterpret_cast<const double2*>(red + vi * kRedStride + (lane & 3) * 18);
     double2 a[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) a[k] = src[k];
@@ -94,7 +104,7 @@ __device__ __forceinline__ double lds_reduce12(const double (&v)[12], double* __
     double x = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     x += dpp_d<kDppQuadXor1>(x);
     x += dpp_d<kDppQuadXor2>(x);
-    __syncthreads();  // every lane has read before the next group overwrites red
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // these reads before the next call's writes
     return x;
 }
 
