@@ -330,6 +330,9 @@ cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]);
  * md_step, md_run; n <= 2^18): p in {2,3,4,5,6,8}, wg = j's per reduction
  * group = 4, splits = segment length in {256,512,1024,2048}.  Algorithm 3
  * (md_step, md_run; n <= 8192): p = 1, wg = 64, splits = j-parts in 1..32.
+ * For CB_OP_HVP and CB_OP_ADJOINT, algorithm 2 is the Newton's-third-law
+ * product: p in {1, 2, 4}, wg = the most vectors per pass in {1, 2, 4},
+ * splits = segment length in {64, 128, 256, 512}; n <= 131072 p.
  * For CB_OP_MD_ENSEMBLE (n = total ions): algorithm 0 with p = 4, wg = 512,
  * splits = 1 (the persistent kernel's fixed shape), or algorithm 2 with p in
  * {4, 8}, wg = 4, splits = JL in {256, 512}.

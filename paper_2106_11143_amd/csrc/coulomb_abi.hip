@@ -91,7 +91,7 @@ LaunchCfg default_cfg(int op, int64_t n, int prec) {
         c.splits = 256;
         return c;
     }
-    const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
+    const bool force_op = sym_op(op);
     if ((op == CB_OP_MD_STEP || op == CB_OP_MD_RUN) && n <= kSmallRunDefault) {
         // One launch per step: for a few hundred ions the two-launch step is
         // bound by the latency of its second launch (measured on MI355X with
@@ -109,23 +109,34 @@ LaunchCfg default_cfg(int op, int64_t n, int prec) {
         // summed through LDS.  Eight ions per lane amortise the per-j wave
         // reduction best; below 32768 ions smaller tiles keep enough of them
         // in flight; below 16384 the direct kernel is faster (measured on
-        // MI355X).
+        // MI355X).  The energy takes the same stage, with the potential as a
+        // fourth component of the sums.
         c.algo = ALGO_SYM_LDS;
         c.wg = kSymGroup;
         c.p = n >= 32768 ? 8 : (n >= 24576 ? 6 : 4);
         c.splits = n >= 32768 ? 512 : 256;
         return c;
     }
-    if (op == CB_OP_HVP && n >= kHvpSymMinN && n <= hvp_sym_max_n(2)) {
+    if ((op == CB_OP_HVP || op == CB_OP_ADJOINT) && n >= kHvpSymMinN && n <= hvp_sym_max_n(2)) {
         // Hessian-vector products by Newton's third law (hvp_sym.hpp): two
         // ions per lane (the four-vector pass keeps 24 vector components and
-        // 24 sums per lane) and short segments, for enough tiles at 8192 ions
+        // 24 sums per lane), up to four vectors per pass (wg), short segments
+        // for enough tiles at 8192 ions
         c.algo = ALGO_SYM_LDS;
-        c.wg = kSymGroup;
+        c.wg = 4;
         c.p = 2;
         c.splits = 128;
         return c;
     }
+    return direct_cfg(op, n, prec);
+}
+
+// The all-pairs kernel's default shape for op at n.
+LaunchCfg direct_cfg(int op, int64_t n, int prec) {
+    LaunchCfg c;
+    c.tuned = 0;
+    c.algo = ALGO_DIRECT;
+    (void)prec;
     c.wg = 64;
     c.p = 1;
     const int64_t waves = (n + 64 * c.p - 1) / (64 * c.p);
@@ -173,11 +184,12 @@ bool valid_cfg(int op, const LaunchCfg& c) {
     if (op == CB_OP_MD_ENSEMBLE)
         return (c.algo == ALGO_DIRECT && c.p == kBatchP && c.wg == kBatchWG && c.splits == 1) ||
                (c.algo == ALGO_SYM_LDS && c.wg == kSymGroup && ens_cfg_ok(c.p, c.splits));
-    const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
+    const bool force_op = sym_op(op);
     const bool hv_op = (op == CB_OP_HVP || op == CB_OP_ADJOINT);
     if (is_sym(c.algo))
         return (force_op && sym_cfg_ok(c.p, c.wg, c.splits)) ||
-               (hv_op && c.algo == ALGO_SYM_LDS && c.wg == kSymGroup && hvp_sym_cfg_ok(c.p, c.splits));
+               (hv_op && c.algo == ALGO_SYM_LDS && (c.wg == 1 || c.wg == 2 || c.wg == 4) &&
+                hvp_sym_cfg_ok(c.p, c.splits));
     if (c.algo != ALGO_DIRECT) return false;
     const bool p_ok = (op == CB_OP_HVP || op == CB_OP_ADJOINT) ? (c.p == 1 || c.p == 2)
                                                                  : (c.p == 1 || c.p == 2 || c.p == 4);
@@ -202,21 +214,31 @@ WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec) 
     const size_t nv = (size_t)std::max(1, (int)nvec);
     size_t off = 0;
     // the configuration whose Newton's-third-law partials the buffer must hold
-    // (coulomb_trap_grad's force stage follows the forces' configuration)
-    const int cfg_op = op == CB_OP_GRAD ? CB_OP_FORCES : op;
+    // (coulomb_trap_grad's force stage follows the forces' configuration, or
+    // the energy's when it also returns the energy: the larger of the two)
+    const int cfg_op = op == CB_OP_GRAD ? CB_OP_ENERGY : op;
+    // the tiles' pair energies too: energies, energy records, the gradient's energy
+    const bool pot = (op == CB_OP_ENERGY || op == CB_OP_MD_RUN || op == CB_OP_GRAD);
     if (op == CB_OP_GRAD) op = CB_OP_MD_STEP;  // the same buffers: force stage, potential partials, energy blocks
     const bool batched = (op == CB_OP_MD_RUN && nrun > 1);
     const bool hv = (op == CB_OP_HVP || op == CB_OP_ADJOINT);
     if (!batched) {
         L.part = off;
         size_t part = sizeof(double) * (size_t)kMaxSplits * 3 * (hv ? nv : 1) * N;
-        const bool force_op = (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN);
-        const LaunchCfg c = get_cfg(cfg_op, n, prec);
+        const bool force_op = sym_op(op);
+        LaunchCfg c = get_cfg(cfg_op, n, prec);
+        if (cfg_op == CB_OP_ENERGY) {  // coulomb_trap_grad: the forces' stage too
+            const LaunchCfg f = get_cfg(CB_OP_FORCES, n, prec);
+            if (is_sym(f.algo) && sym_cfg_ok(f.p, f.wg, f.splits) &&
+                (!is_sym(c.algo) || sym_ws_bytes(n, f.p, f.splits, true) > sym_ws_bytes(n, c.p, c.splits, true)))
+                c = f;
+        }
         if (force_op && n <= kSymMaxN && is_sym(c.algo) && sym_cfg_ok(c.p, c.wg, c.splits))
             // the configured symmetric stage: finished forces [3][n] then its tiles and partials
-            part = std::max(part, al(sizeof(double) * 3 * N) + sym_ws_bytes(n, c.p, c.splits));
-        if (hv && is_sym(c.algo) && hvp_sym_cfg_ok(c.p, c.splits))
-            part = std::max(part, hvp_sym_ws_bytes(n, c.p, c.splits));
+            part = std::max(part, al(sizeof(double) * 3 * N) + sym_ws_bytes(n, c.p, c.splits, pot));
+        if (hv && is_sym(c.algo) && hvp_sym_cfg_ok(c.p, c.splits))  // (the adjoint's product [3][n] first)
+            part = std::max(part, (op == CB_OP_ADJOINT ? al(sizeof(double) * 3 * N) : 0) +
+                                      hvp_sym_ws_bytes(n, c.p, c.splits));
         off += al(part);
         L.ppot = off;
         if (op == CB_OP_ENERGY || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN)

@@ -51,7 +51,7 @@ struct PairRun {
 static PairRun plan(int op, int64_t n, int prec) {
     PairRun r;
     r.cfg = get_cfg(op, n, prec);
-    if (r.cfg.algo != ALGO_DIRECT) r.cfg = default_cfg(CB_OP_ENERGY, n, prec);  // direct kernel needed
+    if (r.cfg.algo != ALGO_DIRECT) r.cfg = direct_cfg(CB_OP_ENERGY, n, prec);  // direct kernel needed
     r.jlen = split_len(n, r.cfg.splits);
     r.S = n_splits(n, r.jlen);
     return r;
@@ -59,25 +59,27 @@ static PairRun plan(int op, int64_t n, int prec) {
 
 static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
-// The force-only pair stage with the configured algorithm.  Direct: partial
-// sums [S][3][n] at ws+L.part (to be scaled by k_C q_i).  Symmetric: the
-// finished forces [3][n] at ws+L.part (S = 1, prescaled), its tiles and
-// partials after them.
+// The pair stage with the configured algorithm: forces, and the potential
+// sums too when pot.  Direct: partial sums [S][3][n] at ws+L.part (to be
+// scaled by k_C q_i) and [S][n] at ws+L.ppot.  Symmetric: the finished forces
+// [3][n] at ws+L.part (S = 1, prescaled), its tiles and partials after them,
+// and the potential sums [n] at ws+L.ppot (S = 1).
 static cb_status force_stage(int op, int prec, int64_t n, const double* x, const double* y, const double* z,
                              const double* q, double eps2, void* ws, const WsLayout& L, hipStream_t st, int* S_out,
-                             bool* prescaled) {
+                             bool* prescaled, bool pot = false) {
     const LaunchCfg cfg = get_cfg(op, n, prec);
     double* part = at(ws, L.part);
+    double* ppot = pot ? at(ws, L.ppot) : nullptr;
     if (is_sym(cfg.algo) && n <= kSymMaxN && prec != CB_MIXED_F32D) {
         *S_out = 1;
         *prescaled = true;
         void* tiles_ws = static_cast<char*>(ws) + L.part + al256(sizeof(double) * 3 * (size_t)n);
-        return launch_pair_sym(prec, cfg, (int)n, x, y, z, q, eps2, tiles_ws, part, st);
+        return launch_pair_sym(prec, cfg, (int)n, x, y, z, q, eps2, tiles_ws, part, st, ppot);
     }
     const PairRun pr = plan(op, n, prec);
     *S_out = pr.S;
     *prescaled = false;
-    return launch_pair(prec, pr.cfg, true, false, (int)n, x, y, z, q, eps2, pr.jlen, part, nullptr, st);
+    return launch_pair(prec, pr.cfg, true, pot, (int)n, x, y, z, q, eps2, pr.jlen, part, ppot, st);
 }
 
 // ------------------------------------------- allocation-free forces
@@ -182,13 +184,16 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
     };
 
     bool prescaled_now = false;
-    // Force (and potential) pair launch: the potential needs the direct kernel;
-    // forces alone use the configured algorithm.
+    // Force (and potential) pair launch with the configured algorithm.  A
+    // potential alone (an energy record of step 0 without CB_INIT_ACCEL) takes
+    // the symmetric stage too when it is configured (its forces unused), else
+    // the direct kernel's potential-only pass.
+    const bool sym_stage = is_sym(get_cfg(op, n, prec).algo) && n <= kSymMaxN;
     auto pairs = [&](bool force, bool pot) -> cb_status {
-        if (force && !pot) {
+        if (force || sym_stage) {
             int S = 0;
             bool pre = false;
-            cb_status r = force_stage(op, prec, n, s->x, s->y, s->z, q, eps2, ws, L, st, &S, &pre);
+            cb_status r = force_stage(op, prec, n, s->x, s->y, s->z, q, eps2, ws, L, st, &S, &pre, pot);
             E.S = S;
             prescaled_now = pre;
             return r;
@@ -204,13 +209,14 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
     }
     E.step = 0;
     E.mode = (init ? EPI_ACCEL : 0u) | (rec0 ? EPI_ENERGY : 0u) | (nsteps > 0 ? EPI_DRIFT : 0u);
-    if (prescaled_now) E.mode |= EPI_PRESCALED;
+    if (prescaled_now) E.mode |= EPI_PRESCALED | EPI_POT_SHARE;
     if (E.mode && (rc = epilogue(rec0 ? energies : nullptr))) return rc;
     for (int64_t k = 1; k <= nsteps; ++k) {
         const bool rec = rec0 && (k % every == 0);
         if ((rc = pairs(true, rec))) return rc;
         E.step = k;
-        E.mode = EPI_KICK | (rec ? EPI_ENERGY : 0u) | (k < nsteps ? EPI_DRIFT : 0u) | (prescaled_now ? EPI_PRESCALED : 0u);
+        E.mode = EPI_KICK | (rec ? EPI_ENERGY : 0u) | (k < nsteps ? EPI_DRIFT : 0u) |
+                 (prescaled_now ? EPI_PRESCALED | EPI_POT_SHARE : 0u);
         if ((rc = epilogue(rec ? energies + 4 * (k / every) : nullptr))) return rc;
     }
     if (pend) {
@@ -325,7 +331,7 @@ cb_status coulomb_forces_noalloc(int64_t n, const double* x, const double* y, co
         if ((rc = launch_pair_sym(prec, cfg, (int)n, x, y, z, q, eps2, static_cast<char*>(ws) + fbytes, part, st)))
             return rc;
     } else {
-        LaunchCfg c = cfg.algo == ALGO_DIRECT ? cfg : default_cfg(CB_OP_ENERGY, n, prec);
+        LaunchCfg c = cfg.algo == ALGO_DIRECT ? cfg : direct_cfg(CB_OP_ENERGY, n, prec);
         const int64_t smax = (int64_t)(kScratchBytes / (3 * sizeof(double) * (size_t)n));
         c.splits = (int)std::max<int64_t>(1, std::min<int64_t>(c.splits, smax));
         const int jlen = split_len(n, c.splits);
@@ -366,9 +372,18 @@ cb_status coulomb_forces_range(int64_t n, int64_t i0, int64_t i1, const double* 
     if (overlaps2(fx, ni, fy, ni) || overlaps2(fx, ni, fz, ni) || overlaps2(fy, ni, fz, ni))
         return fail(CB_EINVAL, "coulomb_forces_range: outputs overlap");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    // the direct kernel over the i-range; j-splits sized for the range's waves
+    // The direct kernel over the i-range.  Unless a direct configuration is
+    // set for the forces at this n, the range takes the whole launch's shape
+    // with its j-splits multiplied by n / ni, so that one GPU's share of a
+    // split evaluation fills the chip as the whole evaluation does; the
+    // range's partials [S][3][ni] fit the workspace while S ni <= 64 n.
     LaunchCfg cfg = get_cfg(CB_OP_FORCES, n, prec);
-    if (cfg.algo != ALGO_DIRECT) cfg = default_cfg(CB_OP_ENERGY, ni, prec);
+    if (cfg.algo != ALGO_DIRECT) {
+        cfg = direct_cfg(CB_OP_ENERGY, n, prec);
+        const int64_t s = std::min<int64_t>({(int64_t)cfg.splits * n / ni, (int64_t)kMaxSplits * n / ni,
+                                             std::max<int64_t>(1, n / 64)});
+        cfg.splits = (int)std::max<int64_t>(1, s);
+    }
     const int jlen = split_len(n, cfg.splits);
     const int S = n_splits(n, jlen);
     double* part = at(ws, L.part);
@@ -415,17 +430,29 @@ cb_status coulomb_energy(int64_t n, const double* x, const double* y, const doub
     if (prec == CB_MIXED_F32D) return fail(CB_EUNSUPPORTED, "coulomb_energy: CB_MIXED_F32D is for the forces only");
     if (!x || !y || !z || !q || !u_out) return fail(CB_EINVAL, "coulomb_energy: NULL argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const PairRun pr = plan(CB_OP_ENERGY, n, prec);
     double* ppot = at(ws, L.ppot);
     double* eblk = at(ws, L.eblk);
-    if ((rc = launch_pair(prec, pr.cfg, false, true, (int)n, x, y, z, q, eps2, pr.jlen, nullptr, ppot, st)))
-        return rc;
+    int S = 0;
+    bool share = false;  // the potential partials hold energy shares (the symmetric stage)
+    const LaunchCfg ecfg = get_cfg(CB_OP_ENERGY, n, prec);
+    if (is_sym(ecfg.algo) && n <= kSymMaxN) {
+        // the Newton's-third-law stage with the potential as a fourth
+        // component (its forces are a by-product, left in the workspace)
+        bool prescaled = false;
+        if ((rc = force_stage(CB_OP_ENERGY, prec, n, x, y, z, q, eps2, ws, L, st, &S, &prescaled, true))) return rc;
+        share = prescaled;
+    } else {
+        const PairRun pr = plan(CB_OP_ENERGY, n, prec);
+        S = pr.S;
+        if ((rc = launch_pair(prec, pr.cfg, false, true, (int)n, x, y, z, q, eps2, pr.jlen, nullptr, ppot, st)))
+            return rc;
+    }
     EpiParams E{};
     E.n = (int)n;
-    E.S = pr.S;
+    E.S = S;
     E.ppot = ppot;
     E.q = q;
-    E.mode = EPI_ENERGY | EPI_UC_ONLY;
+    E.mode = EPI_ENERGY | EPI_UC_ONLY | (share ? EPI_POT_SHARE : 0u);
     E.eblk = eblk;
     E.flags = flags_ptr();
     if (!E.flags) return fail(CB_EHIP, "coulomb_energy: device flag symbol not found");
@@ -477,14 +504,14 @@ cb_status coulomb_trap_grad(int64_t n, const double* x, const double* y, const d
     if (!E.flags) return fail(CB_EHIP, "coulomb_trap_grad: device flag symbol not found");
     E.mode = (want_g ? EPI_GRAD : 0u) | (u_out ? (EPI_ENERGY | EPI_UPOT) : 0u);
     if (u_out) {
-        // the potential needs the direct kernel (forces and potentials in one pass)
-        const PairRun pr = plan(CB_OP_ENERGY, n, prec);
-        E.S = pr.S;
+        // forces and potentials in one pass, with the energy's configuration
+        int S = 0;
+        bool prescaled = false;
+        if ((rc = force_stage(CB_OP_ENERGY, prec, n, x, y, z, q, eps2, ws, L, st, &S, &prescaled, true))) return rc;
+        E.S = S;
         E.part = at(ws, L.part);
         E.ppot = at(ws, L.ppot);
-        if ((rc = launch_pair(prec, pr.cfg, want_g, true, (int)n, x, y, z, q, eps2, pr.jlen,
-                              want_g ? at(ws, L.part) : nullptr, at(ws, L.ppot), st)))
-            return rc;
+        if (prescaled) E.mode |= EPI_PRESCALED | EPI_POT_SHARE;
     } else {
         int S = 0;
         bool prescaled = false;

@@ -134,8 +134,9 @@ static cb_status launch_hvp_sym(int prec, const LaunchCfg& c, int nvec, int n, c
     int lgJL = 0;
     while ((1 << lgJL) < JL) ++lgJL;
     const unsigned nb = (unsigned)((n + 63) / 64);
+    const int nvmax = c.wg;  // the most vectors per pass: 1, 2 or 4
     for (int b0 = 0; b0 < nvec;) {
-        const int left = nvec - b0;
+        const int left = std::min(nvec - b0, nvmax);
         const int nv = left >= 4 ? 4 : left >= 2 ? 2 : 1;
         const double* vb = v + (size_t)b0 * 3 * n;
         double* hb = hv + (size_t)b0 * 3 * n;
@@ -211,13 +212,15 @@ __global__ void __launch_bounds__(kEpiThreads) k_adj_pre(int n, const double* __
 
 // The adjoint update after the HVP, plus per-block partial sums of the
 // trap-frequency gradient terms -2 w_c r_c la*_c.  final_only: only the
-// gradient term of (r, la), lam unchanged.
+// gradient term of (r, la), lam unchanged.  part: the Coulomb product's
+// j-split partials [S][3][n] (to be scaled by k_C q_i), or with prescaled
+// the finished Coulomb product [3][n] (S = 1).
 __global__ void __launch_bounds__(kEpiThreads) k_adj_post(int n, int S, const double* __restrict__ part,
                                                          const double* __restrict__ x, const double* __restrict__ y,
                                                          const double* __restrict__ z, const double* __restrict__ q,
                                                          const double* __restrict__ m, const double* __restrict__ u,
                                                          TrapK k, double wx, double wy, double wz, double dt,
-                                                         int final_only, double* __restrict__ lam,
+                                                         int final_only, int prescaled, double* __restrict__ lam,
                                                          double* __restrict__ eblk, unsigned* flags) {
     const int i = blockIdx.x * kEpiThreads + threadIdx.x;
     double g[3] = {0.0, 0.0, 0.0};
@@ -229,7 +232,7 @@ __global__ void __launch_bounds__(kEpiThreads) k_adj_post(int n, int S, const do
             for (int c = 0; c < 3; ++c) g[c] = -2.0 * w[c] * r[c] * lam[(6 + c) * (size_t)n + i];
         } else {
             const double kk[3] = {k.kx, k.ky, k.kz};
-            const double cq = kCoulomb * q[i];
+            const double cq = prescaled ? 1.0 : kCoulomb * q[i];
             double ss[3];
             const double* ps[3] = {part + i, part + (size_t)n + i, part + 2 * (size_t)n + i};
             const size_t st[3] = {3 * (size_t)n, 3 * (size_t)n, 3 * (size_t)n};
@@ -370,17 +373,29 @@ cb_status md_adjoint_step(int64_t n, const double* x, const double* y, const dou
     double* eblk = at(ws, L.eblk);
     double* u = at(ws, L.aux);
     int S = 0;
+    bool prescaled = false;
     const bool final_only = (flags & CB_ADJ_FINAL) != 0;
     if (!final_only) {
         k_adj_pre<<<nb, kEpiThreads, 0, st>>>((int)n, lam, m, dt, u);
         if ((rc = check_launch("k_adj_pre"))) return rc;
         const LaunchCfg cfg = get_cfg(CB_OP_ADJOINT, n, prec);
-        const int jlen = split_len(n, cfg.splits);
-        S = n_splits(n, jlen);
-        if ((rc = launch_hvp(prec, cfg, 1, (int)n, x, y, z, q, u, eps2, jlen, part, st))) return rc;
+        if (is_sym(cfg.algo)) {
+            // the Coulomb product H_C u by Newton's third law, finished into
+            // part[3][n] (no trap term: k_adj_post adds it), scratch after it
+            S = 1;
+            prescaled = true;
+            void* hws = static_cast<char*>(ws) + L.part + al256h(sizeof(double) * 3 * (size_t)n);
+            if ((rc = launch_hvp_sym(prec, cfg, 1, (int)n, x, y, z, q, u, nullptr, TrapK{0.0, 0.0, 0.0}, eps2, hws,
+                                     part, fl, st)))
+                return rc;
+        } else {
+            const int jlen = split_len(n, cfg.splits);
+            S = n_splits(n, jlen);
+            if ((rc = launch_hvp(prec, cfg, 1, (int)n, x, y, z, q, u, eps2, jlen, part, st))) return rc;
+        }
     }
     k_adj_post<<<nb, kEpiThreads, 0, st>>>((int)n, S, part, x, y, z, q, m, u, k, trap->wx, trap->wy, trap->wz, dt,
-                                            final_only ? 1 : 0, lam, eblk, fl);
+                                            final_only ? 1 : 0, prescaled ? 1 : 0, lam, eblk, fl);
     if ((rc = check_launch("k_adj_post"))) return rc;
     k_adj_final<<<1, kEpiThreads, 0, st>>>(nb, eblk, dldw);
     if ((rc = check_launch("k_adj_final"))) return rc;

@@ -2,8 +2,8 @@
 // evaluated once for NV vectors.
 //
 // With d = r_i - r_j, u = v_i - v_j and y = (|d|^2 + eps2)^{-1/2}, ion i's
-// pair term is k_C q_i q_j T_ij with T_ij = 3 d (d . u) y^5 - u y^3, and
-// T_ji = -T_ij (d and u both change sign).  So, as for the force
+// pair term is k_C q_i q_j T_ij with T_ij = 3 d (d . u) y^5 - u y^3
+// = y^3 (3 y^2 (d . u) d - u), and T_ji = -T_ij (d and u both change sign).  So, as for the force
 // (pair_sym.hpp), a tile of i-block I and j-segment s evaluates T once per
 // pair, adds q_i q_j T_ij to i's sums and the wave's sum over i of q_i T_ij
 // to j's reaction (the finish scales it by -k_C q_j).  The same tile table,
@@ -63,6 +63,39 @@ __device__ __forceinline__ HvpJRec<NV> load_hvp_j(const double* __restrict__ J, 
     return a;
 }
 
+// q y^3 and 3 y^2 from r^2 + eps2 (the refinement of the force, section 4 of
+// the paper, with r^-2 = t (1 + e + e^2 + ...) from the same estimate).  The
+// pair term is then T = y^3 (w d - u) with w = 3 y^2 (d . u): per vector three
+// products fewer than 3 d (d . u) y^5 - u y^3 written out.
+template <int PREC>
+__device__ __forceinline__ void hvp_scales_w(double r2, double q, const SeriesK& K, double& s3, double& g3) {
+    if (PREC == PREC_IEEE) {
+        const double r = 1.0 / __builtin_sqrt(r2);
+        const double y2 = r * r;
+        s3 = y2 * r * q;
+        g3 = 3.0 * y2;
+    } else if (PREC == PREC_FP32) {
+        const double y0 = rsq_seed(r2);
+        const double t = y0 * y0;
+        s3 = (y0 * q) * t;
+        g3 = 3.0 * t;
+    } else {
+        const double y0 = rsq_seed(r2);
+        const double t = y0 * y0;
+        const double e = __builtin_fma(-r2, t, 1.0);
+        const double w = (y0 * q) * t;
+        const double t3 = 3.0 * t;
+        if (PREC == PREC_FP64) {
+            const double p = __builtin_fma(e, K.c1875, K.c15);
+            s3 = __builtin_fma(w, e * p, w);
+            g3 = __builtin_fma(t3, __builtin_fma(e, e, e), t3);
+        } else {
+            s3 = __builtin_fma(w, K.c15 * e, w);
+            g3 = __builtin_fma(t3, e, t3);
+        }
+    }
+}
+
 // Pairs of one j with the lane's P ions: i sums into ia[p][b][c] (q_i q_j T,
 // or T when UNI), this lane's share of j's reaction (sum over p of q_i T, or
 // T) into sh[b][c].
@@ -77,29 +110,24 @@ __device__ __forceinline__ void hvp_sym_pair(const HvpJRec<NV>& J, double eps2, 
     for (int p = 0; p < P; ++p) {
         const double dx = xi[p] - J.x, dy = yi[p] - J.y, dz = zi[p] - J.z;
         const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
-        double s3, s5;  // q_i y^3 and 3 q_i y^5 (y^3, 3 y^5 when UNI)
-        hvp_scales<PREC>(r2, UNI ? 1.0 : qi[p], K, s3, s5);
+        double s3, g3;  // q_i y^3 (y^3 when UNI) and 3 y^2
+        hvp_scales_w<PREC>(r2, UNI ? 1.0 : qi[p], K, s3, g3);
+        const double a3 = UNI ? s3 : s3 * J.q;  // q_i q_j y^3
 #pragma unroll
         for (int b = 0; b < NV; ++b) {
             const double ux = vi[b][0][p] - J.v[b][0];
             const double uy = vi[b][1][p] - J.v[b][1];
             const double uz = vi[b][2][p] - J.v[b][2];
-            const double c = __builtin_fma(dx, ux, __builtin_fma(dy, uy, dz * uz)) * s5;
-            const double tx = __builtin_fma(dx, c, -(ux * s3));
-            const double ty = __builtin_fma(dy, c, -(uy * s3));
-            const double tz = __builtin_fma(dz, c, -(uz * s3));
-            if constexpr (UNI) {
-                ia[p][b][0] += tx;
-                ia[p][b][1] += ty;
-                ia[p][b][2] += tz;
-            } else {
-                ia[p][b][0] = __builtin_fma(J.q, tx, ia[p][b][0]);
-                ia[p][b][1] = __builtin_fma(J.q, ty, ia[p][b][1]);
-                ia[p][b][2] = __builtin_fma(J.q, tz, ia[p][b][2]);
-            }
-            sh[b][0] += tx;
-            sh[b][1] += ty;
-            sh[b][2] += tz;
+            const double w = __builtin_fma(dx, ux, __builtin_fma(dy, uy, dz * uz)) * g3;
+            const double vx = __builtin_fma(w, dx, -ux);  // T / y^3
+            const double vy = __builtin_fma(w, dy, -uy);
+            const double vz = __builtin_fma(w, dz, -uz);
+            ia[p][b][0] = __builtin_fma(a3, vx, ia[p][b][0]);
+            ia[p][b][1] = __builtin_fma(a3, vy, ia[p][b][1]);
+            ia[p][b][2] = __builtin_fma(a3, vz, ia[p][b][2]);
+            sh[b][0] = __builtin_fma(s3, vx, sh[b][0]);
+            sh[b][1] = __builtin_fma(s3, vy, sh[b][1]);
+            sh[b][2] = __builtin_fma(s3, vz, sh[b][2]);
         }
     }
 }
@@ -109,7 +137,7 @@ __device__ __forceinline__ void hvp_sym_pair(const HvpJRec<NV>& J, double eps2, 
 // variants spill at most a few registers).
 template <int P, int NV>
 constexpr int hvp_sym_waves() {
-    return P == 1 ? 4 : (P == 2 ? (NV == 4 ? 3 : 4) : (NV == 1 ? 3 : 2));
+    return P == 1 ? 4 : (P == 2 ? (NV == 4 ? 2 : 4) : (NV == 1 ? 3 : 2));
 }
 
 // The j loop of tile t over [j0, j1) and the stores of its partials:
@@ -244,14 +272,14 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_hvp_sym_finish(
     for (int j = lo; j < hi; ++j) {  // q_j T_kj over k's own block
         const double dx = xk - x[j], dy = yk - y[j], dz = zk - z[j];
         const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
-        double s3, s5;
-        hvp_scales<PREC>(r2, q[j], K, s3, s5);
-        if (j == kc) s3 = s5 = 0.0;
+        double s3, g3;
+        hvp_scales_w<PREC>(r2, q[j], K, s3, g3);
+        if (j == kc) s3 = g3 = 0.0;  // the self pair (both scales: they are not finite at r = 0)
         const double ux = vk[0] - vb[j], uy = vk[1] - vb[n + j], uz = vk[2] - vb[2 * (size_t)n + j];
-        const double c = __builtin_fma(dx, ux, __builtin_fma(dy, uy, dz * uz)) * s5;
-        d[0] += __builtin_fma(dx, c, -(ux * s3));
-        d[1] += __builtin_fma(dy, c, -(uy * s3));
-        d[2] += __builtin_fma(dz, c, -(uz * s3));
+        const double w = __builtin_fma(dx, ux, __builtin_fma(dy, uy, dz * uz)) * g3;
+        d[0] = __builtin_fma(s3, __builtin_fma(w, dx, -ux), d[0]);
+        d[1] = __builtin_fma(s3, __builtin_fma(w, dy, -uy), d[1]);
+        d[2] = __builtin_fma(s3, __builtin_fma(w, dz, -uz), d[2]);
     }
     const int off = kc - b0;
     share(rowstart[Ik], rowstart[Ik + 1], w, lo, hi);

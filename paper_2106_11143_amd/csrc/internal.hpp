@@ -28,6 +28,11 @@ enum : int { ALGO_DIRECT = 0, ALGO_SYM = 1, ALGO_SYM_LDS = 2, ALGO_SMALL = 3 };
 
 constexpr bool is_sym(int algo) { return algo == ALGO_SYM || algo == ALGO_SYM_LDS; }
 
+// Operations whose pair stage may take the Newton's-third-law kernels.
+constexpr bool sym_op(int op) {
+    return op == CB_OP_FORCES || op == CB_OP_ENERGY || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN;
+}
+
 // Symmetric path launch parameters: i-particles per lane, j's per reaction
 // group, segment lengths (powers of two).
 constexpr int kSymP[] = {2, 3, 4, 5, 6, 8};
@@ -97,6 +102,7 @@ class HostUpload {
 
 int n_bucket(int64_t n);
 LaunchCfg default_cfg(int op, int64_t n, int prec);
+LaunchCfg direct_cfg(int op, int64_t n, int prec);
 LaunchCfg get_cfg(int op, int64_t n, int prec);
 void put_cfg(int op, int64_t n, int prec, LaunchCfg c);
 void drop_cfg(int op, int64_t n, int prec);
@@ -123,11 +129,13 @@ int64_t sym_tiles(int64_t n, int IB, int JL);
 size_t sym_plan_bytes(int64_t n, int IB, int JL);
 cb_status sym_plan(int n, int IB, int JL, void* ws, SymPlan* out, hipStream_t st);
 
-// Symmetric (Newton's third law) force path (pair.hip): workspace bytes for
-// (n, p, JL), and the launch sequence ending with finished forces F[3][n].
-size_t sym_ws_bytes(int64_t n, int p, int jl);
+// Symmetric (Newton's third law) force path (pair_sym.hip): workspace bytes
+// for (n, p, JL) (pot: with the tiles' pair energies), and the launch
+// sequence ending with finished forces F[3][n] and, when phi is set, each
+// ion's share of the Coulomb energy, U_C = k_C sum_k phi[k].
+size_t sym_ws_bytes(int64_t n, int p, int jl, bool pot = false);
 cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, const double* y, const double* z,
-                          const double* q, double eps2, void* ws, double* F, hipStream_t st);
+                          const double* q, double eps2, void* ws, double* F, hipStream_t st, double* phi = nullptr);
 
 // Launches of the pair kernels (pair.hip).  The _range form evaluates the
 // forces / potentials of the ions i0 .. i0 + ni - 1 only (partials indexed by

@@ -62,38 +62,56 @@ int64_t sym_tiles(int64_t n, int IB, int JL) {
 }
 
 // Workspace carve-up: rowstart[nI+1] | tiles[T] | Pi[T][3][IB] | R[T][3][JL]
-size_t sym_ws_bytes(int64_t n, int p, int jl) {
+// (| Et[T], the tiles' pair energies, with the energy)
+size_t sym_ws_bytes(int64_t n, int p, int jl, bool pot) {
     const int IB = 64 * p;
     const int64_t T = sym_tiles(n, IB, jl);
     return sym_plan_bytes(n, IB, jl) + al256(sizeof(double) * 3 * IB * (T + 1)) +
-           al256(sizeof(double) * 3 * (size_t)jl * (T + 1));
+           al256(sizeof(double) * 3 * (size_t)jl * (T + 1)) + (pot ? al256(sizeof(double) * (T + 1)) : 0);
 }
 
-template <int PREC, int P, int RED>
+template <int PREC, int P, int RED, bool POT>
 static void go_sym(int n, int JL, int64_t T, const double* x, const double* y, const double* z, const double* q,
-                   double eps2, const int2* tiles, double* Pi, double* R, hipStream_t st) {
-    k_pair_sym<PREC, P, RED><<<(unsigned)T, 64, 0, st>>>(n, x, y, z, q, eps2, JL, tiles, Pi, R);
+                   double eps2, const int2* tiles, double* Pi, double* R, double* Et, hipStream_t st) {
+    k_pair_sym<PREC, P, RED, POT><<<(unsigned)T, 64, 0, st>>>(n, x, y, z, q, eps2, JL, tiles, Pi, R, Et);
 }
 
-template <int PREC, int RED>
+template <int PREC, int RED, bool POT>
 static bool go_sym_p(int P, int n, int JL, int64_t T, const double* x, const double* y, const double* z,
-                     const double* q, double eps2, const int2* tiles, double* Pi, double* R, hipStream_t st) {
+                     const double* q, double eps2, const int2* tiles, double* Pi, double* R, double* Et,
+                     hipStream_t st) {
     switch (P) {
-        case 2: go_sym<PREC, 2, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 3: go_sym<PREC, 3, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 4: go_sym<PREC, 4, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 5: go_sym<PREC, 5, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 6: go_sym<PREC, 6, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
-        case 8: go_sym<PREC, 8, RED>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); return true;
+        case 2: go_sym<PREC, 2, RED, POT>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); return true;
+        case 3: go_sym<PREC, 3, RED, POT>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); return true;
+        case 4: go_sym<PREC, 4, RED, POT>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); return true;
+        case 5: go_sym<PREC, 5, RED, POT>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); return true;
+        case 6: go_sym<PREC, 6, RED, POT>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); return true;
+        case 8: go_sym<PREC, 8, RED, POT>(n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); return true;
         default: return false;
     }
 }
 
+// red: 1 = reactions summed through LDS, 0 = by permutes; the energy's
+// variant sums them through LDS.
 template <int PREC>
-static bool go_sym_pr(int P, int red, int n, int JL, int64_t T, const double* x, const double* y, const double* z,
-                      const double* q, double eps2, const int2* tiles, double* Pi, double* R, hipStream_t st) {
-    return red ? go_sym_p<PREC, 1>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st)
-               : go_sym_p<PREC, 0>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st);
+static bool go_sym_pr(int P, int red, bool pot, int n, int JL, int64_t T, const double* x, const double* y,
+                      const double* z, const double* q, double eps2, const int2* tiles, double* Pi, double* R,
+                      double* Et, hipStream_t st) {
+    if (pot) return go_sym_p<PREC, 1, true>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st);
+    return red ? go_sym_p<PREC, 1, false>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st)
+               : go_sym_p<PREC, 0, false>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st);
+}
+
+template <int PREC>
+static void go_finish(bool pot, unsigned nb, int n, int IB, int JL, int lgJL, const double* x, const double* y,
+                      const double* z, const double* q, double eps2, const int* rowstart, const double* Pi,
+                      const double* R, const double* Et, double* F, double* phi, hipStream_t st) {
+    if (pot)
+        k_sym_finish<PREC, true><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi,
+                                                                   R, Et, F, phi);
+    else
+        k_sym_finish<PREC, false><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi,
+                                                                    R, Et, F, phi);
 }
 
 size_t sym_plan_bytes(int64_t n, int IB, int JL) {
@@ -115,7 +133,7 @@ cb_status sym_plan(int n, int IB, int JL, void* ws, SymPlan* out, hipStream_t st
 }
 
 cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, const double* y, const double* z,
-                          const double* q, double eps2, void* ws, double* F, hipStream_t st) {
+                          const double* q, double eps2, void* ws, double* F, hipStream_t st, double* phi) {
     const int P = c.p, JL = c.splits, IB = 64 * P;
     if (!is_sym(c.algo) || !sym_cfg_ok(P, c.wg, JL)) return fail(CB_EINVAL, "launch_pair_sym: bad configuration");
     const int red = c.algo == ALGO_SYM_LDS ? 1 : 0;
@@ -125,17 +143,20 @@ cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, 
     const int64_t T = plan.T;
     int* rowstart = plan.rowstart;
     const int2* tiles = plan.tiles;
+    const bool pot = phi != nullptr;
     char* base = static_cast<char*>(ws) + plan.bytes;
     double* Pi = reinterpret_cast<double*>(base);
     base += al256(sizeof(double) * 3 * IB * (T + 1));
     double* R = reinterpret_cast<double*>(base);
+    base += al256(sizeof(double) * 3 * (size_t)JL * (T + 1));
+    double* Et = pot ? reinterpret_cast<double*>(base) : nullptr;
     if (T > 0) {
         bool okk = false;
         switch (prec) {
-            case PREC_FP64: okk = go_sym_pr<PREC_FP64>(P, red, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_MIXED: okk = go_sym_pr<PREC_MIXED>(P, red, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_IEEE: okk = go_sym_pr<PREC_IEEE>(P, red, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
-            case PREC_FP32: okk = go_sym_pr<PREC_FP32>(P, red, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, st); break;
+            case PREC_FP64: okk = go_sym_pr<PREC_FP64>(P, red, pot, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); break;
+            case PREC_MIXED: okk = go_sym_pr<PREC_MIXED>(P, red, pot, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); break;
+            case PREC_IEEE: okk = go_sym_pr<PREC_IEEE>(P, red, pot, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); break;
+            case PREC_FP32: okk = go_sym_pr<PREC_FP32>(P, red, pot, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); break;
             default: break;
         }
         if (!okk) return fail(CB_EINVAL, "launch_pair_sym: unsupported precision %d / p %d", prec, P);
@@ -145,10 +166,10 @@ cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, 
     int lgJL = 0;
     while ((1 << lgJL) < JL) ++lgJL;
     switch (prec) {
-        case PREC_FP64: k_sym_finish<PREC_FP64><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
-        case PREC_MIXED: k_sym_finish<PREC_MIXED><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
-        case PREC_IEEE: k_sym_finish<PREC_IEEE><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
-        default: k_sym_finish<PREC_FP32><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, F); break;
+        case PREC_FP64: go_finish<PREC_FP64>(pot, nb, n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, Et, F, phi, st); break;
+        case PREC_MIXED: go_finish<PREC_MIXED>(pot, nb, n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, Et, F, phi, st); break;
+        case PREC_IEEE: go_finish<PREC_IEEE>(pot, nb, n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, Et, F, phi, st); break;
+        default: go_finish<PREC_FP32>(pot, nb, n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, Et, F, phi, st); break;
     }
     return check_launch("k_sym_finish");
 }

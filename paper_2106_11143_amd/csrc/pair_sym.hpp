@@ -120,10 +120,13 @@ __device__ __forceinline__ bool tile_charges(const double (&qi)[P], const double
 // (no charge load, no charge multiply); the i sums are scaled by qI qJ when
 // stored and the reactions by rscale = qI here, so that the partials hold
 // what the general loop stores.
-template <int PREC, int P, int RED, bool TAIL, bool UNI>
+// POT: the pair energies too, into one sum per lane, pe += q_i q_j r^-1
+// (r^-1 when UNI), from r^-1 = r^2 r^-3: one or two operations per pair and
+// no reaction (each unordered pair's energy is counted once, here).
+template <int PREC, int P, int RED, bool TAIL, bool UNI, bool POT>
 __device__ __forceinline__ void sym_group(const JGroupT<!UNI>& jd, int jg, int live, int j0, int JL, double eps2,
                                           const double (&xi)[P], const double (&yi)[P], const double (&zi)[P],
-                                          const double (&qi)[P], double (&ia)[P][3], const SeriesK& K,
+                                          const double (&qi)[P], double (&ia)[P][3], double& pe, const SeriesK& K,
                                           double rscale, double* __restrict__ Rt, double* __restrict__ red) {
     double jv[3 * kGroupJ];  // this lane's share of each reaction: sum over its P ions of q_i d r^-3
 #pragma unroll
@@ -144,6 +147,7 @@ __device__ __forceinline__ void sym_group(const JGroupT<!UNI>& jd, int jg, int l
             a0 = __builtin_fma(dx, s, a0);
             a1 = __builtin_fma(dy, s, a1);
             a2 = __builtin_fma(dz, s, a2);
+            if constexpr (POT) pe = __builtin_fma(r2, sq, pe);  // r^2 (q_i q_j) r^-3
         }
         jv[3 * u + 0] = a0;
         jv[3 * u + 1] = a1;
@@ -155,6 +159,7 @@ __device__ __forceinline__ void sym_group(const JGroupT<!UNI>& jd, int jg, int l
     // more VGPRs, half the occupancy).
 #pragma unroll
     for (int p = 0; p < P; ++p) asm volatile("" : "+v"(ia[p][0]), "+v"(ia[p][1]), "+v"(ia[p][2]));
+    if constexpr (POT) asm volatile("" : "+v"(pe));
     const int lane = threadIdx.x;
     if constexpr (RED == 0) {
         double o[3];
@@ -175,23 +180,25 @@ __device__ __forceinline__ void sym_group(const JGroupT<!UNI>& jd, int jg, int l
 
 // Waves per SIMD the register budget is sized for (no spills at these; the
 // IEEE square root and division need more registers).
-template <int PREC, int P>
+template <int PREC, int P, bool POT = false>
 constexpr int sym_waves() {
     return PREC == PREC_IEEE ? (P <= 4 ? 4 : (P <= 6 ? 3 : 2)) : (P <= 5 ? 4 : 3);
 }
 
 // The j loop of a tile over [j0, j1) and the store of its i sums (see
-// sym_tile); UNI: a tile of one charge per side, qI and qJ.
-template <int PREC, int P, int RED, bool UNI>
+// sym_tile); UNI: a tile of one charge per side, qI and qJ.  With POT the
+// tile's pair energy sum_{i, j} q_i q_j r^-1 goes to Et[t].
+template <int PREC, int P, int RED, bool UNI, bool POT>
 __device__ __forceinline__ void sym_tile_body(const double* __restrict__ x, const double* __restrict__ y,
                                               const double* __restrict__ z, const double* __restrict__ q,
                                               double eps2, int JL, int j0, int j1, int t, const double (&xi)[P],
                                               const double (&yi)[P], const double (&zi)[P], const double (&qi)[P],
                                               double qI, double qJ, double* __restrict__ red,
-                                              double* __restrict__ Pi, double* __restrict__ R) {
+                                              double* __restrict__ Pi, double* __restrict__ R,
+                                              double* __restrict__ Et) {
     constexpr int IB = 64 * P;
     const int lane = threadIdx.x;
-    double ia[P][3];
+    double ia[P][3], pe = 0.0;
 #pragma unroll
     for (int p = 0; p < P; ++p) ia[p][0] = ia[p][1] = ia[p][2] = 0.0;
     const SeriesK K;
@@ -209,14 +216,16 @@ __device__ __forceinline__ void sym_tile_body(const double* __restrict__ x, cons
             const int jn = jg + kGroupJ;
             load_group<false>(nxt, jn < jfull ? jn : jg, 0, x, y, z, q);
             __builtin_amdgcn_sched_barrier(0);  // keep the requests ahead of the arithmetic
-            sym_group<PREC, P, RED, false, UNI>(cur, jg, kGroupJ, j0, JL, eps2, xi, yi, zi, qi, ia, K, qI, Rt, red);
+            sym_group<PREC, P, RED, false, UNI, POT>(cur, jg, kGroupJ, j0, JL, eps2, xi, yi, zi, qi, ia, pe, K, qI,
+                                                     Rt, red);
             cur = nxt;
         }
     }
     if (jg < j1) {  // the last, partial group: j's from j1 on are masked
         JGroupT<!UNI> tail;
         load_group<true>(tail, jg, j1 - jg - 1, x, y, z, q);
-        sym_group<PREC, P, RED, true, UNI>(tail, jg, j1 - jg, j0, JL, eps2, xi, yi, zi, qi, ia, K, qI, Rt, red);
+        sym_group<PREC, P, RED, true, UNI, POT>(tail, jg, j1 - jg, j0, JL, eps2, xi, yi, zi, qi, ia, pe, K, qI, Rt,
+                                                red);
     }
     const double sc = UNI ? qI * qJ : 1.0;
     double* Pt = Pi + (size_t)t * 3 * IB;
@@ -224,17 +233,26 @@ __device__ __forceinline__ void sym_tile_body(const double* __restrict__ x, cons
     for (int p = 0; p < P; ++p)
 #pragma unroll
         for (int c = 0; c < 3; ++c) Pt[(size_t)c * IB + p * 64 + lane] = UNI ? sc * ia[p][c] : ia[p][c];
+    if constexpr (POT) {
+        // the tile's energy: a fixed butterfly over the wave (every run adds
+        // in the same order), stored by lane 0
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) pe += __shfl_xor(pe, o);
+        if (lane == 0) Et[t] = UNI ? sc * pe : pe;
+    }
 }
 
 // Tile (row I, segment sg) of a run of n ions at x, y, z, q: i sums to
-// Pi[t][3][IB], reactions to R[t][3][JL].  red: the LDS reduction buffer.
-// A tile whose i-block and j-segment each hold ions of one charge (ions
-// grouped by species) takes the charge-free pair loop.
-template <int PREC, int P, int RED>
+// Pi[t][3][IB], reactions to R[t][3][JL] (and with POT its pair energy to
+// Et[t]).  red: the LDS reduction buffer.  A tile whose i-block and
+// j-segment each hold ions of one charge (ions grouped by species) takes the
+// charge-free pair loop.
+template <int PREC, int P, int RED, bool POT = false>
 __device__ __forceinline__ void sym_tile(int n, const double* __restrict__ x, const double* __restrict__ y,
                                          const double* __restrict__ z, const double* __restrict__ q, double eps2,
                                          int JL, int I, int sg, int t, double* __restrict__ red,
-                                         double* __restrict__ Pi, double* __restrict__ R) {
+                                         double* __restrict__ Pi, double* __restrict__ R,
+                                         double* __restrict__ Et = nullptr) {
     constexpr int IB = 64 * P;
     const int lane = threadIdx.x;
     double xi[P], yi[P], zi[P], qi[P];
@@ -250,22 +268,25 @@ __device__ __forceinline__ void sym_tile(int n, const double* __restrict__ x, co
     const int j1 = min(n, j0 + JL);
     double qI, qJ;
     if (tile_charges<P>(qi, q, j0, j1, qI, qJ))
-        sym_tile_body<PREC, P, RED, true>(x, y, z, q, eps2, JL, j0, j1, t, xi, yi, zi, qi, qI, qJ, red, Pi, R);
+        sym_tile_body<PREC, P, RED, true, POT>(x, y, z, q, eps2, JL, j0, j1, t, xi, yi, zi, qi, qI, qJ, red, Pi, R,
+                                               Et);
     else
-        sym_tile_body<PREC, P, RED, false>(x, y, z, q, eps2, JL, j0, j1, t, xi, yi, zi, qi, 1.0, 1.0, red, Pi, R);
+        sym_tile_body<PREC, P, RED, false, POT>(x, y, z, q, eps2, JL, j0, j1, t, xi, yi, zi, qi, 1.0, 1.0, red, Pi,
+                                                R, Et);
 }
 
-template <int PREC, int P, int RED>
-__global__ void __launch_bounds__(64, (sym_waves<PREC, P>())) k_pair_sym(int n, const double* __restrict__ x,
+template <int PREC, int P, int RED, bool POT>
+__global__ void __launch_bounds__(64, (sym_waves<PREC, P, POT>())) k_pair_sym(int n, const double* __restrict__ x,
                                                                  const double* __restrict__ y,
                                                                  const double* __restrict__ z,
                                                                  const double* __restrict__ q, double eps2, int JL,
                                                                  const int2* __restrict__ tiles,
-                                                                 double* __restrict__ Pi, double* __restrict__ R) {
+                                                                 double* __restrict__ Pi, double* __restrict__ R,
+                                                                 double* __restrict__ Et) {
     __shared__ __align__(16) double red_buf[RED == 1 ? 12 * kRedStride : 2];
     const int t = blockIdx.x;
     const int2 tl = tiles[t];
-    sym_tile<PREC, P, RED>(n, x, y, z, q, eps2, JL, tl.x, tl.y, t, red_buf, Pi, R);
+    sym_tile<PREC, P, RED, POT>(n, x, y, z, q, eps2, JL, tl.x, tl.y, t, red_buf, Pi, R, Et);
 }
 
 // Per ion k: direct pairs inside its own i-block, plus its i sums over the
@@ -283,7 +304,11 @@ __host__ __device__ __forceinline__ void share(int a, int b, int w, int& lo, int
     hi = min(b, lo + len);
 }
 
-template <int PREC>
+// With POT, phi[k] receives ion k's share of the Coulomb energy, U_C =
+// k_C sum_k phi[k]: q_k times its pairs with the later ions of its own block
+// (q_j r^-1, j > k), plus the energies of the tiles of its row numbered
+// off, off + IB, ... within the row (each tile's energy goes to one ion).
+template <int PREC, bool POT>
 __global__ void __launch_bounds__(64 * kFinishParts) k_sym_finish(int n, int IB, int JL, int lgJL,
                                                                   const double* __restrict__ x,
                                                                   const double* __restrict__ y,
@@ -292,8 +317,10 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_sym_finish(int n, int IB,
                                                                   const int* __restrict__ rowstart,
                                                                   const double* __restrict__ Pi,
                                                                   const double* __restrict__ R,
-                                                                  double* __restrict__ F) {
-    __shared__ double red[kFinishParts][9][64];
+                                                                  const double* __restrict__ Et,
+                                                                  double* __restrict__ F, double* __restrict__ phi) {
+    constexpr int NS = POT ? 10 : 9;  // per lane: direct 3, i sums 3, reactions 3 (+ the energy share)
+    __shared__ double red[kFinishParts][NS][64];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int k0 = blockIdx.x * 64;
@@ -304,12 +331,13 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_sym_finish(int n, int IB,
     const double xk = x[kc], yk = y[kc], zk = z[kc];
     const SeriesK K;
     int lo, hi;
-    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, ps = 0.0;
     share(b0, b1, w, lo, hi);
     for (int j = lo; j < hi; ++j) {
         const double dx = xk - x[j], dy = yk - y[j], dz = zk - z[j];
         const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
-        double s = sym_s<PREC>(r2, q[j], K);
+        double s = sym_s<PREC>(r2, q[j], K);  // q_j r^-3
+        if (POT) ps = j > kc ? __builtin_fma(r2, s, ps) : ps;  // q_j r^-1 of the later ions
         if (j == kc) s = 0.0;
         d0 = __builtin_fma(dx, s, d0);
         d1 = __builtin_fma(dy, s, d1);
@@ -336,14 +364,21 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_sym_finish(int n, int IB,
         e1 += Rt[JL];
         e2 += Rt[2 * JL];
     }
-    const double v[9] = {d0, d1, d2, p0, p1, p2, e0, e1, e2};
+    double es = 0.0;
+    if (POT) {
+        const double qk = q[kc];
+        es = qk * ps;
+        if (w == 0)
+            for (int t = rowstart[Ik] + off; t < rowstart[Ik + 1]; t += IB) es += Et[t];
+    }
+    const double v[10] = {d0, d1, d2, p0, p1, p2, e0, e1, e2, es};
 #pragma unroll
-    for (int c = 0; c < 9; ++c) red[w][c][lane] = v[c];
+    for (int c = 0; c < NS; ++c) red[w][c][lane] = v[c];
     __syncthreads();
     if (w != 0 || k >= n) return;
-    double tot[9];
+    double tot[NS];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
+    for (int c = 0; c < NS; ++c) {
         double a = red[0][c][lane];
 #pragma unroll
         for (int u = 1; u < kFinishParts; ++u) a += red[u][c][lane];
@@ -353,6 +388,7 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_sym_finish(int n, int IB,
     F[k] = kCoulomb * (tot[3] + qk * (tot[0] - tot[6]));
     F[(size_t)n + k] = kCoulomb * (tot[4] + qk * (tot[1] - tot[7]));
     F[2 * (size_t)n + k] = kCoulomb * (tot[5] + qk * (tot[2] - tot[8]));
+    if (POT) phi[k] = tot[NS - 1];
 }
 
 }  // namespace cb

@@ -25,7 +25,8 @@ enum : unsigned {
     EPI_UC_ONLY = 32u,    // energy: only U_C (no m, v, trap)
     EPI_PRESCALED = 64u,  // part holds finished forces [3][n] (S = 1), not sums to scale by k_C q_i
     EPI_GRAD = 128u,      // write g = -F + m k(t0) r (m NULL: -F) to fx, fy, fz
-    EPI_UPOT = 256u       // energy: U_C and U_trap(t0) only (no velocities; U_trap = 0 when m is NULL)
+    EPI_UPOT = 256u,      // energy: U_C and U_trap(t0) only (no velocities; U_trap = 0 when m is NULL)
+    EPI_POT_SHARE = 512u  // the potential partials hold energy shares (U_C = k_C sum), S = 1
 };
 
 // What sum_record writes: the whole record, U_C alone, or U_C + U_trap alone.

@@ -154,6 +154,8 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
         }
         const double c = kCoulomb * qi;
         const double cf = (mode & EPI_PRESCALED) ? 1.0 : c;
+        // U_C of the ion: half its potential sum times k_C q_i, or its share
+        const double cu = (mode & EPI_POT_SHARE) ? kCoulomb : 0.5 * c;
         const double Fx = cf * sx, Fy = cf * sy, Fz = cf * sz;
         bool ok = true;
         if (mode & EPI_FORCES) {
@@ -184,12 +186,12 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
                 ok = finite3(gx, gy, gz);
             }
             if (mode & EPI_ENERGY) {
-                eC = 0.5 * c * sp;
+                eC = cu * sp;
                 eT = 0.5 * mi * (k.kx * xi * xi + k.ky * yi * yi + k.kz * zi * zi);
                 ok = ok && __builtin_isfinite(eC) && __builtin_isfinite(eT);
             }
         } else if (mode & EPI_UC_ONLY) {
-            eC = 0.5 * c * sp;
+            eC = cu * sp;
             ok = ok && __builtin_isfinite(eC);
         } else if (mode & (EPI_ACCEL | EPI_KICK | EPI_DRIFT | EPI_ENERGY)) {
             const double t = step_time(P.t0, P.dt, P.step);
@@ -224,7 +226,7 @@ __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
             }
             if (mode & EPI_ENERGY) {
                 eK = 0.5 * mi * (vx * vx + vy * vy + vz * vz);
-                eC = 0.5 * c * sp;
+                eC = cu * sp;
                 eT = 0.5 * mi * (k.kx * x * x + k.ky * y * y + k.kz * z * z);
                 ok = ok && finite3(eK, eC, eT);
             }

@@ -69,31 +69,33 @@ __device__ __forceinline__ void reduce_scatter12(const double (&v)[12], double (
 }
 
 // The same sums through LDS, for a workgroup of one wave.  Every lane writes
-// its 12 values value-major into red: row k of kRedStride doubles holds value
-// k of lanes 0-63, each run of 16 lanes followed by 2 doubles of padding.
-// Lane L then reads value vi = min(L / 4, 11) of lanes 16 g .. 16 g + 15
-// (g = L % 4, one contiguous run) as eight 16-byte loads, adds them in a
-// fixed tree, and the four lanes of each quad add their partial sums by DPP.
-// The result, the sum over all 64 lanes of value vi, is returned in every
-// lane of quad vi (lanes 48-63 repeat value 11).  The padding puts the four
-// runs a quad reads 144 bytes apart (distinct banks) and the row stride of
-// 576 bytes puts neighbouring quads' rows half a bank cycle apart, so the
-// loads are free of bank conflicts.
+// its NV (12 or 16) values value-major into red: row k of kRedStride doubles
+// holds value k of lanes 0-63, each run of 16 lanes followed by 2 doubles of
+// padding.  Lane L then reads value vi = min(L / 4, NV - 1) of lanes
+// 16 g .. 16 g + 15 (g = L % 4, one contiguous run) as eight 16-byte loads,
+// adds them in a fixed tree, and the four lanes of each quad add their
+// partial sums by DPP.  The result, the sum over all 64 lanes of value vi, is
+// returned in every lane of quad vi (with 12 values lanes 48-63 repeat value
+// 11).  The padding puts the four runs a quad reads 144 bytes apart (distinct
+// banks) and the row stride of 576 bytes puts neighbouring quads' rows half a
+// bank cycle apart, so the loads are free of bank conflicts.
 // One wave's LDS instructions are performed in issue order, so the reads see
 // the writes and the next call's writes follow these reads without a
 // barrier; the wavefront-scope fences only keep the compiler from moving the
-// accesses across each other.  red holds 12 kRedStride doubles, 16-byte
+// accesses across each other.  red holds NV kRedStride doubles, 16-byte
 // aligned, and is used by one wave only.
 constexpr int kRedStride = 72;
 
-__device__ __forceinline__ double lds_reduce12(const double (&v)[12], double* __restrict__ red) {
+template <int NV>
+__device__ __forceinline__ double lds_reduce(const double (&v)[NV], double* __restrict__ red) {
+    static_assert(NV == 12 || NV == 16, "12 or 16 values per lane");
     const int lane = __lane_id();
     const int wpos = lane + 2 * (lane >> 4);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) red[k * kRedStride + wpos] = v[k];
+    for (int k = 0; k < NV; ++k) red[k * kRedStride + wpos] = v[k];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int vi = min(lane >> 2, 11);
+    const int vi = min(lane >> 2, NV - 1);
     const double2* src = reinterpret_cast<const double2*>(red + vi * kRedStride + (lane & 3) * 18);
     double2 a[8];
 #pragma unroll
@@ -106,6 +108,10 @@ __device__ __forceinline__ double lds_reduce12(const double (&v)[12], double* __
     x += dpp_d<kDppQuadXor2>(x);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // these reads before the next call's writes
     return x;
+}
+
+__device__ __forceinline__ double lds_reduce12(const double (&v)[12], double* __restrict__ red) {
+    return lds_reduce<12>(v, red);
 }
 
 }  // namespace cb

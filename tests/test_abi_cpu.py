@@ -196,7 +196,9 @@ def test_symmetric_config_validation(api):
                 dict(op="md_run", n=1000, p=2, wg=64, splits=8)):
         with pytest.raises(api.CoulombError):
             api.set_config(bad["op"], bad["n"], "fp64", p=bad["p"], wg=bad["wg"], splits=bad["splits"], algo=3)
-    assert api.get_config("energy", 50000, "fp64")["algo"] == 0  # the potential needs every ordered pair
+    # the energy takes the Newton's-third-law stage too (the potential as a fourth component)
+    assert api.get_config("energy", 50000, "fp64")["algo"] == 2
+    assert api.get_config("energy", 10000, "fp64")["algo"] == 0
     for algo in (1, 2):
         for p in (2, 3, 4, 5, 6, 8):
             for jl in (256, 512, 1024, 2048):
@@ -207,8 +209,8 @@ def test_symmetric_config_validation(api):
     with pytest.raises(api.CoulombError):
         api.set_config("forces", 5000, "fp64", p=4, wg=4, splits=512, algo=3)
     for bad in (dict(op="forces", n=1 << 19, p=2, wg=4, splits=1024),  # beyond the symmetric size limit
-                dict(op="hvp", n=5000, p=2, wg=4, splits=1024),  # forces only
-                dict(op="energy", n=5000, p=2, wg=4, splits=1024),
+                dict(op="hvp", n=5000, p=2, wg=4, splits=1024),  # not a segment length of the HVP tiles
+                dict(op="adjoint", n=5000, p=2, wg=4, splits=1024),
                 dict(op="forces", n=5000, p=4, wg=8, splits=1024),  # groups are 4 j's
                 dict(op="forces", n=5000, p=7, wg=4, splits=1024),
                 dict(op="forces", n=5000, p=1, wg=4, splits=1024),
@@ -332,3 +334,25 @@ def test_noalloc_argument_errors(api):
     assert L.coulomb_forces_noalloc(10, o1, P, P, P, 0.0, 0, o1, o2, o3, None) == api.CB_EINVAL
     assert "alias" in api.last_error()
     assert L.coulomb_forces_noalloc(10, P, P, P, P, 0.0, 0, o1, o1, o3, None) == api.CB_EINVAL
+
+
+def test_hvp_config_validation(api):
+    """The Newton's-third-law HVP shapes (algorithm 2): p in {1, 2, 4}, wg =
+    the most vectors per pass in {1, 2, 4}, segments of 64 .. 512, n up to
+    131072 p; for the HVP and the adjoint step."""
+    for op in ("hvp", "adjoint"):
+        for p in (1, 2, 4):
+            for wg in (1, 2, 4):
+                for jl in (64, 128, 256, 512):
+                    api.set_config(op, 5000, "fp64", p=p, wg=wg, splits=jl, algo=2)
+                    c = api.get_config(op, 5000, "fp64")
+                    assert (c["algo"], c["p"], c["wg"], c["splits"]) == (2, p, wg, jl)
+        api.reset_config(op, 5000, "fp64")
+        for bad in (dict(p=3, wg=4, splits=128), dict(p=2, wg=3, splits=128), dict(p=2, wg=4, splits=1024),
+                    dict(p=2, wg=4, splits=96)):
+            with pytest.raises(api.CoulombError):
+                api.set_config(op, 5000, "fp64", algo=2, **bad)
+        with pytest.raises(api.CoulombError):  # beyond the tile table of p = 1
+            api.set_config(op, 131073, "fp64", p=1, wg=4, splits=128, algo=2)
+        api.set_config(op, 131073, "fp64", p=2, wg=4, splits=128, algo=2)
+        api.reset_config(op, 131073, "fp64")

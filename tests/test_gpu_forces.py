@@ -239,3 +239,60 @@ def test_nonfinite_flag_on_coincident_ions(api):
     f = api.coulomb_forces(dev(x), dev(z), dev(z), dev(q), eps2=1e-14)
     assert api.poll_flags() == 0
     assert np.isfinite(np.stack([t.cpu().numpy() for t in f])).all()
+
+
+@pytest.mark.parametrize("p,jl", [(2, 256), (4, 512), (8, 512), (6, 1024)])
+def test_energy_on_the_symmetric_stage(api, oracle, p, jl):
+    """coulomb_energy on the Newton's-third-law tiles (the potential summed
+    as a fourth component, its reactions with the same sign): ragged sizes,
+    mixed charges and ions grouped by species, against the oracle."""
+    from _gpu_util import dev
+    for k, n in enumerate([2, 3, 129, 513, 1000, 2049, 4001]):
+        g = np.random.Generator(np.random.PCG64(9100 + n))
+        d = dict(x=g.normal(0, 20e-6, n), y=g.normal(0, 20e-6, n), z=g.normal(0, 60e-6, n))
+        if k % 2:
+            d["q"] = inputs.E_CHARGE * g.choice([1.0, 2.0, -1.0], n)
+        else:
+            d["q"] = np.full(n, inputs.E_CHARGE)
+            d["q"][int(0.7 * n):] = 2.0 * inputs.E_CHARGE
+        eps2 = (1e-7) ** 2 if n % 2 else 0.0
+        ref, _ = oracle.coulomb_energy(d["x"], d["y"], d["z"], d["q"], eps2=eps2)
+        for prec, tol in (("fp64", 1e-12), ("mixed", 1e-9)):
+            api.set_config("energy", n, prec, p=p, wg=4, splits=jl, algo=2)
+            try:
+                u = float(api.coulomb_energy(*(dev(d[c]) for c in "xyzq"), eps2=eps2, prec=prec)[0])
+            finally:
+                api.reset_config("energy", n, prec)
+            assert abs(u - ref) <= tol * abs(ref), (p, jl, n, prec, u, ref)
+    api.clear_workspace_cache()
+
+
+def test_energy_records_on_the_symmetric_stage(api, oracle):
+    """md_run at 20000 ions with an energy record every step: the recording
+    steps take the Newton's-third-law stage with the potential (no direct
+    fallback), records and state against the oracle's envelope; and
+    coulomb_trap_grad's energy on the same stage."""
+    from _gpu_util import dev, state_host, state_tensors
+    n = 20000
+    d = inputs.cloud1024(n=n, seed=21)
+    st = inputs.state9(d)
+    assert api.get_config("md_run", n, "fp64")["algo"] == 2
+    nsteps = 4
+    ref, en_ref, _ = oracle.md_run(st, d["q"], d["m"], d["trap"], 0.0, d["dt"], nsteps, every=1)
+    perm = np.arange(n)[::-1]
+    alt, en_alt, _ = oracle.md_run(st[:, perm], d["q"][perm], d["m"][perm], d["trap"], 0.0, d["dt"], nsteps, every=1)
+    alt = alt[:, np.argsort(perm)]
+    ts = state_tensors(st)
+    en = api.md_run(ts, dev(d["q"]), dev(d["m"]), d["trap"], 0.0, d["dt"], nsteps, every=1)
+    got = state_host(ts)
+    for blk in (slice(0, 3), slice(3, 6), slice(6, 9)):
+        D = np.abs(alt[blk] - ref[blk]).max()
+        assert np.abs(got[blk] - ref[blk]).max() <= 10 * D + 1e-13 * np.abs(ref[blk]).max(), blk
+    en = en.cpu().numpy()[0]
+    print(f"[records n={n}] max energy err {np.abs(en - en_ref).max(axis=0)}", flush=True)
+    assert np.all(np.abs(en - en_ref) <= 10 * np.abs(en_alt - en_ref) + 1e-12 * np.abs(en_ref).max(axis=0))
+    # the gradient's energy (U_C + U_trap) on the same stage
+    _, u = api.coulomb_trap_grad(*(dev(d[c]) for c in "xyzq"), dev(d["m"]), d["trap"], 0.0, energy=True)
+    uref = oracle.coulomb_energy(d["x"], d["y"], d["z"], d["q"])[0] + \
+        oracle.trap_energy(d["x"], d["y"], d["z"], d["m"], d["trap"], 0.0)
+    assert abs(float(u[0]) - uref) <= 1e-12 * abs(uref)

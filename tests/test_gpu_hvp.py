@@ -52,17 +52,17 @@ def test_hvp_matches_oracle(api, oracle, n, nvec, with_trap):
         assert err.max() <= tol
 
 
-HVP_SYM_SHAPES = [(1, 64), (2, 128), (2, 512), (4, 256), (1, 256), (4, 64)]
+HVP_SYM_SHAPES = [(1, 64, 4), (2, 128, 4), (2, 512, 2), (4, 256, 1), (1, 256, 2), (4, 64, 4)]
 HVP_SIZES = [2, 65, 129, 130, 257, 1000, 2049, 4097]
 
 
-@pytest.mark.parametrize("p,jl", HVP_SYM_SHAPES)
-def test_hvp_symmetric_ragged_sizes(api, oracle, p, jl):
+@pytest.mark.parametrize("p,jl,nvmax", HVP_SYM_SHAPES)
+def test_hvp_symmetric_ragged_sizes(api, oracle, p, jl, nvmax):
     """The Newton's-third-law HVP (each unordered pair once, reactions summed
-    over the wave): i-blocks of 64 p, j-segments of jl, ragged blocks and
-    segments, 1, 3 and 8 vectors (passes of 4, 2 and 1), mixed charges and
-    ions grouped by species, with and without the trap term; every ion of
-    every vector against the oracle."""
+    over the wave): i-blocks of 64 p, j-segments of jl, at most nvmax vectors
+    per pass, ragged blocks and segments, 1, 3 and 8 vectors (passes of 4, 2
+    and 1), mixed charges and ions grouped by species, with and without the
+    trap term; every ion of every vector against the oracle."""
     from _gpu_util import dev, host
     for k, n in enumerate(HVP_SIZES):
         g = np.random.Generator(np.random.PCG64(700 + n))
@@ -79,7 +79,7 @@ def test_hvp_symmetric_ragged_sizes(api, oracle, p, jl):
         eps2 = (1e-7) ** 2 if n % 2 else 0.0
         ref = oracle.hvp(*pos, q, v, m=m if trap else None, trap=trap, t=1.3e-8, eps2=eps2)
         for prec, tol in (("fp64", 1e-12), ("mixed", 1e-8)):
-            api.set_config("hvp", n, prec, p=p, wg=4, splits=jl, algo=2)
+            api.set_config("hvp", n, prec, p=p, wg=nvmax, splits=jl, algo=2)
             try:
                 hv = host(api.coulomb_hvp(dev(pos[0]), dev(pos[1]), dev(pos[2]), dev(q), dev(v),
                                           dev(m) if trap else None, trap, 1.3e-8, eps2=eps2, prec=prec))
@@ -92,9 +92,10 @@ def test_hvp_symmetric_ragged_sizes(api, oracle, p, jl):
 
 
 def test_hvp_default_launch_is_newtons_third_law_at_8192(api):
-    cfg = api.get_config("hvp", 8192, "fp64")
-    assert (cfg["algo"], cfg["p"], cfg["splits"]) == (2, 2, 128)
-    assert api.get_config("hvp", 4095, "fp64")["algo"] == 0
+    for op in ("hvp", "adjoint"):
+        cfg = api.get_config(op, 8192, "fp64")
+        assert (cfg["algo"], cfg["p"], cfg["wg"], cfg["splits"]) == (2, 2, 4, 128)
+        assert api.get_config(op, 4095, "fp64")["algo"] == 0
 
 
 def test_hvp_exact_identities(api, oracle):
@@ -240,3 +241,27 @@ def test_damped_md_minimiser_reaches_the_lbfgs_chain(api):
     zb = np.sort(rb[2].cpu().numpy())
     assert np.max(np.abs(za - zb)) <= 1e-7 * np.max(np.abs(za))
     assert np.max(np.abs(rb[:2].cpu().numpy())) <= 1e-9 * np.max(np.abs(za))
+
+
+@pytest.mark.parametrize("p,jl", [(1, 64), (2, 128)])
+def test_trajectory_gradient_on_the_symmetric_hvp(api, oracle, p, jl):
+    """md_adjoint_step with its Coulomb product on the Newton's-third-law
+    tiles (the default from 4096 ions, forced here at 300): the checkpointed
+    adjoint gradient against the oracle's discrete adjoint."""
+    from paper_2106_11143_amd import drivers
+    from _gpu_util import dev
+    n = 300
+    d = inputs.crystal8192(n=n, seed=22)
+    trap = d["trap"]
+    st = inputs.state9(d)
+    dt, nsteps = 1e-9, 80
+    api.set_config("adjoint", n, "fp64", p=p, wg=1, splits=jl, algo=2)
+    try:
+        L, g, _ = drivers.traj_grad(dev(st), dev(d["q"]), dev(d["m"]), trap, dt, nsteps, checkpoint_every=25)
+    finally:
+        api.reset_config("adjoint", n, "fp64")
+    Lr, gr = oracle.msd_grad(st[:6], d["q"], d["m"], trap, dt, nsteps)
+    g = g.cpu().numpy()
+    print(f"[traj_grad sym p={p} jl={jl}] L {L:.6e} vs {Lr:.6e}; grad {g} vs {gr}", flush=True)
+    assert L == pytest.approx(Lr, rel=1e-10)
+    assert np.allclose(g, gr, rtol=1e-8, atol=1e-12 * np.abs(gr).max())
