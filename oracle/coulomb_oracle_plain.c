@@ -18,6 +18,25 @@
 #define ORP_PI 3.14159265358979323846
 static const double ORP_EPS0 = 8.8541878128e-12; /* F/m, CODATA 2018 */
 
+/* Sum over j of q_j (r_i - r_j) / (|r_i - r_j|^2 + eps2)^{3/2} for j in
+ * [j0, j1), added to acc[3]: one square root and one division per pair. */
+static inline void orp_row(const double* x, const double* y, const double* z, const double* q, double eps2,
+                           double xi, double yi, double zi, int64_t j0, int64_t j1, double acc[3]) {
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int64_t j = j0; j < j1; ++j) {
+        const double dx = xi - x[j], dy = yi - y[j], dz = zi - z[j];
+        const double r2 = dx * dx + dy * dy + dz * dz + eps2;
+        const double inv_r = 1.0 / sqrt(r2);
+        const double s = q[j] * (inv_r * inv_r * inv_r);
+        sx += dx * s;
+        sy += dy * s;
+        sz += dz * s;
+    }
+    acc[0] += sx;
+    acc[1] += sy;
+    acc[2] += sz;
+}
+
 /* Forces on ions i0 .. i1-1 against all n ions, written to f?[i - i0].
  * Returns the number of threads used. */
 int orp_forces_range(int64_t n, const double* x, const double* y, const double* z, const double* q,
@@ -38,30 +57,13 @@ int orp_forces_range(int64_t n, const double* x, const double* y, const double* 
 #endif
 #pragma omp for schedule(static)
         for (int64_t i = i0; i < i1; ++i) {
-            const double xi = x[i], yi = y[i], zi = z[i];
-            double ax = 0.0, ay = 0.0, az = 0.0;
-            for (int64_t j = 0; j < i; ++j) {
-                double dx = xi - x[j], dy = yi - y[j], dz = zi - z[j];
-                double r2inv = dx * dx + dy * dy + dz * dz + eps2;
-                r2inv = 1.0 / sqrt(r2inv);
-                r2inv = r2inv * r2inv * r2inv * q[j];
-                ax += dx * r2inv;
-                ay += dy * r2inv;
-                az += dz * r2inv;
-            }
-            for (int64_t j = i + 1; j < n; ++j) {
-                double dx = xi - x[j], dy = yi - y[j], dz = zi - z[j];
-                double r2inv = dx * dx + dy * dy + dz * dz + eps2;
-                r2inv = 1.0 / sqrt(r2inv);
-                r2inv = r2inv * r2inv * r2inv * q[j];
-                ax += dx * r2inv;
-                ay += dy * r2inv;
-                az += dz * r2inv;
-            }
+            double acc[3] = {0.0, 0.0, 0.0};
+            orp_row(x, y, z, q, eps2, x[i], y[i], z[i], 0, i, acc);      /* j < i */
+            orp_row(x, y, z, q, eps2, x[i], y[i], z[i], i + 1, n, acc);  /* j > i: the self pair skipped */
             const double c = kc * q[i];
-            fx[i - i0] = c * ax;
-            fy[i - i0] = c * ay;
-            fz[i - i0] = c * az;
+            fx[i - i0] = c * acc[0];
+            fy[i - i0] = c * acc[1];
+            fz[i - i0] = c * acc[2];
         }
     }
     return used;
