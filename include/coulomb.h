@@ -141,7 +141,8 @@ typedef struct {
 } cb_state;
 
 /* Size in bytes of the workspace the call `op` needs for n ions (n_total for
- * md_run), nrun runs, nvec HVP vectors and precision prec.  0 on bad input.
+ * md_run), nrun runs, nvec HVP vectors and precision prec.  0 on bad input
+ * (including n outside [1, 2^28], the range every entry point accepts).
  * For md_run with nrun > 1 it covers both ensemble paths for any split of
  * n_total into nrun runs of at most 4096 ions (about 0.5 KB per ion). */
 size_t cb_workspace_size(int32_t op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec);
@@ -321,7 +322,9 @@ cb_status cb_load_tuning(const char* cache_path);
  *          j's per reduction group (algorithm 1),
  * out[3] = j-splits (algorithm 0), j-segment length (algorithms 1, 2) or
  *          j-parts per 64 ions (algorithm 3),
- * out[4] = 1 if it came from tuning or cb_set_config. */
+ * out[4] = 1 if it came from tuning or cb_set_config.
+ * CB_EINVAL for a NULL out, n outside [1, 2^28], or an op or prec outside
+ * its enum. */
 cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]);
 
 /* Forces the launch configuration for (op, n power-of-two bucket, prec), with
@@ -337,7 +340,8 @@ cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]);
  * splits = 1 (the persistent kernel's fixed shape), or algorithm 2 with p in
  * {4, 8}, wg = 4, splits = JL in {256, 512}.
  * algo = p = wg = splits = 0 removes a forced or tuned entry (back to the
- * built-in heuristic).  CB_EINVAL if unsupported. */
+ * built-in heuristic).  CB_EINVAL if unsupported, or for n outside [1, 2^28]
+ * or an op or prec outside its enum. */
 cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t algo, int32_t p, int32_t wg, int32_t splits);
 
 #ifdef __cplusplus

@@ -262,7 +262,9 @@ cb_status cb_load_tuning(const char* cache_path) {
                         "\"wg\": %d, \"splits\": %d, \"algo\": %d",
                         a, &op, &prec, &bucket, &n, &p, &wg, &sp, &algo) < 8)
             continue;
-        if (arch != a || op < 0 || op > CB_OP_ADJOINT || n < 1) continue;
+        if (arch != a || op < 0 || op > CB_OP_ADJOINT || prec < 0 || prec > CB_MIXED_F32D || n < 1 ||
+            n > kMaxIons)
+            continue;
         LaunchCfg c{p, wg, sp, 1, algo};
         if (!valid_cfg(op, c)) continue;
         if (op == CB_OP_FORCES || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN) {

@@ -65,12 +65,17 @@ static std::map<long long, LaunchCfg> g_cfg;
 
 int n_bucket(int64_t n) {
     int b = 0;
-    while ((int64_t(1) << b) < n) ++b;
-    return b;
+    while (b < 62 && (int64_t(1) << b) < n) ++b;
+    return (int64_t(1) << b) < n ? 63 : b;
 }
 
+// (op, precision, size bucket) -> table key; op and precision are taken as
+// unsigned fields, so an out-of-range value from a caller or a tuning file
+// gives a key of its own rather than an undefined shift
 static long long cfg_key(int op, int prec, int64_t n) {
-    return ((long long)op << 40) | ((long long)prec << 32) | (long long)n_bucket(n);
+    const unsigned long long k = ((unsigned long long)(uint16_t)op << 40) | ((unsigned long long)(uint8_t)prec << 32) |
+                                 (unsigned long long)n_bucket(n);
+    return (long long)k;
 }
 
 // Heuristic default (measured on MI355X at n = 1e5): one i-particle per
@@ -210,6 +215,9 @@ static size_t al(size_t b) { return (b + 255) / 256 * 256; }
 
 WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec) {
     WsLayout L{};
+    // entry points size the workspace before they check n: keep the sizing
+    // arithmetic in range for any n (the call then fails on n itself)
+    n = std::min<int64_t>(std::max<int64_t>(n, 1), kMaxIons);
     const size_t N = (size_t)n;
     const size_t nv = (size_t)std::max(1, (int)nvec);
     size_t off = 0;
@@ -293,13 +301,16 @@ extern "C" {
 const char* cb_last_error(void) { return t_err.c_str(); }
 
 size_t cb_workspace_size(int32_t op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec) {
-    if (n < 1 || op < 0 || op == CB_OP_MD_ENSEMBLE || op > CB_OP_GRAD || prec < 0 || prec > CB_MIXED_F32D) return 0;
+    if (n < 1 || n > kMaxIons || op < 0 || op == CB_OP_MD_ENSEMBLE || op > CB_OP_GRAD || prec < 0 ||
+        prec > CB_MIXED_F32D)
+        return 0;
     if (op == CB_OP_HVP && (nvec < 1 || nvec > kMaxVec)) return 0;
     return ws_layout(op, n, nrun, nvec, prec).total;
 }
 
 cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]) {
-    if (!out || n < 1 || op < 0 || op > CB_OP_MD_ENSEMBLE) return fail(CB_EINVAL, "cb_get_config: bad argument");
+    if (!out || n < 1 || n > kMaxIons || op < 0 || op > CB_OP_MD_ENSEMBLE || prec < 0 || prec > CB_MIXED_F32D)
+        return fail(CB_EINVAL, "cb_get_config: bad argument");
     LaunchCfg c = get_cfg(op, n, prec);
     out[0] = c.algo;
     out[1] = c.p;
@@ -310,7 +321,8 @@ cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]) {
 }
 
 cb_status cb_set_config(int32_t op, int64_t n, int32_t prec, int32_t algo, int32_t p, int32_t wg, int32_t splits) {
-    if (n < 1 || op < 0 || op > CB_OP_MD_ENSEMBLE) return fail(CB_EINVAL, "cb_set_config: bad argument");
+    if (n < 1 || n > kMaxIons || op < 0 || op > CB_OP_MD_ENSEMBLE || prec < 0 || prec > CB_MIXED_F32D)
+        return fail(CB_EINVAL, "cb_set_config: bad argument");
     if (algo == 0 && p == 0 && wg == 0 && splits == 0) {
         drop_cfg(op, n, prec);
         return ok();

@@ -23,7 +23,7 @@ static bool overlaps(const void* a, const void* b, int64_t n) {
 
 static cb_status check_common(const char* who, int64_t n, int32_t prec, double eps2, void* ws, size_t ws_bytes,
                               size_t need) {
-    if (n < 1 || n > (int64_t(1) << 28)) return fail(CB_EINVAL, "%s: n = %lld out of range [1, 2^28]", who, (long long)n);
+    if (n < 1 || n > kMaxIons) return fail(CB_EINVAL, "%s: n = %lld out of range [1, 2^28]", who, (long long)n);
     if (prec < CB_FP64 || prec > CB_MIXED_F32D) return fail(CB_EINVAL, "%s: unknown precision %d", who, prec);
     if (!(eps2 >= 0.0) || !std::isfinite(eps2)) return fail(CB_EINVAL, "%s: eps2 must be finite and >= 0", who);
     if (!ws) return fail(CB_EINVAL, "%s: workspace is NULL", who);

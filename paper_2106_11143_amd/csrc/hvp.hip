@@ -287,7 +287,7 @@ static bool overl(const void* a, const void* b, size_t bytes_a, size_t bytes_b) 
 
 static cb_status hvp_common(const char* who, int64_t n, int32_t prec, double eps2, void* ws, size_t ws_bytes,
                             size_t need) {
-    if (n < 1 || n > (int64_t(1) << 28)) return fail(CB_EINVAL, "%s: n = %lld out of range", who, (long long)n);
+    if (n < 1 || n > kMaxIons) return fail(CB_EINVAL, "%s: n = %lld out of range [1, 2^28]", who, (long long)n);
     if (prec == CB_MIXED_F32D) return fail(CB_EUNSUPPORTED, "%s: CB_MIXED_F32D is for the forces only", who);
     if (prec < CB_FP64 || prec > CB_FP32_RSQ) return fail(CB_EINVAL, "%s: unknown precision %d", who, prec);
     if (!(eps2 >= 0.0) || !std::isfinite(eps2)) return fail(CB_EINVAL, "%s: eps2 must be finite and >= 0", who);

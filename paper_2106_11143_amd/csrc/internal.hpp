@@ -17,6 +17,7 @@ constexpr int kBatchGridMax = 2048;  // workgroups of one batched launch (force 
 constexpr int kBatchWG = 512;        // threads per workgroup of the persistent batched kernel
 constexpr int kBatchP = 4;           // ions per thread and register group in that kernel
 constexpr int kEpiBlock = 256;       // threads per element-wise block
+constexpr int64_t kMaxIons = int64_t(1) << 28;  // largest n any entry point accepts
 constexpr int64_t kSymMaxN = int64_t(1) << 18;  // largest n for the symmetric kernel (partials grow as n^2)
 constexpr int kMaxDevices = 64;      // GPUs per process the per-device symbol tables hold
 
