@@ -40,7 +40,7 @@ sys.path.insert(0, ROOT)
 # on the Newton's-third-law stage: the work the kernel performs, not a dense-equivalent count.
 FLOPS_PER_PAIR = 20
 FLOPS_PER_SYM_PAIR = 27
-SYM_ALGOS = (1, 2)
+SYM_ALGOS = (1, 2, 4)
 
 
 # Hessian-vector products, counted the same way, per ordered pair and B vectors: geometry and
@@ -75,6 +75,9 @@ STAGE_KERNELS = {
     2: "force stage cb::k_sym_plan + cb::k_pair_sym<FP64> + cb::k_sym_finish<FP64> (each unordered pair "
        "evaluated once and applied to both ions, reactions summed through LDS; tile partials summed in fixed "
        "order)",
+    4: "force stage cb::k_sym_plan + cb::k_pair_sym_rows<FP64> + cb::k_sym_finish<FP64> (each unordered pair "
+       "evaluated once and applied to both ions; four i-blocks per workgroup share each j-segment and add their "
+       "reactions in LDS before one store; tile partials summed in fixed order)",
 }
 
 
@@ -118,7 +121,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (rocprofv3 counter calibration)")
     ap.add_argument("--workload", default="cloud100k",
-                    choices=["cloud100k", "cloud1024", "rf32768", "kz512", "crystal8192", "hvp8192", "rsqrt_sweep"],
+                    choices=["cloud100k", "cloud1024", "rf32768", "kz512", "crystal8192", "hvp8192", "rsqrt_sweep",
+                             "recording", "uniform_tiles"],
                     help="cloud100k is the headline; the others time the remaining workloads")
     ap.add_argument("--no-extras", action="store_true",
                     help="cloud100k: only the timed legs (steps, force stage, mixed), no error or 200-step legs "
@@ -126,6 +130,10 @@ def main():
     ap.add_argument("--ungrouped", action="store_true",
                     help="time cloud100k in its seeded ion order (species interleaved) instead of grouped by "
                          "species")
+    ap.add_argument("--algo", type=int, choices=[1, 2, 4], default=None,
+                    help="force one Newton's-third-law variant for cloud100k (1: reactions by permutes, 2: through "
+                         "LDS, one wave per tile; 4: four i-blocks per workgroup sharing each j-segment) at the "
+                         "default tile shape")
     ap.add_argument("--direct", action="store_true",
                     help="force the direct kernel (every ordered pair, j-split partials) instead of the "
                          "default Newton's-third-law stage, at the direct kernel's default launch")
@@ -158,6 +166,12 @@ def main():
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
     q, m = dev(d["q"]), dev(d["m"])
     trap, dt = d["trap"], d["dt"]
+    if args.algo is not None:
+        for op in ("md_run", "forces", "energy"):
+            for prec in ("fp64", "mixed"):
+                c = api.get_config(op, n, prec)
+                api.set_config(op, n, prec, p=c["p"] if c["algo"] in (1, 2, 4) else 8, wg=4,
+                               splits=c["splits"] if c["algo"] in (1, 2, 4) else 512, algo=args.algo)
     if args.direct:
         waves = -(-n // 64)
         splits = max(1, min(64, -(-65536 // waves), max(1, n // 64)))
@@ -776,6 +790,85 @@ def bench_rsqrt_sweep(args):
                  {"variants": variants, "table": rows})
 
 
+def bench_recording(args):
+    """Energy-recording steps against plain steps on cloud100k (grouped by
+    species, FP64, default launch): md_run of --steps steps without records
+    and with a record every step, alternated three times after a clock
+    pre-warm; the line's value is the recording step's rate."""
+    np, torch, api, inputs, dev = _setup()
+    d = inputs.group_by_charge(inputs.cloud100k())
+    st = inputs.state9(d)
+    ts = [dev(st[k]) for k in range(9)]
+    q, m = dev(d["q"]), dev(d["m"])
+    x, y, z = (dev(d[k]) for k in "xyz")
+    prewarm(torch, lambda: api.coulomb_pair_stage(x, y, z, q), 1.0)
+    api.md_run(ts, q, m, d["trap"], 0.0, d["dt"], 0, init_accel=True)
+    K = args.steps if args.steps != 50 else 30
+    rows = []
+    for _ in range(3):
+        for every in (0, 1):
+            e0, e1 = _timer(torch)
+            e0.record()
+            api.md_run(ts, q, m, d["trap"], 0.0, d["dt"], K, init_accel=False, every=every)
+            e1.record()
+            torch.cuda.synchronize()
+            rows.append({"every": every, "ms_per_step": e0.elapsed_time(e1) / K})
+            print(f"md_run cloud100k every={every}: {rows[-1]['ms_per_step']:.4f} ms per step", file=sys.stderr,
+                  flush=True)
+    plain = [r["ms_per_step"] for r in rows if r["every"] == 0]
+    rec = [r["ms_per_step"] for r in rows if r["every"] == 1]
+    n = d["n"]
+    return _line("pair interactions/s (FP64 velocity-Verlet steps recording the energies)",
+                 float(n) * n / (np.mean(rec) * 1e-3), "pairs/s", K, 0, float(np.mean(rec)),
+                 "cloud100k grouped by species: md_run steps with an energy record every step vs none",
+                 {"plain_ms_per_step": plain, "recording_ms_per_step": rec,
+                  "recording_over_plain": float(np.mean(rec) / np.mean(plain))})
+
+
+def bench_uniform_tiles(args):
+    """The charge-free tile loop on the single-species workloads: rf32768's
+    force stage (3 evaluations) and 3 kz512 md_run steps, first with their
+    uniform charges, then with every other charge scaled by 1 + 1e-7 (no tile
+    uniform: the per-j charge path everywhere), for counter runs and times."""
+    np, torch, api, inputs, dev = _setup()
+    d = inputs.rf32768()
+    x, y, z = (dev(d[k]) for k in "xyz")
+    qm = d["q"].copy()
+    qm[1::2] *= 1 + 1e-7
+    res = {}
+    for tag, q in (("uniform", dev(d["q"])), ("perturbed", dev(qm))):
+        api.coulomb_pair_stage(x, y, z, q)
+        torch.cuda.synchronize()
+        e0, e1 = _timer(torch)
+        e0.record()
+        for _ in range(3):
+            api.coulomb_pair_stage(x, y, z, q)
+        e1.record()
+        torch.cuda.synchronize()
+        res[f"rf32768_{tag}_stage_ms"] = e0.elapsed_time(e1) / 3
+    k = inputs.kz512(nsteps=3)
+    st0 = inputs.state9(k)
+    m = dev(k["m"])
+    for tag in ("uniform", "perturbed"):
+        q = k["q"].copy()
+        if tag == "perturbed":
+            q[1::2] *= 1 + 1e-7
+        ts = [dev(st0[c]) for c in range(9)]
+        torch.cuda.synchronize()
+        e0, e1 = _timer(torch)
+        e0.record()
+        api.md_run(ts, dev(q), m, k["traps"], 0.0, k["dt"], 3, offsets=k["offsets"])
+        e1.record()
+        torch.cuda.synchronize()
+        res[f"kz512_{tag}_ms_per_step"] = e0.elapsed_time(e1) / 3
+    n = d["n"]
+    return _line("pair interactions/s (rf32768 force stage, charge-free tiles)",
+                 float(n) * n / (res["rf32768_uniform_stage_ms"] * 1e-3), "pairs/s", 3, 1,
+                 res["rf32768_uniform_stage_ms"],
+                 "rf32768 force stage and kz512 steps, uniform charges vs every other charge scaled by 1+1e-7",
+                 res)
+
+
 OTHER_WORKLOADS = {
     "cloud1024": lambda a: bench_md_single(a, "cloud1024"),
     "rf32768": lambda a: bench_md_single(a, "rf32768"),
@@ -783,6 +876,8 @@ OTHER_WORKLOADS = {
     "crystal8192": bench_crystal,
     "hvp8192": bench_hvp,
     "rsqrt_sweep": bench_rsqrt_sweep,
+    "recording": bench_recording,
+    "uniform_tiles": bench_uniform_tiles,
 }
 
 

@@ -128,14 +128,16 @@ cb_status cb_autotune(int32_t op, int64_t n, int32_t prec, const char* cache_pat
     if (rc == CB_OK && force_op && n <= kSymMaxN) {
         size_t need = 0;
         for (int p : kSymP)
-            for (int jl : kSymJL) need = std::max(need, sym_ws_bytes(n, p, jl));
+            for (int jl : kSymJL)
+                need = std::max({need, sym_ws_bytes(n, p, jl), sym_ws_bytes(n, p, jl, false, kSymRows)});
         DevBuf sws, F;
         if (hipMalloc(&sws.p, need) != hipSuccess || hipMalloc(&F.p, sizeof(double) * 3 * (size_t)n) != hipSuccess)
             rc = fail(CB_EHIP, "cb_autotune: allocation failed");
-        for (int algo : {ALGO_SYM, ALGO_SYM_LDS})
+        for (int algo : {ALGO_SYM, ALGO_SYM_LDS, ALGO_SYM_ROWS})
         for (int p : kSymP)
             for (int jl : kSymJL) {
                 if (rc) break;
+                if (algo == ALGO_SYM_ROWS && !sym_rows_p_ok(p)) continue;
                 LaunchCfg c{p, kSymGroup, jl, 1, algo};
                 auto launch = [&]() {
                     return launch_pair_sym(prec, c, (int)n, x, y, z, q, 0.0, sws.p, static_cast<double*>(F.p), st);

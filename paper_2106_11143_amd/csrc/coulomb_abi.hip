@@ -191,6 +191,7 @@ bool valid_cfg(int op, const LaunchCfg& c) {
                (c.algo == ALGO_SYM_LDS && c.wg == kSymGroup && ens_cfg_ok(c.p, c.splits));
     const bool force_op = sym_op(op);
     const bool hv_op = (op == CB_OP_HVP || op == CB_OP_ADJOINT);
+    if (c.algo == ALGO_SYM_ROWS) return force_op && sym_cfg_ok(c.p, c.wg, c.splits) && sym_rows_p_ok(c.p);
     if (is_sym(c.algo))
         return (force_op && sym_cfg_ok(c.p, c.wg, c.splits)) ||
                (hv_op && c.algo == ALGO_SYM_LDS && (c.wg == 1 || c.wg == 2 || c.wg == 4) &&
@@ -238,15 +239,16 @@ WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec) 
         if (cfg_op == CB_OP_ENERGY) {  // coulomb_trap_grad: the forces' stage too
             const LaunchCfg f = get_cfg(CB_OP_FORCES, n, prec);
             if (is_sym(f.algo) && sym_cfg_ok(f.p, f.wg, f.splits) &&
-                (!is_sym(c.algo) || sym_ws_bytes(n, f.p, f.splits, true) > sym_ws_bytes(n, c.p, c.splits, true)))
+                (!is_sym(c.algo) || sym_ws_bytes(n, f.p, f.splits, true, sym_rows(f.algo)) >
+                                        sym_ws_bytes(n, c.p, c.splits, true, sym_rows(c.algo))))
                 c = f;
         }
         if (force_op && n <= kSymMaxN && is_sym(c.algo) && sym_cfg_ok(c.p, c.wg, c.splits))
             // the configured symmetric stage: finished forces [3][n] then its tiles and partials
-            part = std::max(part, al(sizeof(double) * 3 * N) + sym_ws_bytes(n, c.p, c.splits, pot));
+            part = std::max(part, al(sizeof(double) * 3 * N) + sym_ws_bytes(n, c.p, c.splits, pot, sym_rows(c.algo)));
         if (hv && is_sym(c.algo) && hvp_sym_cfg_ok(c.p, c.splits))  // (the adjoint's product [3][n] first)
             part = std::max(part, (op == CB_OP_ADJOINT ? al(sizeof(double) * 3 * N) : 0) +
-                                      hvp_sym_ws_bytes(n, c.p, c.splits));
+                                      hvp_sym_ws_bytes(n, c.p, c.splits, hvp_sym_passes((int)nv, c.wg)));
         off += al(part);
         L.ppot = off;
         if (op == CB_OP_ENERGY || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN)

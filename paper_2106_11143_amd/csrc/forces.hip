@@ -325,7 +325,7 @@ cb_status coulomb_forces_noalloc(int64_t n, const double* x, const double* y, co
     const LaunchCfg cfg = get_cfg(CB_OP_FORCES, n, prec);
     const size_t fbytes = al256(sizeof(double) * 3 * (size_t)n);
     const bool sym = is_sym(cfg.algo) && n <= kSymMaxN && prec != CB_MIXED_F32D &&
-                     fbytes + sym_ws_bytes(n, cfg.p, cfg.splits) <= kScratchBytes;
+                     fbytes + sym_ws_bytes(n, cfg.p, cfg.splits, false, sym_rows(cfg.algo)) <= kScratchBytes;
     int S = 1;
     if (sym) {
         if ((rc = launch_pair_sym(prec, cfg, (int)n, x, y, z, q, eps2, static_cast<char*>(ws) + fbytes, part, st)))

@@ -61,108 +61,117 @@ cb_status launch_hvp(int prec, const LaunchCfg& c, int nvec, int n, const double
 // ------------------------------------------- Newton's third law (hvp_sym.hpp)
 static size_t al256h(size_t b) { return (b + 255) / 256 * 256; }
 
-// tile table | Pi[T][4][3][IB] | R[T][4][3][JL] | packed j records [n][16]
-size_t hvp_sym_ws_bytes(int64_t n, int p, int jl) {
+// tile table | Pi[npass T][4][3][IB] | R[npass T][4][3][JL] | packed j
+// records [npass][n][16] (npass passes of at most 4 vectors in one launch)
+size_t hvp_sym_ws_bytes(int64_t n, int p, int jl, int npass) {
     const int IB = 64 * p;
     const int64_t T = sym_tiles(n, IB, jl);
-    return sym_plan_bytes(n, IB, jl) + al256h(sizeof(double) * 12 * (size_t)IB * (T + 1)) +
-           al256h(sizeof(double) * 12 * (size_t)jl * (T + 1)) + al256h(sizeof(double) * kHvpRec * (size_t)n);
+    const size_t np = (size_t)npass;
+    return sym_plan_bytes(n, IB, jl) + al256h(sizeof(double) * 12 * (size_t)IB * (np * T + 1)) +
+           al256h(sizeof(double) * 12 * (size_t)jl * (np * T + 1)) +
+           al256h(sizeof(double) * kHvpRec * np * (size_t)n);
 }
 
 template <int PREC, int P, int NV>
-static void go_hvp_sym(int n, const SymPlan& pl, int JL, const double* x, const double* y, const double* z,
-                       const double* q, const double* v, const double* J, double eps2, double* Pi, double* R,
-                       hipStream_t st) {
-    k_hvp_sym<PREC, P, NV><<<(unsigned)pl.T, 64, 0, st>>>(n, x, y, z, q, v, J, eps2, JL, pl.tiles, Pi, R);
+static void go_hvp_sym(int npass, int n, const SymPlan& pl, int JL, const double* x, const double* y,
+                       const double* z, const double* q, const double* v, const double* J, double eps2, double* Pi,
+                       double* R, hipStream_t st) {
+    const dim3 g((unsigned)pl.T, (unsigned)npass);
+    k_hvp_sym<PREC, P, NV><<<g, 64, 0, st>>>(n, x, y, z, q, v, J, eps2, JL, pl.tiles, Pi, R);
 }
 
 template <int PREC, int NV>
-static bool go_hvp_sym_p(int P, int n, const SymPlan& pl, int JL, const double* x, const double* y, const double* z,
-                         const double* q, const double* v, const double* J, double eps2, double* Pi, double* R,
-                         hipStream_t st) {
+static bool go_hvp_sym_p(int P, int npass, int n, const SymPlan& pl, int JL, const double* x, const double* y,
+                         const double* z, const double* q, const double* v, const double* J, double eps2, double* Pi,
+                         double* R, hipStream_t st) {
     switch (P) {
-        case 1: go_hvp_sym<PREC, 1, NV>(n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st); return true;
-        case 2: go_hvp_sym<PREC, 2, NV>(n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st); return true;
-        case 4: go_hvp_sym<PREC, 4, NV>(n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st); return true;
+        case 1: go_hvp_sym<PREC, 1, NV>(npass, n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st); return true;
+        case 2: go_hvp_sym<PREC, 2, NV>(npass, n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st); return true;
+        case 4: go_hvp_sym<PREC, 4, NV>(npass, n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st); return true;
         default: return false;
     }
 }
 
 template <int PREC>
-static bool go_hvp_sym_nv(int nv, int P, int n, const SymPlan& pl, int JL, const double* x, const double* y,
-                          const double* z, const double* q, const double* v, const double* J, double eps2, double* Pi,
-                          double* R, hipStream_t st) {
+static bool go_hvp_sym_nv(int nv, int P, int npass, int n, const SymPlan& pl, int JL, const double* x,
+                          const double* y, const double* z, const double* q, const double* v, const double* J,
+                          double eps2, double* Pi, double* R, hipStream_t st) {
     switch (nv) {
-        case 1: return go_hvp_sym_p<PREC, 1>(P, n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st);
-        case 2: return go_hvp_sym_p<PREC, 2>(P, n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st);
-        case 4: return go_hvp_sym_p<PREC, 4>(P, n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st);
+        case 1: return go_hvp_sym_p<PREC, 1>(P, npass, n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st);
+        case 2: return go_hvp_sym_p<PREC, 2>(P, npass, n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st);
+        case 4: return go_hvp_sym_p<PREC, 4>(P, npass, n, pl, JL, x, y, z, q, v, J, eps2, Pi, R, st);
         default: return false;
     }
 }
 
 template <int PREC>
-static bool go_hvp_fin(int nv, unsigned nb, int n, int IB, int JL, int lgJL, const double* x, const double* y,
-                       const double* z, const double* q, const double* v, double eps2, const int* rowstart,
-                       const double* Pi, const double* R, const double* m, TrapK k, double* hv, unsigned* fl,
-                       hipStream_t st) {
-    const dim3 g(nb, nv), b(64 * kFinishParts);
+static bool go_hvp_fin(int nv, int npass, unsigned nb, int n, int IB, int JL, int lgJL, int T, const double* x,
+                       const double* y, const double* z, const double* q, const double* v, double eps2,
+                       const int* rowstart, const double* Pi, const double* R, const double* m, TrapK k, double* hv,
+                       unsigned* fl, hipStream_t st) {
+    const dim3 g(nb, (unsigned)(npass * nv)), b(64 * kFinishParts);
     switch (nv) {
-        case 1: k_hvp_sym_finish<PREC, 1><<<g, b, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, v, eps2, rowstart, Pi, R, m, k, hv, fl); return true;
-        case 2: k_hvp_sym_finish<PREC, 2><<<g, b, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, v, eps2, rowstart, Pi, R, m, k, hv, fl); return true;
-        case 4: k_hvp_sym_finish<PREC, 4><<<g, b, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, v, eps2, rowstart, Pi, R, m, k, hv, fl); return true;
+        case 1: k_hvp_sym_finish<PREC, 1><<<g, b, 0, st>>>(n, IB, JL, lgJL, T, x, y, z, q, v, eps2, rowstart, Pi, R, m, k, hv, fl); return true;
+        case 2: k_hvp_sym_finish<PREC, 2><<<g, b, 0, st>>>(n, IB, JL, lgJL, T, x, y, z, q, v, eps2, rowstart, Pi, R, m, k, hv, fl); return true;
+        case 4: k_hvp_sym_finish<PREC, 4><<<g, b, 0, st>>>(n, IB, JL, lgJL, T, x, y, z, q, v, eps2, rowstart, Pi, R, m, k, hv, fl); return true;
         default: return false;
     }
 }
 
-// nvec products in passes of 4, 2, 1 vectors: per pass the j records are
-// packed, the tiles evaluated and each ion finished (trap term included).
+// nvec products in passes of 4, 2, 1 vectors (at most c.wg per pass), up to
+// kHvpSymPasses passes of one size in one launch: per launch the j records
+// are packed, the tiles evaluated and each ion finished (trap term included).
 static cb_status launch_hvp_sym(int prec, const LaunchCfg& c, int nvec, int n, const double* x, const double* y,
                                 const double* z, const double* q, const double* v, const double* m, TrapK k,
                                 double eps2, void* ws, double* hv, unsigned* fl, hipStream_t st) {
     const int P = c.p, JL = c.splits, IB = 64 * P;
     if (!hvp_sym_cfg_ok(P, JL) || n > hvp_sym_max_n(P))
         return fail(CB_EINVAL, "coulomb_hvp: bad Newton's-third-law configuration p %d / JL %d at n = %d", P, JL, n);
+    const int nvmax = c.wg;  // the most vectors per pass: 1, 2 or 4
+    const int wsp = hvp_sym_passes(nvec, nvmax);  // the passes the workspace holds
     SymPlan pl;
     cb_status rc = sym_plan(n, IB, JL, ws, &pl, st);
     if (rc) return rc;
+    const size_t np = (size_t)wsp;
     char* base = static_cast<char*>(ws) + pl.bytes;
     double* Pi = reinterpret_cast<double*>(base);
-    base += al256h(sizeof(double) * 12 * (size_t)IB * (pl.T + 1));
+    base += al256h(sizeof(double) * 12 * (size_t)IB * (np * pl.T + 1));
     double* R = reinterpret_cast<double*>(base);
-    base += al256h(sizeof(double) * 12 * (size_t)JL * (pl.T + 1));
+    base += al256h(sizeof(double) * 12 * (size_t)JL * (np * pl.T + 1));
     double* J = reinterpret_cast<double*>(base);
     int lgJL = 0;
     while ((1 << lgJL) < JL) ++lgJL;
     const unsigned nb = (unsigned)((n + 63) / 64);
-    const int nvmax = c.wg;  // the most vectors per pass: 1, 2 or 4
     for (int b0 = 0; b0 < nvec;) {
         const int left = std::min(nvec - b0, nvmax);
         const int nv = left >= 4 ? 4 : left >= 2 ? 2 : 1;
+        const int npass = std::max(1, std::min(wsp, (nvec - b0) / nv));
         const double* vb = v + (size_t)b0 * 3 * n;
         double* hb = hv + (size_t)b0 * 3 * n;
-        k_hvp_pack<<<(n + 255) / 256, 256, 0, st>>>(n, nv, x, y, z, q, vb, J);
+        k_hvp_pack<<<dim3((n + 255) / 256, npass), 256, 0, st>>>(n, nv, x, y, z, q, vb, J);
         if ((rc = check_launch("k_hvp_pack"))) return rc;
         bool okk = false;
         if (pl.T > 0) {
             switch (prec) {
-                case PREC_FP64: okk = go_hvp_sym_nv<PREC_FP64>(nv, P, n, pl, JL, x, y, z, q, vb, J, eps2, Pi, R, st); break;
-                case PREC_MIXED: okk = go_hvp_sym_nv<PREC_MIXED>(nv, P, n, pl, JL, x, y, z, q, vb, J, eps2, Pi, R, st); break;
-                case PREC_IEEE: okk = go_hvp_sym_nv<PREC_IEEE>(nv, P, n, pl, JL, x, y, z, q, vb, J, eps2, Pi, R, st); break;
-                case PREC_FP32: okk = go_hvp_sym_nv<PREC_FP32>(nv, P, n, pl, JL, x, y, z, q, vb, J, eps2, Pi, R, st); break;
+                case PREC_FP64: okk = go_hvp_sym_nv<PREC_FP64>(nv, P, npass, n, pl, JL, x, y, z, q, vb, J, eps2, Pi, R, st); break;
+                case PREC_MIXED: okk = go_hvp_sym_nv<PREC_MIXED>(nv, P, npass, n, pl, JL, x, y, z, q, vb, J, eps2, Pi, R, st); break;
+                case PREC_IEEE: okk = go_hvp_sym_nv<PREC_IEEE>(nv, P, npass, n, pl, JL, x, y, z, q, vb, J, eps2, Pi, R, st); break;
+                case PREC_FP32: okk = go_hvp_sym_nv<PREC_FP32>(nv, P, npass, n, pl, JL, x, y, z, q, vb, J, eps2, Pi, R, st); break;
                 default: break;
             }
             if (!okk) return fail(CB_EINVAL, "coulomb_hvp: unsupported precision %d / p %d", prec, P);
             if ((rc = check_launch("k_hvp_sym"))) return rc;
         }
+        const int T = (int)pl.T;
         switch (prec) {
-            case PREC_FP64: okk = go_hvp_fin<PREC_FP64>(nv, nb, n, IB, JL, lgJL, x, y, z, q, vb, eps2, pl.rowstart, Pi, R, m, k, hb, fl, st); break;
-            case PREC_MIXED: okk = go_hvp_fin<PREC_MIXED>(nv, nb, n, IB, JL, lgJL, x, y, z, q, vb, eps2, pl.rowstart, Pi, R, m, k, hb, fl, st); break;
-            case PREC_IEEE: okk = go_hvp_fin<PREC_IEEE>(nv, nb, n, IB, JL, lgJL, x, y, z, q, vb, eps2, pl.rowstart, Pi, R, m, k, hb, fl, st); break;
-            default: okk = go_hvp_fin<PREC_FP32>(nv, nb, n, IB, JL, lgJL, x, y, z, q, vb, eps2, pl.rowstart, Pi, R, m, k, hb, fl, st); break;
+            case PREC_FP64: okk = go_hvp_fin<PREC_FP64>(nv, npass, nb, n, IB, JL, lgJL, T, x, y, z, q, vb, eps2, pl.rowstart, Pi, R, m, k, hb, fl, st); break;
+            case PREC_MIXED: okk = go_hvp_fin<PREC_MIXED>(nv, npass, nb, n, IB, JL, lgJL, T, x, y, z, q, vb, eps2, pl.rowstart, Pi, R, m, k, hb, fl, st); break;
+            case PREC_IEEE: okk = go_hvp_fin<PREC_IEEE>(nv, npass, nb, n, IB, JL, lgJL, T, x, y, z, q, vb, eps2, pl.rowstart, Pi, R, m, k, hb, fl, st); break;
+            default: okk = go_hvp_fin<PREC_FP32>(nv, npass, nb, n, IB, JL, lgJL, T, x, y, z, q, vb, eps2, pl.rowstart, Pi, R, m, k, hb, fl, st); break;
         }
         if (!okk) return fail(CB_EINVAL, "coulomb_hvp: unsupported vector count %d", nv);
         if ((rc = check_launch("k_hvp_sym_finish"))) return rc;
-        b0 += nv;
+        b0 += npass * nv;
     }
     return CB_OK;
 }

@@ -27,14 +27,17 @@ namespace cb {
 
 constexpr int kHvpRec = 16;  // doubles per packed j record: x, y, z, q, v[b][c] (b < 4)
 
-// J[i] = (x, y, z, q, v[0][0..2], ..., v[nv-1][0..2], 0 ...) for one pass of nv <= 4 vectors.
+// J[i] = (x, y, z, q, v[0][0..2], ..., v[nv-1][0..2], 0 ...) for one pass of
+// nv <= 4 vectors; pass blockIdx.y takes vectors nv blockIdx.y ... and writes
+// its records n kHvpRec doubles further on.
 __global__ void __launch_bounds__(256) k_hvp_pack(int n, int nv, const double* __restrict__ x,
                                                   const double* __restrict__ y, const double* __restrict__ z,
                                                   const double* __restrict__ q, const double* __restrict__ v,
                                                   double* __restrict__ J) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    double* r = J + (size_t)i * kHvpRec;
+    v += (size_t)blockIdx.y * nv * 3 * n;
+    double* r = J + ((size_t)blockIdx.y * n + i) * kHvpRec;
     r[0] = x[i];
     r[1] = y[i];
     r[2] = z[i];
@@ -137,7 +140,7 @@ __device__ __forceinline__ void hvp_sym_pair(const HvpJRec<NV>& J, double eps2, 
 // variants spill at most a few registers).
 template <int P, int NV>
 constexpr int hvp_sym_waves() {
-    return P == 1 ? 4 : (P == 2 ? (NV == 4 ? 2 : 4) : (NV == 1 ? 3 : 2));
+    return P == 1 ? (NV == 4 ? 3 : 4) : (P == 2 ? (NV == 4 ? 2 : (NV == 2 ? 3 : 4)) : (NV == 1 ? 3 : 2));
 }
 
 // The j loop of tile t over [j0, j1) and the stores of its partials:
@@ -158,6 +161,19 @@ __device__ __forceinline__ void hvp_sym_body(const double* __restrict__ J, doubl
         for (int b = 0; b < NV; ++b) ia[p][b][0] = ia[p][b][1] = ia[p][b][2] = 0.0;
     const SeriesK K;
     double* Rt = R + (size_t)t * NV * 3 * JL;
+    // one group's wave sums are in flight while the next group is evaluated:
+    // the loads of group pjg are requested after its evaluation and added
+    // (and stored) after the evaluation of the following group
+    double2 a[8];
+    int pjg = -1, plive = 0;
+    const int v = lane >> 2;  // value v = (g NV + b) 3 + c of quad v
+    auto store = [&](int jgs, int lv) {
+        const double o = lds_sum12(a);
+        if ((lane & 3) == 0 && v < 12) {
+            const int g = v / (3 * NV), b = (v / 3) % NV, c = v % 3;
+            if (g < lv) Rt[(size_t)(b * 3 + c) * JL + (jgs - j0) + g] = UNI ? o * qI : o;
+        }
+    };
     HvpJRec<NV> cur = load_hvp_j<NV>(J, j0);
     for (int jg = j0; jg < j1; jg += GJ) {
         const int live = min(GJ, j1 - jg);
@@ -181,16 +197,15 @@ __device__ __forceinline__ void hvp_sym_body(const double* __restrict__ J, doubl
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int b = 0; b < NV; ++b) asm volatile("" : "+v"(ia[p][b][0]), "+v"(ia[p][b][1]), "+v"(ia[p][b][2]));
+        if (pjg >= 0) store(pjg, plive);
         double v12[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) v12[k] = sh[k / (3 * NV)][(k / 3) % NV][k % 3];
-        const double o = lds_reduce12(v12, red);
-        const int v = lane >> 2;  // value v = (g NV + b) 3 + c of quad v
-        if ((lane & 3) == 0 && v < 12) {
-            const int g = v / (3 * NV), b = (v / 3) % NV, c = v % 3;
-            if (g < live) Rt[(size_t)(b * 3 + c) * JL + (jg - j0) + g] = UNI ? o * qI : o;
-        }
+        lds_put12(v12, red, a);
+        pjg = jg;
+        plive = live;
     }
+    if (pjg >= 0) store(pjg, plive);
     const double sc = UNI ? qI * qJ : 1.0;
     double* Pt = Pi + (size_t)t * NV * 3 * IB;
 #pragma unroll
@@ -202,8 +217,10 @@ __device__ __forceinline__ void hvp_sym_body(const double* __restrict__ J, doubl
                 Pt[(size_t)(b * 3 + c) * IB + p * 64 + lane] = UNI ? sc * ia[p][b][c] : ia[p][b][c];
 }
 
-// One wave per tile (row I, segment s) of the tile table.  v: [NV][3][n] of
-// this pass; J: its packed j records.
+// One wave per tile (row I, segment s) of the tile table and pass
+// blockIdx.y of the launch.  v: [passes][NV][3][n]; J: each pass's packed j
+// records, n kHvpRec doubles apart; the partials of pass u and tile t go to
+// slot u T + t (T = gridDim.x tiles).
 template <int PREC, int P, int NV>
 __global__ void __launch_bounds__(64, (hvp_sym_waves<P, NV>())) k_hvp_sym(int n, const double* __restrict__ x,
                                                                   const double* __restrict__ y,
@@ -218,6 +235,9 @@ __global__ void __launch_bounds__(64, (hvp_sym_waves<P, NV>())) k_hvp_sym(int n,
     const int t = blockIdx.x;
     const int2 tl = tiles[t];
     const int lane = threadIdx.x;
+    const int slot = blockIdx.y * gridDim.x + t;
+    v += (size_t)blockIdx.y * NV * 3 * n;
+    J += (size_t)blockIdx.y * n * kHvpRec;
     double xi[P], yi[P], zi[P], qi[P], vi[NV][3][P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -235,21 +255,22 @@ __global__ void __launch_bounds__(64, (hvp_sym_waves<P, NV>())) k_hvp_sym(int n,
     const int j1 = min(n, j0 + JL);
     double qI, qJ;
     if (tile_charges<P>(qi, q, j0, j1, qI, qJ))
-        hvp_sym_body<PREC, P, NV, true>(J, eps2, JL, j0, j1, t, xi, yi, zi, qi, vi, qI, qJ, red, Pi, R);
+        hvp_sym_body<PREC, P, NV, true>(J, eps2, JL, j0, j1, slot, xi, yi, zi, qi, vi, qI, qJ, red, Pi, R);
     else
-        hvp_sym_body<PREC, P, NV, false>(J, eps2, JL, j0, j1, t, xi, yi, zi, qi, vi, 1.0, 1.0, red, Pi, R);
+        hvp_sym_body<PREC, P, NV, false>(J, eps2, JL, j0, j1, slot, xi, yi, zi, qi, vi, 1.0, 1.0, red, Pi, R);
 }
 
-// Per ion k and vector b = blockIdx.y (64 ions per workgroup, kFinishParts
-// waves each taking a fixed share of every sum): the pairs inside k's own
-// i-block (direct, self pair skipped), k's i sums over the tiles of its row,
-// minus q_k times its reactions from the rows above; hv[b][c][k] = k_C (those)
-// + m_k kk_c v_k (m may be NULL).  The waves' shares are added in wave order
-// (deterministic).  One vector per workgroup spreads the partial reads of a
-// pass over NV times the workgroups.
+// Per ion k and vector b = blockIdx.y of the launch (pass b / NV, its vector
+// b % NV; 64 ions per workgroup, kFinishParts waves each taking a fixed share
+// of every sum): the pairs inside k's own i-block (direct, self pair
+// skipped), k's i sums over the tiles of its row, minus q_k times its
+// reactions from the rows above; hv[b][c][k] = k_C (those) + m_k kk_c v_k (m
+// may be NULL).  T: tiles per pass.  The waves' shares are added in wave
+// order (deterministic).  One vector per workgroup spreads the partial reads
+// of a pass over NV times the workgroups.
 template <int PREC, int NV>
 __global__ void __launch_bounds__(64 * kFinishParts) k_hvp_sym_finish(
-    int n, int IB, int JL, int lgJL, const double* __restrict__ x, const double* __restrict__ y,
+    int n, int IB, int JL, int lgJL, int T, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ q, const double* __restrict__ v, double eps2,
     const int* __restrict__ rowstart, const double* __restrict__ Pi, const double* __restrict__ R,
     const double* __restrict__ m, TrapK kk, double* __restrict__ hv, unsigned* flags) {
@@ -257,6 +278,8 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_hvp_sym_finish(
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int b = blockIdx.y;
+    const size_t pslot = (size_t)(b / NV) * T;  // the pass's first partial slot
+    const int bl = b % NV;
     const int k0 = blockIdx.x * 64;
     const int k = k0 + lane;
     const int kc = min(k, n - 1);
@@ -285,7 +308,7 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_hvp_sym_finish(
     share(rowstart[Ik], rowstart[Ik + 1], w, lo, hi);
 #pragma unroll 4
     for (int t = lo; t < hi; ++t) {  // k's i sums over the tiles of its row
-        const double* Pt = Pi + ((size_t)t * NV + b) * 3 * IB + off;
+        const double* Pt = Pi + ((pslot + t) * NV + bl) * 3 * IB + off;
         s[0] += Pt[0];
         s[1] += Pt[IB];
         s[2] += Pt[2 * IB];
@@ -295,7 +318,7 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_hvp_sym_finish(
     for (int I = lo; I < hi; ++I) {  // k's reactions from the rows above
         const int rel = kc - (I + 1) * IB;
         const int sI = rel >> lgJL;
-        const double* Rt = R + ((size_t)(rowstart[I] + sI) * NV + b) * 3 * JL + (rel - (sI << lgJL));
+        const double* Rt = R + ((pslot + rowstart[I] + sI) * NV + bl) * 3 * JL + (rel - (sI << lgJL));
         e[0] += Rt[0];
         e[1] += Rt[JL];
         e[2] += Rt[2 * JL];

@@ -22,12 +22,19 @@ constexpr int64_t kSymMaxN = int64_t(1) << 18;  // largest n for the symmetric k
 constexpr int kMaxDevices = 64;      // GPUs per process the per-device symbol tables hold
 
 // ALGO_SYM and ALGO_SYM_LDS differ only in how the per-j reactions are summed
-// over the wave (cross-lane permutes and DPP, or LDS).
+// over the wave (cross-lane permutes and DPP, or LDS).  ALGO_SYM_ROWS: as
+// ALGO_SYM_LDS with kSymRows consecutive i-blocks per workgroup sharing each
+// j-segment, their reactions added in LDS before one store.
 // ALGO_SMALL (md_step / md_run of one run of at most kSmallRunMax ions):
 // one launch per step, every pair direct (md_run_small).
-enum : int { ALGO_DIRECT = 0, ALGO_SYM = 1, ALGO_SYM_LDS = 2, ALGO_SMALL = 3 };
+enum : int { ALGO_DIRECT = 0, ALGO_SYM = 1, ALGO_SYM_LDS = 2, ALGO_SMALL = 3, ALGO_SYM_ROWS = 4 };
 
-constexpr bool is_sym(int algo) { return algo == ALGO_SYM || algo == ALGO_SYM_LDS; }
+constexpr bool is_sym(int algo) { return algo == ALGO_SYM || algo == ALGO_SYM_LDS || algo == ALGO_SYM_ROWS; }
+
+// i-blocks per workgroup of the row-group variant, and of the others.
+constexpr int kSymRows = 4;
+constexpr int sym_rows(int algo) { return algo == ALGO_SYM_ROWS ? kSymRows : 1; }
+constexpr bool sym_rows_p_ok(int p) { return p == 4 || p == 6 || p == 8; }
 
 // Operations whose pair stage may take the Newton's-third-law kernels.
 constexpr bool sym_op(int op) {
@@ -53,7 +60,14 @@ constexpr bool hvp_sym_cfg_ok(int p, int jl) {
     return pk && jk;
 }
 constexpr int64_t hvp_sym_max_n(int p) { return int64_t(2048) * 64 * p; }
-size_t hvp_sym_ws_bytes(int64_t n, int p, int jl);
+// Passes of nvmax vectors that one launch evaluates together (more waves in
+// flight than one pass of a small problem gives), and the passes a
+// workspace for nvec vectors holds.
+constexpr int kHvpSymPasses = 2;
+constexpr int hvp_sym_passes(int nvec, int nvmax) {
+    return nvec / nvmax < 1 ? 1 : (nvec / nvmax > kHvpSymPasses ? kHvpSymPasses : nvec / nvmax);
+}
+size_t hvp_sym_ws_bytes(int64_t n, int p, int jl, int npass);
 
 constexpr bool sym_cfg_ok(int p, int g, int jl) {
     bool pk = false, jk = false;
@@ -116,25 +130,27 @@ WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec);
 
 bool trap_ok(const cb_trap* t, const char* who, cb_status* st);
 
-// Tile table of the Newton's-third-law kernels (pair_sym.hip): rows of
-// i-blocks of IB ions, each cut into j-segments of JL.  sym_plan carves
-// rowstart[nI+1] and tiles[T] from the start of ws (sym_plan_bytes of it)
-// and enqueues the kernel that fills them.
+// Tile table of the Newton's-third-law kernels (pair_sym.hip): row groups of
+// W consecutive i-blocks of IB ions (W = 1: single rows), the j's above the
+// group's first block cut into j-segments of JL.  sym_plan carves
+// rowstart[nG+1] and tiles[T] (tile = (group, segment)) from the start of ws
+// (sym_plan_bytes of it) and enqueues the kernel that fills them.
 struct SymPlan {
     int* rowstart;
     int2* tiles;
     int64_t T;
     size_t bytes;
 };
-int64_t sym_tiles(int64_t n, int IB, int JL);
-size_t sym_plan_bytes(int64_t n, int IB, int JL);
-cb_status sym_plan(int n, int IB, int JL, void* ws, SymPlan* out, hipStream_t st);
+int64_t sym_tiles(int64_t n, int IB, int JL, int W = 1);
+size_t sym_plan_bytes(int64_t n, int IB, int JL, int W = 1);
+cb_status sym_plan(int n, int IB, int JL, void* ws, SymPlan* out, hipStream_t st, int W = 1);
 
 // Symmetric (Newton's third law) force path (pair_sym.hip): workspace bytes
-// for (n, p, JL) (pot: with the tiles' pair energies), and the launch
-// sequence ending with finished forces F[3][n] and, when phi is set, each
-// ion's share of the Coulomb energy, U_C = k_C sum_k phi[k].
-size_t sym_ws_bytes(int64_t n, int p, int jl, bool pot = false);
+// for (n, p, JL) and W rows per workgroup (pot: with the tiles' pair
+// energies), and the launch sequence ending with finished forces F[3][n]
+// and, when phi is set, each ion's share of the Coulomb energy, U_C = k_C
+// sum_k phi[k].
+size_t sym_ws_bytes(int64_t n, int p, int jl, bool pot = false, int W = 1);
 cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, const double* y, const double* z,
                           const double* q, double eps2, void* ws, double* F, hipStream_t st, double* phi = nullptr);
 

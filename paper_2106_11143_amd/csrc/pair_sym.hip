@@ -8,24 +8,26 @@
 
 namespace cb {
 
-// Tile table, one workgroup.  rowstart[I] = first tile of row I (exclusive
-// prefix sum over rows of their segment counts), rowstart[nI] = tiles T;
-// tiles[t] = (row, segment) of tile t.  Each thread sums the segments of a
-// contiguous share of rows, the shares are scanned in LDS (Hillis-Steele),
-// the row starts are kept in LDS, and each wave then writes whole rows of
-// the table, its lanes taking consecutive segments.
+// Tile table, one workgroup.  Rows are groups of W i-blocks (W = 1: single
+// blocks); group I's segments cut the j's above its first block, W I.
+// rowstart[I] = first tile of group I (exclusive prefix sum over groups of
+// their segment counts), rowstart[nI] = tiles T; tiles[t] = (group, segment)
+// of tile t.  Each thread sums the segments of a contiguous share of groups,
+// the shares are scanned in LDS (Hillis-Steele), the group starts are kept in
+// LDS, and each wave then writes whole groups of the table, its lanes taking
+// consecutive segments.
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanMaxRows = 2048;  // n <= 2^18 ions in blocks of >= 128
 
-__global__ void __launch_bounds__(kPlanThreads) k_sym_plan(int n, int IB, int JL, int nI, int* __restrict__ rowstart,
-                                                           int2* __restrict__ tiles) {
+__global__ void __launch_bounds__(kPlanThreads) k_sym_plan(int n, int IB, int JL, int W, int nI,
+                                                           int* __restrict__ rowstart, int2* __restrict__ tiles) {
     __shared__ int sh[kPlanThreads];
     __shared__ int rs[kPlanMaxRows + 1];
     const int t = threadIdx.x;
     const int per = (nI + kPlanThreads - 1) / kPlanThreads;
     const int r0 = min(nI, t * per), r1 = min(nI, r0 + per);
     int mine = 0;
-    for (int I = r0; I < r1; ++I) mine += sym_nseg(n, IB, JL, I);
+    for (int I = r0; I < r1; ++I) mine += sym_nseg(n, IB, JL, I * W);
     sh[t] = mine;
     __syncthreads();
     for (int w = 1; w < kPlanThreads; w <<= 1) {
@@ -38,7 +40,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_sym_plan(int n, int IB, int JL
     for (int I = r0; I < r1; ++I) {
         rs[I] = acc;
         rowstart[I] = acc;
-        acc += sym_nseg(n, IB, JL, I);
+        acc += sym_nseg(n, IB, JL, I * W);
     }
     if (t == kPlanThreads - 1) {
         rs[nI] = sh[t];
@@ -54,20 +56,26 @@ __global__ void __launch_bounds__(kPlanThreads) k_sym_plan(int n, int IB, int JL
 
 static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
-int64_t sym_tiles(int64_t n, int IB, int JL) {
+static int sym_groups(int64_t n, int IB, int W) {
     const int nI = (int)((n + IB - 1) / IB);
+    return (nI + W - 1) / W;
+}
+
+int64_t sym_tiles(int64_t n, int IB, int JL, int W) {
+    const int nG = sym_groups(n, IB, W);
     int64_t T = 0;
-    for (int I = 0; I < nI; ++I) T += sym_nseg((int)n, IB, JL, I);
+    for (int G = 0; G < nG; ++G) T += sym_nseg((int)n, IB, JL, G * W);
     return T;
 }
 
-// Workspace carve-up: rowstart[nI+1] | tiles[T] | Pi[T][3][IB] | R[T][3][JL]
-// (| Et[T], the tiles' pair energies, with the energy)
-size_t sym_ws_bytes(int64_t n, int p, int jl, bool pot) {
+// Workspace carve-up: rowstart[nG+1] | tiles[T] | Pi[T][W][3][IB] |
+// R[T][3][JL] (| Et[T][W], the tiles' pair energies, with the energy)
+size_t sym_ws_bytes(int64_t n, int p, int jl, bool pot, int W) {
     const int IB = 64 * p;
-    const int64_t T = sym_tiles(n, IB, jl);
-    return sym_plan_bytes(n, IB, jl) + al256(sizeof(double) * 3 * IB * (T + 1)) +
-           al256(sizeof(double) * 3 * (size_t)jl * (T + 1)) + (pot ? al256(sizeof(double) * (T + 1)) : 0);
+    const int64_t T = sym_tiles(n, IB, jl, W);
+    const size_t TW = (size_t)W * T;
+    return sym_plan_bytes(n, IB, jl, W) + al256(sizeof(double) * 3 * IB * (TW + 1)) +
+           al256(sizeof(double) * 3 * (size_t)jl * (T + 1)) + (pot ? al256(sizeof(double) * (TW + 1)) : 0);
 }
 
 template <int PREC, int P, int RED, bool POT>
@@ -102,43 +110,67 @@ static bool go_sym_pr(int P, int red, bool pot, int n, int JL, int64_t T, const 
                : go_sym_p<PREC, 0, false>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st);
 }
 
+// The row-group kernel (kSymRows i-blocks per workgroup), for P = 4, 6, 8.
+template <int PREC, bool POT>
+static bool go_sym_rows(int P, int n, int JL, int64_t T, const double* x, const double* y, const double* z,
+                        const double* q, double eps2, const int2* tiles, double* Pi, double* R, double* Et,
+                        hipStream_t st) {
+    const unsigned g = (unsigned)T, b = 64 * kSymRows;
+    switch (P) {
+        case 4: k_pair_sym_rows<PREC, 4, POT><<<g, b, 0, st>>>(n, x, y, z, q, eps2, JL, tiles, Pi, R, Et); return true;
+        case 6: k_pair_sym_rows<PREC, 6, POT><<<g, b, 0, st>>>(n, x, y, z, q, eps2, JL, tiles, Pi, R, Et); return true;
+        case 8: k_pair_sym_rows<PREC, 8, POT><<<g, b, 0, st>>>(n, x, y, z, q, eps2, JL, tiles, Pi, R, Et); return true;
+        default: return false;
+    }
+}
+
 template <int PREC>
-static void go_finish(bool pot, unsigned nb, int n, int IB, int JL, int lgJL, const double* x, const double* y,
-                      const double* z, const double* q, double eps2, const int* rowstart, const double* Pi,
-                      const double* R, const double* Et, double* F, double* phi, hipStream_t st) {
+static bool go_sym_rows_p(int P, bool pot, int n, int JL, int64_t T, const double* x, const double* y,
+                          const double* z, const double* q, double eps2, const int2* tiles, double* Pi, double* R,
+                          double* Et, hipStream_t st) {
+    return pot ? go_sym_rows<PREC, true>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st)
+               : go_sym_rows<PREC, false>(P, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st);
+}
+
+template <int PREC>
+static void go_finish(bool pot, unsigned nb, int n, int IB, int JL, int lgJL, int W, const double* x,
+                      const double* y, const double* z, const double* q, double eps2, const int* rowstart,
+                      const double* Pi, const double* R, const double* Et, double* F, double* phi, hipStream_t st) {
     if (pot)
-        k_sym_finish<PREC, true><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi,
-                                                                   R, Et, F, phi);
+        k_sym_finish<PREC, true><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, W, x, y, z, q, eps2, rowstart,
+                                                                   Pi, R, Et, F, phi);
     else
-        k_sym_finish<PREC, false><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi,
-                                                                    R, Et, F, phi);
+        k_sym_finish<PREC, false><<<nb, 64 * kFinishParts, 0, st>>>(n, IB, JL, lgJL, W, x, y, z, q, eps2, rowstart,
+                                                                    Pi, R, Et, F, phi);
 }
 
-size_t sym_plan_bytes(int64_t n, int IB, int JL) {
-    const int64_t nI = (n + IB - 1) / IB;
-    return al256(sizeof(int) * (nI + 1)) + al256(sizeof(int2) * (sym_tiles(n, IB, JL) + 1));
+size_t sym_plan_bytes(int64_t n, int IB, int JL, int W) {
+    const int64_t nG = sym_groups(n, IB, W);
+    return al256(sizeof(int) * (nG + 1)) + al256(sizeof(int2) * (sym_tiles(n, IB, JL, W) + 1));
 }
 
-cb_status sym_plan(int n, int IB, int JL, void* ws, SymPlan* out, hipStream_t st) {
+cb_status sym_plan(int n, int IB, int JL, void* ws, SymPlan* out, hipStream_t st, int W) {
     const int nI = (n + IB - 1) / IB;
     if (nI > kPlanMaxRows) return fail(CB_EINVAL, "sym_plan: n = %d is too large for the symmetric kernels", n);
-    out->T = sym_tiles(n, IB, JL);
+    const int nG = sym_groups(n, IB, W);
+    out->T = sym_tiles(n, IB, JL, W);
     char* base = static_cast<char*>(ws);
     out->rowstart = reinterpret_cast<int*>(base);
-    base += al256(sizeof(int) * (nI + 1));
+    base += al256(sizeof(int) * (nG + 1));
     out->tiles = reinterpret_cast<int2*>(base);
-    out->bytes = sym_plan_bytes(n, IB, JL);
-    k_sym_plan<<<1, kPlanThreads, 0, st>>>(n, IB, JL, nI, out->rowstart, out->tiles);
+    out->bytes = sym_plan_bytes(n, IB, JL, W);
+    k_sym_plan<<<1, kPlanThreads, 0, st>>>(n, IB, JL, W, nG, out->rowstart, out->tiles);
     return check_launch("k_sym_plan");
 }
 
 cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, const double* y, const double* z,
                           const double* q, double eps2, void* ws, double* F, hipStream_t st, double* phi) {
-    const int P = c.p, JL = c.splits, IB = 64 * P;
-    if (!is_sym(c.algo) || !sym_cfg_ok(P, c.wg, JL)) return fail(CB_EINVAL, "launch_pair_sym: bad configuration");
-    const int red = c.algo == ALGO_SYM_LDS ? 1 : 0;
+    const int P = c.p, JL = c.splits, IB = 64 * P, W = sym_rows(c.algo);
+    if (!is_sym(c.algo) || !sym_cfg_ok(P, c.wg, JL) || (W > 1 && !sym_rows_p_ok(P)))
+        return fail(CB_EINVAL, "launch_pair_sym: bad configuration");
+    const int red = c.algo == ALGO_SYM ? 0 : 1;
     SymPlan plan;
-    cb_status rc = sym_plan(n, IB, JL, ws, &plan, st);
+    cb_status rc = sym_plan(n, IB, JL, ws, &plan, st, W);
     if (rc) return rc;
     const int64_t T = plan.T;
     int* rowstart = plan.rowstart;
@@ -146,11 +178,22 @@ cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, 
     const bool pot = phi != nullptr;
     char* base = static_cast<char*>(ws) + plan.bytes;
     double* Pi = reinterpret_cast<double*>(base);
-    base += al256(sizeof(double) * 3 * IB * (T + 1));
+    base += al256(sizeof(double) * 3 * IB * ((size_t)W * T + 1));
     double* R = reinterpret_cast<double*>(base);
     base += al256(sizeof(double) * 3 * (size_t)JL * (T + 1));
     double* Et = pot ? reinterpret_cast<double*>(base) : nullptr;
-    if (T > 0) {
+    if (T > 0 && W > 1) {
+        bool okk = false;
+        switch (prec) {
+            case PREC_FP64: okk = go_sym_rows_p<PREC_FP64>(P, pot, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); break;
+            case PREC_MIXED: okk = go_sym_rows_p<PREC_MIXED>(P, pot, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); break;
+            case PREC_IEEE: okk = go_sym_rows_p<PREC_IEEE>(P, pot, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); break;
+            case PREC_FP32: okk = go_sym_rows_p<PREC_FP32>(P, pot, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); break;
+            default: break;
+        }
+        if (!okk) return fail(CB_EINVAL, "launch_pair_sym: unsupported precision %d / p %d", prec, P);
+        if ((rc = check_launch("k_pair_sym_rows"))) return rc;
+    } else if (T > 0) {
         bool okk = false;
         switch (prec) {
             case PREC_FP64: okk = go_sym_pr<PREC_FP64>(P, red, pot, n, JL, T, x, y, z, q, eps2, tiles, Pi, R, Et, st); break;
@@ -166,10 +209,10 @@ cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, 
     int lgJL = 0;
     while ((1 << lgJL) < JL) ++lgJL;
     switch (prec) {
-        case PREC_FP64: go_finish<PREC_FP64>(pot, nb, n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, Et, F, phi, st); break;
-        case PREC_MIXED: go_finish<PREC_MIXED>(pot, nb, n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, Et, F, phi, st); break;
-        case PREC_IEEE: go_finish<PREC_IEEE>(pot, nb, n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, Et, F, phi, st); break;
-        default: go_finish<PREC_FP32>(pot, nb, n, IB, JL, lgJL, x, y, z, q, eps2, rowstart, Pi, R, Et, F, phi, st); break;
+        case PREC_FP64: go_finish<PREC_FP64>(pot, nb, n, IB, JL, lgJL, W, x, y, z, q, eps2, rowstart, Pi, R, Et, F, phi, st); break;
+        case PREC_MIXED: go_finish<PREC_MIXED>(pot, nb, n, IB, JL, lgJL, W, x, y, z, q, eps2, rowstart, Pi, R, Et, F, phi, st); break;
+        case PREC_IEEE: go_finish<PREC_IEEE>(pot, nb, n, IB, JL, lgJL, W, x, y, z, q, eps2, rowstart, Pi, R, Et, F, phi, st); break;
+        default: go_finish<PREC_FP32>(pot, nb, n, IB, JL, lgJL, W, x, y, z, q, eps2, rowstart, Pi, R, Et, F, phi, st); break;
     }
     return check_launch("k_sym_finish");
 }

@@ -21,6 +21,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "internal.hpp"
 #include "rsqrt.hpp"
 #include "step_common.hpp"
 #include "wave_reduce.hpp"
@@ -160,7 +161,7 @@ __device__ __forceinline__ void sym_group(const JGroupT<!UNI>& jd, int jg, int l
 #pragma unroll
     for (int p = 0; p < P; ++p) asm volatile("" : "+v"(ia[p][0]), "+v"(ia[p][1]), "+v"(ia[p][2]));
     if constexpr (POT) asm volatile("" : "+v"(pe));
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     if constexpr (RED == 0) {
         double o[3];
         reduce_scatter12(jv, o);
@@ -289,13 +290,167 @@ __global__ void __launch_bounds__(64, (sym_waves<PREC, P, POT>())) k_pair_sym(in
     sym_tile<PREC, P, RED, POT>(n, x, y, z, q, eps2, JL, tl.x, tl.y, t, red_buf, Pi, R, Et);
 }
 
+// ---------------------------------------------------------------- row groups
+// Algorithm 4: a workgroup of kSymRows waves takes the i-blocks I = kSymRows G
+// + w (w = its waves) of row group G against one j-segment [c0, c0 + JL),
+// c0 = (kSymRows G + 1) IB + s JL: each wave evaluates the part of the
+// segment above its own diagonal block (j >= (I + 1) IB; segments and blocks
+// are multiples of 64 apart, so a wave's part starts on a 64-j boundary).
+// The waves' per-j reactions go to one LDS slab per wave, 64 j's at a time;
+// after each 64 j's the workgroup adds the slabs in wave order and stores one
+// reaction partial R[t][3][JL] for the tile, so the reaction partials are a
+// kSymRows-th of one-wave tiles' and the waves share the segment's j data.
+// The i sums go to Pi[t][w][3][IB] (zeros from a wave with no pairs), the
+// pair energies (POT) to Et[t kSymRows + w].
+constexpr int kRowChunk = 64;               // j's per LDS slab
+constexpr int kRowStride = kRowChunk + 1;  // doubles per component row of a slab (odd: the rows' stores hit distinct banks)
+
+// The pairs of j in [cs, ce) (whole groups, the last one partial) of one
+// wave: reactions into its slab slabw[3][kRowStride] (index j - cs).  first:
+// the chunk's first group, already requested (when the chunk holds one).
+template <int PREC, int P, bool UNI, bool POT>
+__device__ __forceinline__ void sym_rows_chunk(const double* __restrict__ x, const double* __restrict__ y,
+                                               const double* __restrict__ z, const double* __restrict__ q,
+                                               double eps2, int cs, int ce, const JGroupT<!UNI>& first,
+                                               const double (&xi)[P], const double (&yi)[P], const double (&zi)[P],
+                                               const double (&qi)[P], double (&ia)[P][3], double& pe, double qI,
+                                               double* __restrict__ slabw, double* __restrict__ red) {
+    const SeriesK K;
+    const int jfull = cs + (ce - cs) / kGroupJ * kGroupJ;
+    int jg = cs;
+    if (jg < jfull) {
+        JGroupT<!UNI> cur = first;
+        for (; jg < jfull; jg += kGroupJ) {
+            JGroupT<!UNI> nxt;
+            const int jn = jg + kGroupJ;
+            load_group<false>(nxt, jn < jfull ? jn : jg, 0, x, y, z, q);
+            __builtin_amdgcn_sched_barrier(0);  // keep the requests ahead of the arithmetic
+            sym_group<PREC, P, 1, false, UNI, POT>(cur, jg, kGroupJ, cs, kRowStride, eps2, xi, yi, zi, qi, ia, pe, K,
+                                                   qI, slabw, red);
+            cur = nxt;
+        }
+    }
+    if (jg < ce) {  // the last, partial group: j's from ce on are masked
+        JGroupT<!UNI> tail;
+        load_group<true>(tail, jg, ce - jg - 1, x, y, z, q);
+        sym_group<PREC, P, 1, true, UNI, POT>(tail, jg, ce - jg, cs, kRowStride, eps2, xi, yi, zi, qi, ia, pe, K, qI,
+                                              slabw, red);
+    }
+}
+
+// The j loop of a row-group tile (the workgroup's 64-j chunks of [c0, c1),
+// each wave's pairs from j0 on) and the stores of its partials.  UNI is
+// uniform over the workgroup, so every wave meets every barrier.
+template <int PREC, int P, bool UNI, bool POT>
+__device__ __forceinline__ void sym_rows_tile(const double* __restrict__ x, const double* __restrict__ y,
+                                              const double* __restrict__ z, const double* __restrict__ q,
+                                              double eps2, int JL, int t, int w, int c0, int c1, int j0, bool live,
+                                              const double (&xi)[P], const double (&yi)[P], const double (&zi)[P],
+                                              const double (&qi)[P], double qI, double qJ,
+                                              double (*__restrict__ slab)[3 * kRowStride],
+                                              double* __restrict__ red, double* __restrict__ Pi,
+                                              double* __restrict__ R, double* __restrict__ Et) {
+    constexpr int IB = 64 * P;
+    const int lane = threadIdx.x & 63;
+    double ia[P][3], pe = 0.0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) ia[p][0] = ia[p][1] = ia[p][2] = 0.0;
+    double* slabw = slab[w];
+    double* Rt = R + (size_t)t * 3 * JL;
+    // the first group of the wave's next chunk is requested before the
+    // barriers, so that its load overlaps the workgroup's slab sums
+    JGroupT<!UNI> first;
+    if (live && j0 + kGroupJ <= min(c1, j0 + kRowChunk)) load_group<false>(first, j0, 0, x, y, z, q);
+    for (int cs = c0; cs < c1; cs += kRowChunk) {
+        const int ce = min(c1, cs + kRowChunk);
+        if (live && cs >= j0)
+            sym_rows_chunk<PREC, P, UNI, POT>(x, y, z, q, eps2, cs, ce, first, xi, yi, zi, qi, ia, pe,
+                                              UNI ? qI : 1.0, slabw, red);
+        else
+            for (int u = lane; u < 3 * kRowStride; u += 64) slabw[u] = 0.0;
+        const int cn = cs + kRowChunk;  // the next chunk
+        if (live && cn >= j0 && cn + kGroupJ <= min(c1, cn + kRowChunk)) load_group<false>(first, cn, 0, x, y, z, q);
+        __syncthreads();
+        for (int u = threadIdx.x; u < 3 * kRowChunk; u += 64 * kSymRows) {
+            const int c = u / kRowChunk, jj = u - c * kRowChunk, k = c * kRowStride + jj;
+            if (cs + jj < ce) {
+                double a = slab[0][k];
+#pragma unroll
+                for (int v = 1; v < kSymRows; ++v) a += slab[v][k];
+                Rt[(size_t)c * JL + (cs - c0) + jj] = a;
+            }
+        }
+        __syncthreads();  // the slabs are rewritten by the next 64 j's
+    }
+    const double sc = UNI ? qI * qJ : 1.0;
+    double* Pt = Pi + ((size_t)t * kSymRows + w) * 3 * IB;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Pt[(size_t)c * IB + p * 64 + lane] = UNI ? sc * ia[p][c] : ia[p][c];
+    if constexpr (POT) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) pe += __shfl_xor(pe, o);
+        if (lane == 0) Et[(size_t)t * kSymRows + w] = UNI ? sc * pe : pe;
+    }
+}
+
+template <int PREC, int P, bool POT>
+__global__ void __launch_bounds__(64 * kSymRows, (sym_waves<PREC, P, POT>()))
+    k_pair_sym_rows(int n, const double* __restrict__ x, const double* __restrict__ y,
+                    const double* __restrict__ z, const double* __restrict__ q, double eps2, int JL,
+                    const int2* __restrict__ tiles, double* __restrict__ Pi, double* __restrict__ R,
+                    double* __restrict__ Et) {
+    __shared__ __align__(16) double red_buf[kSymRows][12 * kRedStride];
+    __shared__ double slab[kSymRows][3 * kRowStride];
+    __shared__ int nonuni;
+    constexpr int IB = 64 * P;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = blockIdx.x;
+    const int2 tl = tiles[t];
+    const int I = tl.x * kSymRows + w;
+    const int c0 = (tl.x * kSymRows + 1) * IB + tl.y * JL;
+    const int c1 = min(n, c0 + JL);
+    const int jr = (I + 1) * IB;  // the first j above this wave's diagonal block
+    const int j0 = max(c0, jr);
+    const bool live = j0 < c1;    // then block I is a full block
+    double xi[P], yi[P], zi[P], qi[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int i = min(I * IB + p * 64 + lane, n - 1);
+        xi[p] = x[i];
+        yi[p] = y[i];
+        zi[p] = z[i];
+        qi[p] = q[i];
+    }
+    // the charge-free loop when every wave with pairs has one charge on each
+    // side (each wave keeps its own qI, qJ)
+    double qI = 1.0, qJ = 1.0;
+    const bool uni = !live || tile_charges<P>(qi, q, j0, c1, qI, qJ);
+    if (threadIdx.x == 0) nonuni = 0;
+    __syncthreads();
+    if (!uni && lane == 0) nonuni = 1;
+    __syncthreads();
+    if (nonuni == 0)
+        sym_rows_tile<PREC, P, true, POT>(x, y, z, q, eps2, JL, t, w, c0, c1, j0, live, xi, yi, zi, qi, qI, qJ, slab,
+                                          red_buf[w], Pi, R, Et);
+    else
+        sym_rows_tile<PREC, P, false, POT>(x, y, z, q, eps2, JL, t, w, c0, c1, j0, live, xi, yi, zi, qi, qI, qJ,
+                                           slab, red_buf[w], Pi, R, Et);
+}
+
 // Per ion k: direct pairs inside its own i-block, plus its i sums over the
 // segments of its row, minus q_k times its reactions from the rows above;
-// writes the finished force F = k_C (...) to F[3][n].  One workgroup = 64
-// consecutive ions (one i-block holds them all, IB being a multiple of 64)
-// and kFinishParts waves; wave w takes the w-th contiguous share of each of
-// the three sums, and the shares are added in wave order through LDS, so the
-// result does not depend on timing.  All j and row loops are uniform.
+// writes the finished force F = k_C (...) to F[3][n].  Rows come in groups of
+// W i-blocks (W = 1, or kSymRows for the row-group tiles): ion k's block Ik
+// is wave Ik % W of group Ik / W, its i sums sit in that wave's slot of each
+// tile of the group, and every group whose segments start at or below k
+// holds one reaction slot for k.  One workgroup = 64 consecutive ions (one
+// i-block holds them all, IB being a multiple of 64) and kFinishParts
+// waves; wave w takes the w-th contiguous share of each of the three sums,
+// and the shares are added in wave order through LDS, so the result does not
+// depend on timing.  All j and row loops are uniform.
 constexpr int kFinishParts = 4;
 
 __host__ __device__ __forceinline__ void share(int a, int b, int w, int& lo, int& hi) {
@@ -309,7 +464,7 @@ __host__ __device__ __forceinline__ void share(int a, int b, int w, int& lo, int
 // (q_j r^-1, j > k), plus the energies of the tiles of its row numbered
 // off, off + IB, ... within the row (each tile's energy goes to one ion).
 template <int PREC, bool POT>
-__global__ void __launch_bounds__(64 * kFinishParts) k_sym_finish(int n, int IB, int JL, int lgJL,
+__global__ void __launch_bounds__(64 * kFinishParts) k_sym_finish(int n, int IB, int JL, int lgJL, int W,
                                                                   const double* __restrict__ x,
                                                                   const double* __restrict__ y,
                                                                   const double* __restrict__ z,
@@ -327,6 +482,7 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_sym_finish(int n, int IB,
     const int k = k0 + lane;
     const int kc = min(k, n - 1);
     const int Ik = k0 / IB;
+    const int Gk = Ik / W, wk = Ik - Gk * W;
     const int b0 = Ik * IB, b1 = min(n, b0 + IB);
     const double xk = x[kc], yk = y[kc], zk = z[kc];
     const SeriesK K;
@@ -345,21 +501,23 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_sym_finish(int n, int IB,
     }
     const int off = kc - b0;
     double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-    share(rowstart[Ik], rowstart[Ik + 1], w, lo, hi);
+    share(rowstart[Gk], rowstart[Gk + 1], w, lo, hi);
 #pragma unroll 4
     for (int t = lo; t < hi; ++t) {
-        const double* Pt = Pi + (size_t)t * 3 * IB + off;
+        const double* Pt = Pi + ((size_t)t * W + wk) * 3 * IB + off;
         p0 += Pt[0];
         p1 += Pt[IB];
         p2 += Pt[2 * IB];
     }
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-    share(0, Ik, w, lo, hi);
+    // the groups whose segments start at or below k: all above k's group, and
+    // k's own group when k is not in its first block
+    share(0, Gk + (wk > 0 ? 1 : 0), w, lo, hi);
 #pragma unroll 4
-    for (int I = lo; I < hi; ++I) {
-        const int rel = kc - (I + 1) * IB;
+    for (int G = lo; G < hi; ++G) {
+        const int rel = kc - (G * W + 1) * IB;
         const int sI = rel >> lgJL;
-        const double* Rt = R + (size_t)(rowstart[I] + sI) * 3 * JL + (rel - (sI << lgJL));
+        const double* Rt = R + (size_t)(rowstart[G] + sI) * 3 * JL + (rel - (sI << lgJL));
         e0 += Rt[0];
         e1 += Rt[JL];
         e2 += Rt[2 * JL];
@@ -369,7 +527,7 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_sym_finish(int n, int IB,
         const double qk = q[kc];
         es = qk * ps;
         if (w == 0)
-            for (int t = rowstart[Ik] + off; t < rowstart[Ik + 1]; t += IB) es += Et[t];
+            for (int t = rowstart[Gk] + off; t < rowstart[Gk + 1]; t += IB) es += Et[(size_t)t * W + wk];
     }
     const double v[10] = {d0, d1, d2, p0, p1, p2, e0, e1, e2, es};
 #pragma unroll

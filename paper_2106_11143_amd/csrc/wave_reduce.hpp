@@ -114,4 +114,33 @@ __device__ __forceinline__ double lds_reduce12(const double (&v)[12], double* __
     return lds_reduce<12>(v, red);
 }
 
+// lds_reduce<12> in two halves, for a loop that evaluates the next j while
+// one j's sums are in flight: lds_put12 writes the values and requests this
+// lane's eight loads into a; lds_sum12 (after independent work) adds them.
+// The next lds_put12 on the same buffer follows the reads in the wave's
+// issue order, so one buffer serves every round.
+__device__ __forceinline__ void lds_put12(const double (&v)[12], double* __restrict__ red, double2 (&a)[8]) {
+    const int lane = __lane_id();
+    const int wpos = lane + 2 * (lane >> 4);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) red[k * kRedStride + wpos] = v[k];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int vi = min(lane >> 2, 11);
+    const double2* src = reinterpret_cast<const double2*>(red + vi * kRedStride + (lane & 3) * 18);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = src[k];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // these reads before the next round's writes
+}
+
+__device__ __forceinline__ double lds_sum12(const double2 (&a)[8]) {
+    double s4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s4[k] = (a[2 * k].x + a[2 * k].y) + (a[2 * k + 1].x + a[2 * k + 1].y);
+    double x = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    x += dpp_d<kDppQuadXor1>(x);
+    x += dpp_d<kDppQuadXor2>(x);
+    return x;
+}
+
 }  // namespace cb

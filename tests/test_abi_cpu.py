@@ -356,3 +356,31 @@ def test_hvp_config_validation(api):
             api.set_config(op, 131073, "fp64", p=1, wg=4, splits=128, algo=2)
         api.set_config(op, 131073, "fp64", p=2, wg=4, splits=128, algo=2)
         api.reset_config(op, 131073, "fp64")
+
+
+def test_row_group_config_validation(api):
+    """Algorithm 4 (four i-blocks per workgroup): forces, energy and md
+    calls, p in {4, 6, 8}, segments of the symmetric path, n <= 2^18; its
+    workspace holds a kSymRows-th of the reaction partials."""
+    for op in ("forces", "energy", "md_step", "md_run"):
+        api.set_config(op, 50000, "fp64", p=8, wg=4, splits=512, algo=4)
+        c = api.get_config(op, 50000, "fp64")
+        assert (c["algo"], c["p"], c["wg"], c["splits"], c["tuned"]) == (4, 8, 4, 512, True)
+        api.reset_config(op, 50000, "fp64")
+    for bad in (dict(op="forces", n=50000, p=2, splits=512),   # p outside {4, 6, 8}
+                dict(op="forces", n=50000, p=8, splits=384),   # not a segment length
+                dict(op="forces", n=300000, p=8, splits=512),  # beyond 2^18
+                dict(op="hvp", n=8192, p=4, splits=128),       # forces-shaped calls only
+                dict(op="md_ensemble", n=50000, p=4, splits=256)):
+        with pytest.raises(api.CoulombError):
+            api.set_config(bad["op"], bad["n"], "fp64", p=bad["p"], wg=4, splits=bad["splits"], algo=4)
+    n = 100000
+    sizes = {}
+    for algo in (2, 4):
+        api.set_config("forces", n, "fp64", p=8, wg=4, splits=512, algo=algo)
+        try:
+            sizes[algo] = api.workspace_size("forces", n)
+        finally:
+            api.reset_config("forces", n, "fp64")
+    # R shrinks fourfold (234 -> 59 MB at N = 1e5); Pi and the tile table stay
+    assert 0 < sizes[4] < sizes[2] - 150e6

@@ -67,14 +67,17 @@ def test_forces_ragged_sizes_and_launch_shapes(api, oracle, p, wg, splits):
 
 SYM_SIZES = [1, 2, 3, 65, 127, 128, 129, 191, 192, 193, 320, 385, 511, 512, 513, 1000, 1537, 2049, 4001]
 SYM_CONFIGS = [(1, 2, 256), (1, 3, 1024), (1, 4, 512), (1, 5, 2048), (1, 6, 256), (1, 8, 512),
-               (2, 2, 512), (2, 4, 256), (2, 6, 1024), (2, 8, 512)]
+               (2, 2, 512), (2, 4, 256), (2, 6, 1024), (2, 8, 512),
+               (4, 4, 256), (4, 6, 512), (4, 8, 512), (4, 8, 2048), (4, 4, 1024)]
 
 
 @pytest.mark.parametrize("algo,p,jl", SYM_CONFIGS)
 def test_forces_symmetric_kernel_ragged_sizes(api, oracle, algo, p, jl):
     """The Newton's-third-law kernel (algo 1: reactions summed over the wave by
-    permutes and DPP; algo 2: through LDS): i-blocks of 64p, j-segments of jl,
-    ragged last blocks and segments, sizes with no off-diagonal tile."""
+    permutes and DPP; algo 2: through LDS; algo 4: as 2 with four i-blocks per
+    workgroup sharing each j-segment, their reactions added in LDS): i-blocks
+    of 64p, j-segments of jl, ragged last blocks and segments, row groups with
+    rows that have no pairs, sizes with no off-diagonal tile."""
     group = 4
     from _gpu_util import per_ion_rel
     for n in SYM_SIZES:
@@ -241,8 +244,9 @@ def test_nonfinite_flag_on_coincident_ions(api):
     assert np.isfinite(np.stack([t.cpu().numpy() for t in f])).all()
 
 
-@pytest.mark.parametrize("p,jl", [(2, 256), (4, 512), (8, 512), (6, 1024)])
-def test_energy_on_the_symmetric_stage(api, oracle, p, jl):
+@pytest.mark.parametrize("algo,p,jl", [(2, 2, 256), (2, 4, 512), (2, 8, 512), (2, 6, 1024), (4, 4, 256),
+                                       (4, 8, 512)])
+def test_energy_on_the_symmetric_stage(api, oracle, algo, p, jl):
     """coulomb_energy on the Newton's-third-law tiles (the potential summed
     as a fourth component, its reactions with the same sign): ragged sizes,
     mixed charges and ions grouped by species, against the oracle."""
@@ -258,12 +262,12 @@ def test_energy_on_the_symmetric_stage(api, oracle, p, jl):
         eps2 = (1e-7) ** 2 if n % 2 else 0.0
         ref, _ = oracle.coulomb_energy(d["x"], d["y"], d["z"], d["q"], eps2=eps2)
         for prec, tol in (("fp64", 1e-12), ("mixed", 1e-9)):
-            api.set_config("energy", n, prec, p=p, wg=4, splits=jl, algo=2)
+            api.set_config("energy", n, prec, p=p, wg=4, splits=jl, algo=algo)
             try:
                 u = float(api.coulomb_energy(*(dev(d[c]) for c in "xyzq"), eps2=eps2, prec=prec)[0])
             finally:
                 api.reset_config("energy", n, prec)
-            assert abs(u - ref) <= tol * abs(ref), (p, jl, n, prec, u, ref)
+            assert abs(u - ref) <= tol * abs(ref), (algo, p, jl, n, prec, u, ref)
     api.clear_workspace_cache()
 
 

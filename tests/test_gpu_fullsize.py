@@ -112,3 +112,29 @@ def test_cloud100k_force_stage_is_bitwise_repeatable(api, prec):
         api.md_run(ts, dev(d["q"]), dev(d["m"]), d["trap"], 0.0, d["dt"], 3, prec=prec)
         runs.append(torch.stack(ts))
     assert torch.equal(runs[0], runs[1])
+
+
+@pytest.mark.parametrize("algo,p,jl", [(2, 8, 512), (4, 8, 512)])
+def test_cloud100k_symmetric_variants_agree_and_repeat(api, oracle, algo, p, jl):
+    """Both Newton's-third-law variants at N = 1e5 (one wave per tile; four
+    i-blocks per workgroup): bitwise repeatable, within the tolerance of the
+    oracle on sampled ions, and within rounding of each other."""
+    import torch
+    from _gpu_util import dev, per_ion_rel
+    d = inputs.group_by_charge(inputs.cloud100k())
+    n = d["n"]
+    args = [dev(d[k]) for k in "xyzq"]
+    idx = np.sort(np.random.Generator(np.random.PCG64(77)).choice(n, 300, replace=False))
+    ref = np.stack(oracle.forces(d["x"], d["y"], d["z"], d["q"], idx=idx))
+    api.set_config("forces", n, "fp64", p=p, wg=4, splits=jl, algo=algo)
+    try:
+        a = [t.clone() for t in api.coulomb_forces(*args)]
+        b = api.coulomb_forces(*args)
+    finally:
+        api.reset_config("forces", n, "fp64")
+    for u, v in zip(a, b):
+        assert torch.equal(u, v)
+    F = np.stack([t.cpu().numpy() for t in a])
+    assert per_ion_rel(F[:, idx], ref).max() <= 1e-12
+    dflt = np.stack([t.cpu().numpy() for t in api.coulomb_forces(*args)])
+    assert per_ion_rel(F, dflt).max() <= 1e-13

@@ -60,9 +60,10 @@ HVP_SIZES = [2, 65, 129, 130, 257, 1000, 2049, 4097]
 def test_hvp_symmetric_ragged_sizes(api, oracle, p, jl, nvmax):
     """The Newton's-third-law HVP (each unordered pair once, reactions summed
     over the wave): i-blocks of 64 p, j-segments of jl, at most nvmax vectors
-    per pass, ragged blocks and segments, 1, 3 and 8 vectors (passes of 4, 2
-    and 1), mixed charges and ions grouped by species, with and without the
-    trap term; every ion of every vector against the oracle."""
+    per pass, ragged blocks and segments, 1, 3, 8 and 7 vectors (passes of
+    4, 2 and 1, up to two passes in one launch, with a remainder), mixed
+    charges and ions grouped by species, with and without the trap term; every
+    ion of every vector against the oracle."""
     from _gpu_util import dev, host
     for k, n in enumerate(HVP_SIZES):
         g = np.random.Generator(np.random.PCG64(700 + n))
@@ -72,7 +73,7 @@ def test_hvp_symmetric_ragged_sizes(api, oracle, p, jl, nvmax):
         else:
             q = np.full(n, E)
             q[int(0.6 * n):] = 2.0 * E
-        nvec = (1, 3, 8)[k % 3]
+        nvec = (1, 3, 8, 7)[k % 4]
         v = g.normal(size=(nvec, 3, n))
         m = np.full(n, M40)
         trap = inputs.rf_trap(0.02, 0.3, 10e6, 0.1e6, phase=0.4) if k % 2 == 0 else None

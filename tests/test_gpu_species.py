@@ -54,7 +54,7 @@ LAYOUTS = ["uniform", "uniform_neg", "two", "three", "random"]
 SIZES = [2, 3, 65, 129, 513, 1000, 2049, 4001]
 # (algo, p, wg, splits): direct kernel shapes, then Newton's-third-law shapes
 SHAPES = [(0, 1, 64, 1), (0, 2, 128, 7), (0, 4, 256, 64), (1, 2, 4, 256), (2, 4, 4, 512), (2, 8, 4, 512),
-          (1, 6, 4, 1024), (2, 3, 4, 256)]
+          (1, 6, 4, 1024), (2, 3, 4, 256), (4, 4, 4, 256), (4, 8, 4, 512)]
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
