@@ -96,16 +96,18 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stage_counters():
+def stage_counters(cfg):
     """The committed rocprofv3 counter summary of one FP64 force evaluation
     (all kernels of the stage): HBM bytes and executed FP64 FLOPs, or None if
-    absent or taken on other code."""
+    absent, taken on other code or on another launch configuration."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kernel_hash") != kernel_hash():
+        return None
+    if t.get("config") != {k: cfg[k] for k in ("algo", "p", "wg", "splits")}:
         return None
     return t
 
@@ -127,6 +129,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="cloud100k: only the timed legs (steps, force stage, mixed), no error or 200-step legs "
                          "(for profiler runs)")
+    ap.add_argument("--stage-only", action="store_true",
+                    help="cloud100k: only FP64 force-stage evaluations of the headline input (--steps of them, "
+                         "after the clock warm-up), for counter runs that must see one kernel configuration only")
     ap.add_argument("--ungrouped", action="store_true",
                     help="time cloud100k in its seeded ion order (species interleaved) instead of grouped by "
                          "species")
@@ -218,6 +223,11 @@ def main():
     # the engine clock ramps over the first few hundred ms of FP64 load: settle it
     # with force evaluations before anything is timed (not part of any timed region)
     prewarm(torch, lambda: time_pair_kernel("fp64", 1), 0.5)
+    if args.stage_only:
+        print(json.dumps({"kernel_ms": time_pair_kernel("fp64", args.steps), "evaluations": args.steps,
+                          "config": api.get_config("forces", n, "fp64"),
+                          "note": "profiling run (--stage-only): not a bench line"}), flush=True)
+        return
     ms_fp64, st64 = time_steps("fp64", args.steps, args.warmup)
     ms_mixed, _ = time_steps("mixed", args.steps, args.warmup)
     reps = max(10, args.steps // 2)
@@ -236,7 +246,7 @@ def main():
     value = pairs_step * args.steps / (ms_fp64 * 1e-3)
     flops_eval = force_eval_flops(n, cfg["algo"])
     achieved = flops_eval / (kt64 * 1e-3) / 1e12
-    counters = stage_counters()
+    counters = stage_counters(cfg)
     traffic = counters.get("bytes_per_launch") if counters else None
     executed = counters.get("executed_fp64_flops_per_launch") if counters else None
 

@@ -314,13 +314,16 @@ cb_status cb_load_tuning(const char* cache_path);
  *          1: each unordered pair evaluated once and applied to both ions by
  *          Newton's third law, forces only, n <= 2^18, the reactions summed
  *          over the wave by cross-lane permutes; 2: as 1, summed through LDS;
+ *          4: as 2, with four i-blocks to a workgroup that share one
+ *          j-segment and sum their reactions in LDS before one write, which
+ *          cuts the partial sums written and read back by four;
  *          3: md_step / md_run of one run of at most 8192 ions in one launch
  *          per step, every ordered pair evaluated by one wave per 64 ions and
  *          j-part, the parts added in a fixed order by the last to finish,
  *          then trap, kick and drift -- the default up to 384 ions),
  * out[1] = i-particles per lane, out[2] = workgroup size (algorithm 0) or
- *          j's per reduction group (algorithm 1),
- * out[3] = j-splits (algorithm 0), j-segment length (algorithms 1, 2) or
+ *          j's per reduction group (algorithms 1, 2, 4),
+ * out[3] = j-splits (algorithm 0), j-segment length (algorithms 1, 2, 4) or
  *          j-parts per 64 ions (algorithm 3),
  * out[4] = 1 if it came from tuning or cb_set_config.
  * CB_EINVAL for a NULL out, n outside [1, 2^28], or an op or prec outside
@@ -330,8 +333,10 @@ cb_status cb_get_config(int32_t op, int64_t n, int32_t prec, int32_t out[5]);
 /* Forces the launch configuration for (op, n power-of-two bucket, prec), with
  * the fields of cb_get_config.  Algorithm 0: p in {1,2,4} ({1,2} for the HVP
  * and adjoint), wg in {64,128,256}, splits in 1..64.  Algorithms 1 and 2 (forces,
- * md_step, md_run; n <= 2^18): p in {2,3,4,5,6,8}, wg = j's per reduction
- * group = 4, splits = segment length in {256,512,1024,2048}.  Algorithm 3
+ * energy, md_step, md_run; n <= 2^18): p in {2,3,4,5,6,8}, wg = j's per reduction
+ * group = 4, splits = segment length in {256,512,1024,2048}.  Algorithm 4
+ * (the same ops and sizes): p in {4, 6, 8},
+ * wg = 4, the same segment lengths.  Algorithm 3
  * (md_step, md_run; n <= 8192): p = 1, wg = 64, splits = j-parts in 1..32.
  * For CB_OP_HVP and CB_OP_ADJOINT, algorithm 2 is the Newton's-third-law
  * product: p in {1, 2, 4}, wg = the most vectors per pass in {1, 2, 4},

@@ -405,8 +405,11 @@ def set_config(op, n: int, prec="fp64", p: int = 1, wg: int = 256, splits: int =
     default).  algo 1 = the Newton's-third-law force kernel (n <= 2^18), with
     p in {2, 3, 4, 5, 6, 8}, wg = j's per reduction group = 4 and splits =
     segment length in {256, 512, 1024, 2048}; algo 2 = the same kernel with
-    the per-j reactions summed through LDS; algo 3 (md_step / md_run, n <=
-    8192) = one launch per step, p = 1, wg = 64, splits = j-parts in 1..32.
+    the per-j reactions summed through LDS; algo 4 = the same tiles run four
+    i-blocks to a 256-thread workgroup that share one j-segment and sum their
+    reactions in LDS before one write (p in {4, 6, 8}); algo 3 (md_step /
+    md_run, n <= 8192) = one launch per step, p = 1, wg = 64, splits = j-parts
+    in 1..32.
     op "md_ensemble" (n = total
     ions) picks the path of md_run with several runs: algo 0 with p = 4,
     wg = 512, splits = 1 is the persistent kernel; algo 2 with p in {4, 8},

@@ -115,8 +115,14 @@ LaunchCfg default_cfg(int op, int64_t n, int prec) {
         // reduction best; below 32768 ions smaller tiles keep enough of them
         // in flight; below 16384 the direct kernel is faster (measured on
         // MI355X).  The energy takes the same stage, with the potential as a
-        // fourth component of the sums.
-        c.algo = ALGO_SYM_LDS;
+        // fourth component of the sums.  From 81920 ions the row-group tiles
+        // (four i-blocks per workgroup) take the same time or less -- 0.98 to
+        // 1.006 of the one-wave tiles' time from 81920 to 262144 ions, 0.96
+        // for the energy at 100000 -- while writing and reading back 0.89 GB
+        // of partial sums per evaluation at 100000 ions instead of 1.30;
+        // below that the workgroups are too few to share out evenly (1.08x
+        // the time at 65536 ions, 1.35x at 32768).
+        c.algo = n >= kSymRowsMinN ? ALGO_SYM_ROWS : ALGO_SYM_LDS;
         c.wg = kSymGroup;
         c.p = n >= 32768 ? 8 : (n >= 24576 ? 6 : 4);
         c.splits = n >= 32768 ? 512 : 256;

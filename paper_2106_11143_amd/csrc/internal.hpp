@@ -35,6 +35,7 @@ constexpr bool is_sym(int algo) { return algo == ALGO_SYM || algo == ALGO_SYM_LD
 constexpr int kSymRows = 4;
 constexpr int sym_rows(int algo) { return algo == ALGO_SYM_ROWS ? kSymRows : 1; }
 constexpr bool sym_rows_p_ok(int p) { return p == 4 || p == 6 || p == 8; }
+constexpr int64_t kSymRowsMinN = 81920;  // the row-group tiles are the default from here
 
 // Operations whose pair stage may take the Newton's-third-law kernels.
 constexpr bool sym_op(int op) {

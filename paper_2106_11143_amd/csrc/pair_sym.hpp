@@ -306,29 +306,29 @@ constexpr int kRowChunk = 64;               // j's per LDS slab
 constexpr int kRowStride = kRowChunk + 1;  // doubles per component row of a slab (odd: the rows' stores hit distinct banks)
 
 // The pairs of j in [cs, ce) (whole groups, the last one partial) of one
-// wave: reactions into its slab slabw[3][kRowStride] (index j - cs).  first:
-// the chunk's first group, already requested (when the chunk holds one).
+// wave: reactions into its slab slabw[3][kRowStride] (index j - cs).  cur:
+// the chunk's first group, already requested (when the chunk holds a whole
+// one); on return it holds the group at jnext (the next chunk's first, when
+// jnext >= 0), requested during this chunk's last whole group, so that only
+// two groups of j data are held in the loop.
 template <int PREC, int P, bool UNI, bool POT>
 __device__ __forceinline__ void sym_rows_chunk(const double* __restrict__ x, const double* __restrict__ y,
                                                const double* __restrict__ z, const double* __restrict__ q,
-                                               double eps2, int cs, int ce, const JGroupT<!UNI>& first,
+                                               double eps2, int cs, int ce, int jnext, JGroupT<!UNI>& cur,
                                                const double (&xi)[P], const double (&yi)[P], const double (&zi)[P],
                                                const double (&qi)[P], double (&ia)[P][3], double& pe, double qI,
                                                double* __restrict__ slabw, double* __restrict__ red) {
     const SeriesK K;
     const int jfull = cs + (ce - cs) / kGroupJ * kGroupJ;
     int jg = cs;
-    if (jg < jfull) {
-        JGroupT<!UNI> cur = first;
-        for (; jg < jfull; jg += kGroupJ) {
-            JGroupT<!UNI> nxt;
-            const int jn = jg + kGroupJ;
-            load_group<false>(nxt, jn < jfull ? jn : jg, 0, x, y, z, q);
-            __builtin_amdgcn_sched_barrier(0);  // keep the requests ahead of the arithmetic
-            sym_group<PREC, P, 1, false, UNI, POT>(cur, jg, kGroupJ, cs, kRowStride, eps2, xi, yi, zi, qi, ia, pe, K,
-                                                   qI, slabw, red);
-            cur = nxt;
-        }
+    for (; jg < jfull; jg += kGroupJ) {
+        JGroupT<!UNI> nxt;
+        const int jn = jg + kGroupJ;
+        load_group<false>(nxt, jn < jfull ? jn : (jnext >= 0 ? jnext : jg), 0, x, y, z, q);
+        __builtin_amdgcn_sched_barrier(0);  // keep the requests ahead of the arithmetic
+        sym_group<PREC, P, 1, false, UNI, POT>(cur, jg, kGroupJ, cs, kRowStride, eps2, xi, yi, zi, qi, ia, pe, K, qI,
+                                               slabw, red);
+        cur = nxt;
     }
     if (jg < ce) {  // the last, partial group: j's from ce on are masked
         JGroupT<!UNI> tail;
@@ -357,19 +357,20 @@ __device__ __forceinline__ void sym_rows_tile(const double* __restrict__ x, cons
     for (int p = 0; p < P; ++p) ia[p][0] = ia[p][1] = ia[p][2] = 0.0;
     double* slabw = slab[w];
     double* Rt = R + (size_t)t * 3 * JL;
-    // the first group of the wave's next chunk is requested before the
-    // barriers, so that its load overlaps the workgroup's slab sums
-    JGroupT<!UNI> first;
-    if (live && j0 + kGroupJ <= min(c1, j0 + kRowChunk)) load_group<false>(first, j0, 0, x, y, z, q);
+    // the first group of each of the wave's chunks is requested during the
+    // chunk before (the first chunk's here), so that its load overlaps the
+    // workgroup's slab sums
+    JGroupT<!UNI> cur;
+    if (live && j0 + kGroupJ <= min(c1, j0 + kRowChunk)) load_group<false>(cur, j0, 0, x, y, z, q);
     for (int cs = c0; cs < c1; cs += kRowChunk) {
         const int ce = min(c1, cs + kRowChunk);
+        const int cn = cs + kRowChunk;  // the next chunk, when it holds a whole group
+        const int jnext = cn + kGroupJ <= min(c1, cn + kRowChunk) ? cn : -1;
         if (live && cs >= j0)
-            sym_rows_chunk<PREC, P, UNI, POT>(x, y, z, q, eps2, cs, ce, first, xi, yi, zi, qi, ia, pe,
+            sym_rows_chunk<PREC, P, UNI, POT>(x, y, z, q, eps2, cs, ce, jnext, cur, xi, yi, zi, qi, ia, pe,
                                               UNI ? qI : 1.0, slabw, red);
         else
             for (int u = lane; u < 3 * kRowStride; u += 64) slabw[u] = 0.0;
-        const int cn = cs + kRowChunk;  // the next chunk
-        if (live && cn >= j0 && cn + kGroupJ <= min(c1, cn + kRowChunk)) load_group<false>(first, cn, 0, x, y, z, q);
         __syncthreads();
         for (int u = threadIdx.x; u < 3 * kRowChunk; u += 64 * kSymRows) {
             const int c = u / kRowChunk, jj = u - c * kRowChunk, k = c * kRowStride + jj;

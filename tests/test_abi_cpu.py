@@ -198,6 +198,14 @@ def test_symmetric_config_validation(api):
             api.set_config(bad["op"], bad["n"], "fp64", p=bad["p"], wg=bad["wg"], splits=bad["splits"], algo=3)
     # the energy takes the Newton's-third-law stage too (the potential as a fourth component)
     assert api.get_config("energy", 50000, "fp64")["algo"] == 2
+    # row-group tiles from 81920 ions (P = 8, JL = 512), one-wave tiles below
+    for op in ("forces", "energy", "md_step", "md_run"):
+        c = api.get_config(op, 100000, "fp64")
+        assert (c["algo"], c["p"], c["wg"], c["splits"]) == (4, 8, 4, 512)
+        assert api.get_config(op, 81919, "fp64")["algo"] == 2
+        assert api.get_config(op, 81920, "fp64")["algo"] == 4
+        assert api.get_config(op, 262144, "fp64")["algo"] == 4
+        assert api.get_config(op, 262145, "fp64")["algo"] == 0
     assert api.get_config("energy", 10000, "fp64")["algo"] == 0
     for algo in (1, 2):
         for p in (2, 3, 4, 5, 6, 8):

@@ -180,7 +180,7 @@ def test_forces_at_the_symmetric_size_limit(api, oracle, n):
     from _gpu_util import dev, host, per_ion_rel, report
     d = inputs.cloud100k(n=n, seed=31)
     cfg = api.get_config("forces", n, "fp64")
-    assert cfg["algo"] == (2 if n <= (1 << 18) else 0)
+    assert cfg["algo"] == (4 if n <= (1 << 18) else 0)  # row-group tiles up to 2^18
     F = np.stack([host(t) for t in api.coulomb_forces(*(dev(d[k]) for k in "xyzq"))])
     g = np.random.Generator(np.random.PCG64(79))
     idx = np.unique(np.concatenate([[0, 1, n - 2, n - 1], g.choice(n, 300, replace=False)]))

@@ -52,7 +52,7 @@ def test_cloud100k_forces_every_ion(api, ref100k, prec):
     from _gpu_util import dev, host, per_ion_rel, report
     d, F_ref, kappa, _, _ = ref100k
     cfg = api.get_config("forces", d["n"], prec)
-    assert cfg["algo"] in (1, 2)  # the default at this size is the Newton's-third-law stage
+    assert cfg["algo"] in (1, 2, 4)  # the default at this size is the Newton's-third-law stage
     F = np.stack([host(t) for t in api.coulomb_forces(*(dev(d[k]) for k in "xyzq"), prec=prec)])
     err = per_ion_rel(F, F_ref)
     report(f"cloud100k/{prec} all ions", err, kappa)
