@@ -320,7 +320,7 @@ cb_status cb_load_tuning(const char* cache_path);
  *          3: md_step / md_run of one run of at most 8192 ions in one launch
  *          per step, every ordered pair evaluated by one wave per 64 ions and
  *          j-part, the parts added in a fixed order by the last to finish,
- *          then trap, kick and drift -- the default up to 384 ions),
+ *          then trap, kick and drift -- the default up to 256 ions),
  * out[1] = i-particles per lane, out[2] = workgroup size (algorithm 0) or
  *          j's per reduction group (algorithms 1, 2, 4),
  * out[3] = j-splits (algorithm 0), j-segment length (algorithms 1, 2, 4) or

@@ -98,11 +98,12 @@ LaunchCfg default_cfg(int op, int64_t n, int prec) {
     }
     const bool force_op = sym_op(op);
     if ((op == CB_OP_MD_STEP || op == CB_OP_MD_RUN) && n <= kSmallRunDefault) {
-        // One launch per step: for a few hundred ions the two-launch step is
-        // bound by the latency of its second launch (measured on MI355X with
-        // energy records every step: 10.2 against 10.6 us per step at 256
-        // ions, 12.2 against 12.7 at 384; at 512 ions the two-launch step is
-        // faster, 11.2 against 13.5).
+        // One launch per step: for the smallest runs the two-launch step is
+        // bound by the latency of its second launch (measured on MI355X,
+        // per step without / with energy records: 6.8 / 9.0 us against 7.7 /
+        // 9.0 at 128 ions, 7.1 / 9.5 against 7.5 / 8.6 at 256; from 384 ions
+        // the two-launch step with its 16-thread epilogue is faster, 8.4 /
+        // 9.6 against 8.7 / 11.3).
         c.algo = ALGO_SMALL;
         c.p = 1;
         c.wg = 64;
@@ -162,11 +163,17 @@ LaunchCfg direct_cfg(int op, int64_t n, int prec) {
     if (hv || small) c.wg = 256;
     int64_t s = ((hv ? 3072 : (small ? 4096 : 65536)) + waves - 1) / waves;
     s = std::max<int64_t>(1, std::min<int64_t>(s, kMaxSplits));
-    // j-ranges of at least 64, or 32 for the force kernel up to 1024 ions:
-    // md_run at 1024 ions with energies every step took 16.5 us per step at
-    // 32 splits of 32 j's, 17.2 at 16 splits and 21 at 64; at 2048 and 3000
-    // ions 64 splits were slower than 32 and 46 (measured on MI355X)
+    // j-ranges of at least 64, or 32 for the force kernel up to 1024 ions
+    // (with one epilogue thread per ion, md_run at 1024 ions with energies
+    // every step took 16.5 us per step at 32 splits of 32 j's, 17.2 at 16
+    // splits and 21 at 64; measured on MI355X)
     s = std::min<int64_t>(s, std::max<int64_t>(1, n / (hv || n > 1024 ? 64 : 32)));
+    // md_step / md_run up to 4096 ions: j-ranges of 16, at most 64 of them,
+    // whose sums the epilogue spreads over 16 threads per ion (with energies
+    // every step: 11.0 us per step at 1024 ions against 11.8-12.0 with 32 or
+    // 48 splits; 14.3 at 2048 against 15.3; 24.9 at 4096 against 25.2-26.7)
+    if ((op == CB_OP_MD_STEP || op == CB_OP_MD_RUN) && n <= 4096)
+        s = std::min<int64_t>(kMaxSplits, std::max<int64_t>(1, n / 16));
     c.splits = (int)s;
     return c;
 }
@@ -260,7 +267,7 @@ WsLayout ws_layout(int op, int64_t n, int32_t nrun, int32_t nvec, int32_t prec) 
         if (op == CB_OP_ENERGY || op == CB_OP_MD_STEP || op == CB_OP_MD_RUN)
             off += al(sizeof(double) * (size_t)kMaxSplits * N);
         L.eblk = off;  // two sets of block partials (md_run alternates them) and a counter
-        off += al(sizeof(double) * 6 * (N / kEpiBlock + 2));
+        off += al(sizeof(double) * 6 * (N / kEpiMinIons + 2));
         L.aux = off;
         if (op == CB_OP_ADJOINT) off += al(sizeof(double) * 3 * N);
     } else {

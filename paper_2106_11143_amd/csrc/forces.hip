@@ -43,6 +43,22 @@ static bool overlaps2(const void* a, int64_t na, const void* b, int64_t nb) {
 
 static double* at(void* ws, size_t off) { return reinterpret_cast<double*>(static_cast<char*>(ws) + off); }
 
+// Blocks of k_epilogue over E.n ions with epi_parts(E.n, E.S) threads per ion.
+static int epilogue_blocks(const EpiParams& E) {
+    const int ipb = kEpiThreads / epi_parts(E.n, E.S);
+    return (E.n + ipb - 1) / ipb;
+}
+
+// k_epilogue on g blocks (epilogue_blocks(E), plus one for a deferred record).
+static cb_status launch_epilogue(const EpiParams& E, unsigned g, hipStream_t st) {
+    switch (epi_parts(E.n, E.S)) {
+        case 16: k_epilogue<16><<<g, kEpiThreads, 0, st>>>(E); break;
+        case 8: k_epilogue<8><<<g, kEpiThreads, 0, st>>>(E); break;
+        default: k_epilogue<1><<<g, kEpiThreads, 0, st>>>(E); break;
+    }
+    return check_launch("k_epilogue");
+}
+
 struct PairRun {
     LaunchCfg cfg;
     int jlen, S;
@@ -138,8 +154,6 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
     double* eblk = at(ws, L.eblk);
     unsigned* fl = flags_ptr();
     if (!fl) return fail(CB_EHIP, "md_run: device flag symbol not found");
-    const int nb = (int)((n + kEpiThreads - 1) / kEpiThreads);
-
     EpiParams E{};
     E.n = (int)n;
     E.S = pr.S;
@@ -162,23 +176,25 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
     // of two buffers (alternating), and the next epilogue launch sums them
     // with one extra block (stream order makes them complete); a record on
     // the last launch is summed by k_energy_final.
-    const size_t nbuf = 3 * ((size_t)n / kEpiBlock + 1);
+    const size_t nbuf = 3 * ((size_t)n / kEpiMinIons + 1);
     double* ebuf[2] = {eblk, eblk + nbuf};
     int parity = 0;
     const double* pend = nullptr;
     double* pend_out = nullptr;
+    int pend_nb = 0;  // block partials of the pending record
     E.efinal = nullptr;
     E.ecount = nullptr;
     auto epilogue = [&](double* rec_out) -> cb_status {
+        const int nb = epilogue_blocks(E);
         E.eblk = ebuf[parity];
         E.eprev = pend;
         E.eprev_out = pend_out;
-        E.nprev = nb;
-        k_epilogue<<<nb + (pend ? 1 : 0), kEpiThreads, 0, st>>>(E);
-        cb_status r = check_launch("k_epilogue");
+        E.nprev = pend_nb;
+        cb_status r = launch_epilogue(E, (unsigned)(nb + (pend ? 1 : 0)), st);
         if (r) return r;
         pend = rec_out ? ebuf[parity] : nullptr;
         pend_out = rec_out;
+        pend_nb = rec_out ? nb : 0;
         if (rec_out) parity ^= 1;
         return CB_OK;
     };
@@ -220,7 +236,7 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
         if ((rc = epilogue(rec ? energies + 4 * (k / every) : nullptr))) return rc;
     }
     if (pend) {
-        k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, pend, pend_out, REC_ALL);
+        k_energy_final<<<1, kEpiThreads, 0, st>>>(pend_nb, pend, pend_out, REC_ALL);
         if ((rc = check_launch("k_energy_final"))) return rc;
     }
     return ok();
@@ -291,8 +307,7 @@ cb_status coulomb_forces(int64_t n, const double* x, const double* y, const doub
     E.mode = EPI_FORCES | (prescaled ? EPI_PRESCALED : 0u);
     E.flags = flags_ptr();
     if (!E.flags) return fail(CB_EHIP, "coulomb_forces: device flag symbol not found");
-    k_epilogue<<<(int)((n + kEpiThreads - 1) / kEpiThreads), kEpiThreads, 0, st>>>(E);
-    if ((rc = check_launch("k_epilogue"))) return rc;
+    if ((rc = launch_epilogue(E, (unsigned)epilogue_blocks(E), st))) return rc;
     return ok();
 }
 
@@ -348,7 +363,7 @@ cb_status coulomb_forces_noalloc(int64_t n, const double* x, const double* y, co
     E.fz = fz;
     E.mode = EPI_FORCES | (sym ? EPI_PRESCALED : 0u);
     E.flags = fl;
-    k_epilogue<<<(int)((n + kEpiThreads - 1) / kEpiThreads), kEpiThreads, 0, st>>>(E);
+    k_epilogue<1><<<(int)((n + kEpiThreads - 1) / kEpiThreads), kEpiThreads, 0, st>>>(E);
     if ((rc = check_launch("k_epilogue"))) return rc;
     return ok();
 }
@@ -401,7 +416,7 @@ cb_status coulomb_forces_range(int64_t n, int64_t i0, int64_t i1, const double* 
     E.mode = EPI_FORCES;
     E.flags = flags_ptr();
     if (!E.flags) return fail(CB_EHIP, "coulomb_forces_range: device flag symbol not found");
-    k_epilogue<<<(int)((ni + kEpiThreads - 1) / kEpiThreads), kEpiThreads, 0, st>>>(E);
+    k_epilogue<1><<<(int)((ni + kEpiThreads - 1) / kEpiThreads), kEpiThreads, 0, st>>>(E);
     if ((rc = check_launch("k_epilogue"))) return rc;
     return ok();
 }
@@ -456,9 +471,8 @@ cb_status coulomb_energy(int64_t n, const double* x, const double* y, const doub
     E.eblk = eblk;
     E.flags = flags_ptr();
     if (!E.flags) return fail(CB_EHIP, "coulomb_energy: device flag symbol not found");
-    const int nb = (int)((n + kEpiThreads - 1) / kEpiThreads);
-    k_epilogue<<<nb, kEpiThreads, 0, st>>>(E);
-    if ((rc = check_launch("k_epilogue"))) return rc;
+    const int nb = epilogue_blocks(E);
+    if ((rc = launch_epilogue(E, (unsigned)nb, st))) return rc;
     k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, eblk, u_out, REC_UC);
     if ((rc = check_launch("k_energy_final"))) return rc;
     return ok();
@@ -520,9 +534,8 @@ cb_status coulomb_trap_grad(int64_t n, const double* x, const double* y, const d
         E.part = at(ws, L.part);
         if (prescaled) E.mode |= EPI_PRESCALED;
     }
-    const int nb = (int)((n + kEpiThreads - 1) / kEpiThreads);
-    k_epilogue<<<nb, kEpiThreads, 0, st>>>(E);
-    if ((rc = check_launch("k_epilogue"))) return rc;
+    const int nb = epilogue_blocks(E);
+    if ((rc = launch_epilogue(E, (unsigned)nb, st))) return rc;
     if (u_out) {
         k_energy_final<<<1, kEpiThreads, 0, st>>>(nb, E.eblk, u_out, REC_UPOT);
         if ((rc = check_launch("k_energy_final"))) return rc;

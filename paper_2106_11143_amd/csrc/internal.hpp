@@ -17,6 +17,14 @@ constexpr int kBatchGridMax = 2048;  // workgroups of one batched launch (force 
 constexpr int kBatchWG = 512;        // threads per workgroup of the persistent batched kernel
 constexpr int kBatchP = 4;           // ions per thread and register group in that kernel
 constexpr int kEpiBlock = 256;       // threads per element-wise block
+constexpr int kEpiMinIons = kEpiBlock / 16;  // ions per block of the widest epilogue (16 threads per ion)
+// Threads per ion of the epilogue (k_epilogue<T>) of the all-pairs kernel's
+// calls (forces, energy, gradient, md_step, md_run): in a run of at most
+// 8192 ions whose pair launch leaves 16 or more j-split partials per ion, 8
+// or 16 threads share each ion's sums, over 8 or 16 times the CUs (md_run
+// with energies every step on MI355X: 1024 ions 14.5 -> 11.0 us per step,
+// 2048 17.4 -> 14.3, 4096 28.5 -> 24.9, with 64 splits).
+constexpr int epi_parts(int64_t n, int S) { return n > 8192 ? 1 : (S >= 32 ? 16 : (S >= 16 ? 8 : 1)); }
 constexpr int64_t kMaxIons = int64_t(1) << 28;  // largest n any entry point accepts
 constexpr int64_t kSymMaxN = int64_t(1) << 18;  // largest n for the symmetric kernel (partials grow as n^2)
 constexpr int kMaxDevices = 64;      // GPUs per process the per-device symbol tables hold
@@ -182,7 +190,7 @@ cb_status md_run_ensemble(int32_t nrun, const int64_t* offsets, const cb_state* 
 // (ensemble.hip), with S j-parts per 64 ions (1..kSmallPartsMax): workspace
 // bytes, the default S and the driver.
 constexpr int64_t kSmallRunMax = 8192;
-constexpr int64_t kSmallRunDefault = 384;  // largest run that takes it by default
+constexpr int64_t kSmallRunDefault = 256;  // largest run that takes it by default
 constexpr int kSmallPartsMax = 32;
 size_t md_small_ws_bytes(int64_t n, int S);
 int small_parts(int64_t n);

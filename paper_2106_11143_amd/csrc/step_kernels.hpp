@@ -100,58 +100,98 @@ __device__ __forceinline__ void sum_record(int nb, const double* __restrict__ eb
 
 __global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 
+// T threads per ion (T = 1, 2, 4, 8 or 16; kEpiThreads / T ions per block): with
+// T > 1 thread t of an ion sums the t-th contiguous share of the S splits in
+// split order and the shares are added in share order through LDS, so that a
+// few hundred ions with many splits take T times the CUs and 1/T of the
+// dependent loads per thread.  The sum does not depend on timing.
+template <int T = 1>
 __global__ void __launch_bounds__(kEpiThreads) k_epilogue(EpiParams P) {
+    static_assert(T == 1 || T == 2 || T == 4 || T == 8 || T == 16, "threads per ion");
+    constexpr int IPB = kEpiThreads / T;  // ions per block
     if (P.eprev && blockIdx.x == gridDim.x - 1) {  // the extra block: an earlier record's sum
         sum_record(P.nprev, P.eprev, P.eprev_out, REC_ALL);
         return;
     }
-    const int i = blockIdx.x * kEpiThreads + threadIdx.x;
+    const int il = T == 1 ? (int)threadIdx.x : (int)threadIdx.x % IPB;
+    const int share = T == 1 ? 0 : (int)threadIdx.x / IPB;
+    const int i = blockIdx.x * IPB + il;
     double eK = 0.0, eC = 0.0, eT = 0.0;
     const unsigned mode = P.mode;
-    if (i < P.n) {
-        const int n = P.n;
-        double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
-        const bool need_f = (mode & (EPI_FORCES | EPI_ACCEL | EPI_KICK | EPI_GRAD)) != 0;
-        const bool need_p = (mode & EPI_ENERGY) && P.ppot != nullptr;
+    const int n = P.n;
+    const bool need_f = (mode & (EPI_FORCES | EPI_ACCEL | EPI_KICK | EPI_GRAD)) != 0;
+    const bool need_p = (mode & EPI_ENERGY) && P.ppot != nullptr;
+    // the ion's state, requested before the partials so that both round
+    // trips overlap (only share 0 of ion i touches it)
+    const bool need_s =
+        (mode & (EPI_ACCEL | EPI_KICK | EPI_DRIFT | EPI_ENERGY)) && !(mode & (EPI_UC_ONLY | EPI_UPOT | EPI_GRAD));
+    const bool own = i < n && share == 0;
+    double x = 0.0, y = 0.0, z = 0.0, vx = 0.0, vy = 0.0, vz = 0.0, ax = 0.0, ay = 0.0, az = 0.0, mi = 1.0;
+    if (own && need_s) {
+        x = P.x[i];
+        y = P.y[i];
+        z = P.z[i];
+        vx = P.vx[i];
+        vy = P.vy[i];
+        vz = P.vz[i];
+        ax = P.ax[i];
+        ay = P.ay[i];
+        az = P.az[i];
+        mi = P.m[i];
+    }
+    double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+    {
+        int s0 = 0, ns = P.S;  // this thread's splits s0 .. s0 + ns - 1
+        if (T > 1) {
+            const int len = (P.S + T - 1) / T;
+            s0 = min(P.S, share * len);
+            ns = min(P.S, s0 + len) - s0;
+        }
         const size_t n3 = 3 * (size_t)n;
-        // the ion's state, requested before the partials so that both
-        // round trips overlap (only this thread touches ion i)
-        const bool need_s =
-            (mode & (EPI_ACCEL | EPI_KICK | EPI_DRIFT | EPI_ENERGY)) && !(mode & (EPI_UC_ONLY | EPI_UPOT | EPI_GRAD));
-        double x = 0.0, y = 0.0, z = 0.0, vx = 0.0, vy = 0.0, vz = 0.0, ax = 0.0, ay = 0.0, az = 0.0, mi = 1.0;
-        if (need_s) {
-            x = P.x[i];
-            y = P.y[i];
-            z = P.z[i];
-            vx = P.vx[i];
-            vy = P.vy[i];
-            vz = P.vz[i];
-            ax = P.ax[i];
-            ay = P.ay[i];
-            az = P.az[i];
-            mi = P.m[i];
+        if (i < n) {
+            if (need_f && need_p) {  // the four arrays' loads together
+                const double* ps[4] = {P.part + s0 * n3 + i, P.part + s0 * n3 + n + i,
+                                       P.part + s0 * n3 + 2 * (size_t)n + i, P.ppot + (size_t)s0 * n + i};
+                const size_t st[4] = {n3, n3, n3, (size_t)n};
+                double o[4];
+                split_sums<4, 16>(ps, st, ns, o);
+                sx = o[0];
+                sy = o[1];
+                sz = o[2];
+                sp = o[3];
+            } else if (need_f) {
+                const double* ps[3] = {P.part + s0 * n3 + i, P.part + s0 * n3 + n + i,
+                                       P.part + s0 * n3 + 2 * (size_t)n + i};
+                const size_t st[3] = {n3, n3, n3};
+                double o[3];
+                split_sums<3, 16>(ps, st, ns, o);
+                sx = o[0];
+                sy = o[1];
+                sz = o[2];
+            } else if (need_p) {
+                sp = split_sum(P.ppot + (size_t)s0 * n + i, (size_t)n, ns);
+            }
         }
+        if constexpr (T > 1) {  // the shares in share order
+            __shared__ double red[4][T][IPB];
+            red[0][share][il] = sx;
+            red[1][share][il] = sy;
+            red[2][share][il] = sz;
+            red[3][share][il] = sp;
+            __syncthreads();
+            if (share == 0) {
+#pragma unroll
+                for (int u = 1; u < T; ++u) {
+                    sx += red[0][u][il];
+                    sy += red[1][u][il];
+                    sz += red[2][u][il];
+                    sp += red[3][u][il];
+                }
+            }
+        }
+    }
+    if (own) {
         const double qi = P.q[i];
-        if (need_f && need_p) {  // the four arrays' loads together
-            const double* ps[4] = {P.part + i, P.part + n + i, P.part + 2 * (size_t)n + i, P.ppot + i};
-            const size_t st[4] = {n3, n3, n3, (size_t)n};
-            double o[4];
-            split_sums<4, 16>(ps, st, P.S, o);
-            sx = o[0];
-            sy = o[1];
-            sz = o[2];
-            sp = o[3];
-        } else if (need_f) {
-            const double* ps[3] = {P.part + i, P.part + n + i, P.part + 2 * (size_t)n + i};
-            const size_t st[3] = {n3, n3, n3};
-            double o[3];
-            split_sums<3, 16>(ps, st, P.S, o);
-            sx = o[0];
-            sy = o[1];
-            sz = o[2];
-        } else if (need_p) {
-            sp = split_sum(P.ppot + i, (size_t)n, P.S);
-        }
         const double c = kCoulomb * qi;
         const double cf = (mode & EPI_PRESCALED) ? 1.0 : c;
         // U_C of the ion: half its potential sum times k_C q_i, or its share

@@ -178,13 +178,17 @@ def test_symmetric_config_validation(api):
     assert (c["algo"], c["p"], c["wg"], c["splits"], c["tuned"]) == (1, 3, 4, 2048, True)
     api.reset_config("md_run", 50000, "fp64")
     assert api.get_config("md_run", 50000, "fp64")["algo"] == 2  # the default at this size
-    c = api.get_config("md_run", 300, "fp64")  # small runs: one launch per step
-    assert (c["algo"], c["p"], c["wg"], c["splits"], c["tuned"]) == (3, 1, 64, 8, False)
-    assert api.get_config("forces", 300, "fp64")["algo"] == 0
-    assert (api.get_config("md_run", 384, "fp64")["algo"], api.get_config("md_run", 385, "fp64")["algo"]) == (3, 0)
-    c = api.get_config("md_run", 1024, "fp64")  # two launches, j-ranges of 32 ions up to 1024
-    assert (c["algo"], c["wg"], c["splits"]) == (0, 256, 32)
-    assert api.get_config("md_run", 2048, "fp64")["splits"] == 32  # ranges of 64 beyond
+    c = api.get_config("md_run", 250, "fp64")  # small runs: one launch per step
+    assert (c["algo"], c["p"], c["wg"], c["splits"], c["tuned"]) == (3, 1, 64, 7, False)
+    assert api.get_config("forces", 250, "fp64")["algo"] == 0
+    assert (api.get_config("md_run", 256, "fp64")["algo"], api.get_config("md_run", 257, "fp64")["algo"]) == (3, 0)
+    assert api.get_config("md_run", 300, "fp64")["splits"] == 18  # j-ranges of 16
+    c = api.get_config("md_run", 1024, "fp64")  # two launches, j-ranges of 16 ions up to 4096
+    assert (c["algo"], c["wg"], c["splits"]) == (0, 256, 64)
+    assert api.get_config("md_run", 512, "fp64")["splits"] == 32
+    assert api.get_config("md_step", 4096, "fp64")["splits"] == 64
+    assert api.get_config("md_run", 8192, "fp64")["splits"] == 32  # ranges of 64 beyond
+    assert api.get_config("forces", 1024, "fp64")["splits"] == 32  # the forces keep ranges of 32
     assert api.get_config("md_run", 1000, "fp64")["algo"] == 0
     assert api.get_config("md_run", 10000, "fp64")["algo"] == 0
     api.set_config("md_step", 8192, "fp64", p=1, wg=64, splits=7, algo=3)
