@@ -591,7 +591,8 @@ def bench_kz(args):
     del graph
     extra = {"mixed": res["mixed"], "fp64": res["fp64"], "fp64_graph_replay": res["fp64_graph"],
              "fp64_persistent_kernel": res["fp64_persistent"],
-             "path": "stepped (p = 4, JL = 256, the default shape)", "nrun": d["nrun"],
+             "path": "stepped (p = 4; JL = 512, the default shape for ensembles of 2^30 or more ordered pairs)",
+             "nrun": d["nrun"],
              "nsteps_per_run": nsteps,
              "sum_N2": float((ns.astype(np.float64) ** 2).sum()),
              "roofline": _roof(FLOPS_PER_SYM_PAIR * float((ns.astype(np.float64) * (ns - 1) / 2).sum()) * nsteps,

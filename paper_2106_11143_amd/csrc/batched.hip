@@ -456,9 +456,13 @@ cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s
     // a small run at about 1.6e9 ordered pairs/s per CU (its runs are spread
     // over the CUs, the largest bounding the step); the stepped path costs
     // about 40 us of launch latency per step plus the pairs at 1.8e12/s.
-    // The stepped path uses 256-ion i-blocks and 256-ion j-segments, the
-    // fastest shape measured for every mix of run sizes tried (runs of 64 to
-    // 4096 ions, 8 to 512 runs).
+    // The stepped path uses 256-ion i-blocks, with 512-ion j-segments when
+    // the ensemble holds 2^30 or more ordered pairs (4096 or more tiles) and
+    // 256-ion ones below (measured on MI355X, ms per step with JL 256 / 512:
+    // kz512's 512 runs of 64-4096 ions 1.211 / 1.182; 1024 runs of
+    // 1024-4096 3.189 / 3.144; 256 of 2048-4096 1.024 / 1.004; but 128 runs
+    // of 64-2048, 1.9e8 pairs, 0.137 / 0.185).  Eight ions per lane were
+    // slower for each of these mixes.
     LaunchCfg ec = get_cfg(CB_OP_MD_ENSEMBLE, offsets[nrun], prec);
     if (!ec.tuned) {
         double pairs = 0.0;
@@ -468,7 +472,7 @@ cb_status md_run_batched(int32_t nrun, const int64_t* offsets, const cb_state* s
         const double t_stepped = 40e-6 + pairs / 1.8e12;
         ec.algo = t_stepped < t_persistent ? ALGO_SYM_LDS : ALGO_DIRECT;
         ec.p = 4;
-        ec.splits = 256;
+        ec.splits = pairs >= 1073741824.0 ? 512 : 256;
     }
     if (ec.algo == ALGO_SYM_LDS) {
         const WsLayout LE = ws_layout(CB_OP_MD_RUN, offsets[nrun], nrun, 1, prec);

@@ -79,10 +79,12 @@ static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 // sums too when pot.  Direct: partial sums [S][3][n] at ws+L.part (to be
 // scaled by k_C q_i) and [S][n] at ws+L.ppot.  Symmetric: the finished forces
 // [3][n] at ws+L.part (S = 1, prescaled), its tiles and partials after them,
-// and the potential sums [n] at ws+L.ppot (S = 1).
+// and the potential sums [n] at ws+L.ppot (S = 1).  tiles_ready: when
+// non-NULL and true, the tile table of the symmetric stage is already in ws (an earlier
+// call of the same md_run); set to true once it is.
 static cb_status force_stage(int op, int prec, int64_t n, const double* x, const double* y, const double* z,
                              const double* q, double eps2, void* ws, const WsLayout& L, hipStream_t st, int* S_out,
-                             bool* prescaled, bool pot = false) {
+                             bool* prescaled, bool pot = false, bool* tiles_ready = nullptr) {
     const LaunchCfg cfg = get_cfg(op, n, prec);
     double* part = at(ws, L.part);
     double* ppot = pot ? at(ws, L.ppot) : nullptr;
@@ -90,7 +92,10 @@ static cb_status force_stage(int op, int prec, int64_t n, const double* x, const
         *S_out = 1;
         *prescaled = true;
         void* tiles_ws = static_cast<char*>(ws) + L.part + al256(sizeof(double) * 3 * (size_t)n);
-        return launch_pair_sym(prec, cfg, (int)n, x, y, z, q, eps2, tiles_ws, part, st, ppot);
+        const cb_status rc =
+            launch_pair_sym(prec, cfg, (int)n, x, y, z, q, eps2, tiles_ws, part, st, ppot, tiles_ready && *tiles_ready);
+        if (tiles_ready && rc == CB_OK) *tiles_ready = true;
+        return rc;
     }
     const PairRun pr = plan(op, n, prec);
     *S_out = pr.S;
@@ -205,11 +210,14 @@ static cb_status md_single(int64_t n, const cb_state* s, const double* q, const 
     // the symmetric stage too when it is configured (its forces unused), else
     // the direct kernel's potential-only pass.
     const bool sym_stage = is_sym(get_cfg(op, n, prec).algo) && n <= kSymMaxN;
+    // the symmetric stage's tile table is the same at every step: built by
+    // the first force stage of the run, read by the later ones
+    bool plan_ready = false;
     auto pairs = [&](bool force, bool pot) -> cb_status {
         if (force || sym_stage) {
             int S = 0;
             bool pre = false;
-            cb_status r = force_stage(op, prec, n, s->x, s->y, s->z, q, eps2, ws, L, st, &S, &pre, pot);
+            cb_status r = force_stage(op, prec, n, s->x, s->y, s->z, q, eps2, ws, L, st, &S, &pre, pot, &plan_ready);
             E.S = S;
             prescaled_now = pre;
             return r;

@@ -143,7 +143,9 @@ bool trap_ok(const cb_trap* t, const char* who, cb_status* st);
 // W consecutive i-blocks of IB ions (W = 1: single rows), the j's above the
 // group's first block cut into j-segments of JL.  sym_plan carves
 // rowstart[nG+1] and tiles[T] (tile = (group, segment)) from the start of ws
-// (sym_plan_bytes of it) and enqueues the kernel that fills them.
+// (sym_plan_bytes of it) and enqueues the kernel that fills them (unless
+// filled: the same table is already in ws, written by an earlier call on the
+// stream with the same n, IB, JL and W).
 struct SymPlan {
     int* rowstart;
     int2* tiles;
@@ -152,16 +154,18 @@ struct SymPlan {
 };
 int64_t sym_tiles(int64_t n, int IB, int JL, int W = 1);
 size_t sym_plan_bytes(int64_t n, int IB, int JL, int W = 1);
-cb_status sym_plan(int n, int IB, int JL, void* ws, SymPlan* out, hipStream_t st, int W = 1);
+cb_status sym_plan(int n, int IB, int JL, void* ws, SymPlan* out, hipStream_t st, int W = 1, bool filled = false);
 
 // Symmetric (Newton's third law) force path (pair_sym.hip): workspace bytes
 // for (n, p, JL) and W rows per workgroup (pot: with the tiles' pair
 // energies), and the launch sequence ending with finished forces F[3][n]
 // and, when phi is set, each ion's share of the Coulomb energy, U_C = k_C
-// sum_k phi[k].
+// sum_k phi[k].  plan_filled: ws already holds the tile table of (n, c), from
+// an earlier launch on the stream (md_run's later steps).
 size_t sym_ws_bytes(int64_t n, int p, int jl, bool pot = false, int W = 1);
 cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, const double* y, const double* z,
-                          const double* q, double eps2, void* ws, double* F, hipStream_t st, double* phi = nullptr);
+                          const double* q, double eps2, void* ws, double* F, hipStream_t st, double* phi = nullptr,
+                          bool plan_filled = false);
 
 // Launches of the pair kernels (pair.hip).  The _range form evaluates the
 // forces / potentials of the ions i0 .. i0 + ni - 1 only (partials indexed by

@@ -149,7 +149,7 @@ size_t sym_plan_bytes(int64_t n, int IB, int JL, int W) {
     return al256(sizeof(int) * (nG + 1)) + al256(sizeof(int2) * (sym_tiles(n, IB, JL, W) + 1));
 }
 
-cb_status sym_plan(int n, int IB, int JL, void* ws, SymPlan* out, hipStream_t st, int W) {
+cb_status sym_plan(int n, int IB, int JL, void* ws, SymPlan* out, hipStream_t st, int W, bool filled) {
     const int nI = (n + IB - 1) / IB;
     if (nI > kPlanMaxRows) return fail(CB_EINVAL, "sym_plan: n = %d is too large for the symmetric kernels", n);
     const int nG = sym_groups(n, IB, W);
@@ -159,18 +159,20 @@ cb_status sym_plan(int n, int IB, int JL, void* ws, SymPlan* out, hipStream_t st
     base += al256(sizeof(int) * (nG + 1));
     out->tiles = reinterpret_cast<int2*>(base);
     out->bytes = sym_plan_bytes(n, IB, JL, W);
+    if (filled) return CB_OK;
     k_sym_plan<<<1, kPlanThreads, 0, st>>>(n, IB, JL, W, nG, out->rowstart, out->tiles);
     return check_launch("k_sym_plan");
 }
 
 cb_status launch_pair_sym(int prec, const LaunchCfg& c, int n, const double* x, const double* y, const double* z,
-                          const double* q, double eps2, void* ws, double* F, hipStream_t st, double* phi) {
+                          const double* q, double eps2, void* ws, double* F, hipStream_t st, double* phi,
+                          bool plan_filled) {
     const int P = c.p, JL = c.splits, IB = 64 * P, W = sym_rows(c.algo);
     if (!is_sym(c.algo) || !sym_cfg_ok(P, c.wg, JL) || (W > 1 && !sym_rows_p_ok(P)))
         return fail(CB_EINVAL, "launch_pair_sym: bad configuration");
     const int red = c.algo == ALGO_SYM ? 0 : 1;
     SymPlan plan;
-    cb_status rc = sym_plan(n, IB, JL, ws, &plan, st, W);
+    cb_status rc = sym_plan(n, IB, JL, ws, &plan, st, W, plan_filled);
     if (rc) return rc;
     const int64_t T = plan.T;
     int* rowstart = plan.rowstart;
