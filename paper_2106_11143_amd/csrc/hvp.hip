@@ -129,9 +129,10 @@ static cb_status launch_hvp_sym(int prec, const LaunchCfg& c, int nvec, int n, c
         return fail(CB_EINVAL, "coulomb_hvp: bad Newton's-third-law configuration p %d / JL %d at n = %d", P, JL, n);
     const int nvmax = c.wg;  // the most vectors per pass: 1, 2 or 4
     const int wsp = hvp_sym_passes(nvec, nvmax);  // the passes the workspace holds
-    SymPlan pl;
-    cb_status rc = sym_plan(n, IB, JL, ws, &pl, st);
+    SymPlan pl;  // its table is filled by the first pack launch below
+    cb_status rc = sym_plan(n, IB, JL, ws, &pl, st, 1, true);
     if (rc) return rc;
+    const int nG = (n + IB - 1) / IB;
     const size_t np = (size_t)wsp;
     char* base = static_cast<char*>(ws) + pl.bytes;
     double* Pi = reinterpret_cast<double*>(base);
@@ -148,7 +149,9 @@ static cb_status launch_hvp_sym(int prec, const LaunchCfg& c, int nvec, int n, c
         const int npass = std::max(1, std::min(wsp, (nvec - b0) / nv));
         const double* vb = v + (size_t)b0 * 3 * n;
         double* hb = hv + (size_t)b0 * 3 * n;
-        k_hvp_pack<<<dim3((n + 255) / 256, npass), 256, 0, st>>>(n, nv, x, y, z, q, vb, J);
+        const int plan_groups = b0 == 0 ? nG : 0;
+        k_hvp_pack<<<dim3((n + 255) / 256 + (plan_groups > 0 ? 1 : 0), npass), 256, 0, st>>>(
+            n, nv, x, y, z, q, vb, J, IB, JL, plan_groups, pl.rowstart, pl.tiles);
         if ((rc = check_launch("k_hvp_pack"))) return rc;
         bool okk = false;
         if (pl.T > 0) {

@@ -29,11 +29,19 @@ constexpr int kHvpRec = 16;  // doubles per packed j record: x, y, z, q, v[b][c]
 
 // J[i] = (x, y, z, q, v[0][0..2], ..., v[nv-1][0..2], 0 ...) for one pass of
 // nv <= 4 vectors; pass blockIdx.y takes vectors nv blockIdx.y ... and writes
-// its records n kHvpRec doubles further on.
+// its records n kHvpRec doubles further on.  With nG > 0 the launch has one
+// more column of blocks, whose first block writes the tile table of nG row
+// groups (sym_plan_fill, W = 1) instead, so that the table costs no launch
+// of its own.
 __global__ void __launch_bounds__(256) k_hvp_pack(int n, int nv, const double* __restrict__ x,
                                                   const double* __restrict__ y, const double* __restrict__ z,
                                                   const double* __restrict__ q, const double* __restrict__ v,
-                                                  double* __restrict__ J) {
+                                                  double* __restrict__ J, int IB, int JL, int nG,
+                                                  int* __restrict__ rowstart, int2* __restrict__ tiles) {
+    if (nG > 0 && blockIdx.x == gridDim.x - 1) {
+        if (blockIdx.y == 0) sym_plan_fill<256>(n, IB, JL, 1, nG, rowstart, tiles);
+        return;
+    }
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     v += (size_t)blockIdx.y * nv * 3 * n;

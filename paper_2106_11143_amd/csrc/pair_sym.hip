@@ -8,50 +8,12 @@
 
 namespace cb {
 
-// Tile table, one workgroup.  Rows are groups of W i-blocks (W = 1: single
-// blocks); group I's segments cut the j's above its first block, W I.
-// rowstart[I] = first tile of group I (exclusive prefix sum over groups of
-// their segment counts), rowstart[nI] = tiles T; tiles[t] = (group, segment)
-// of tile t.  Each thread sums the segments of a contiguous share of groups,
-// the shares are scanned in LDS (Hillis-Steele), the group starts are kept in
-// LDS, and each wave then writes whole groups of the table, its lanes taking
-// consecutive segments.
 constexpr int kPlanThreads = 1024;
-constexpr int kPlanMaxRows = 2048;  // n <= 2^18 ions in blocks of >= 128
 
+// Tile table, one workgroup (sym_plan_fill in pair_sym.hpp).
 __global__ void __launch_bounds__(kPlanThreads) k_sym_plan(int n, int IB, int JL, int W, int nI,
                                                            int* __restrict__ rowstart, int2* __restrict__ tiles) {
-    __shared__ int sh[kPlanThreads];
-    __shared__ int rs[kPlanMaxRows + 1];
-    const int t = threadIdx.x;
-    const int per = (nI + kPlanThreads - 1) / kPlanThreads;
-    const int r0 = min(nI, t * per), r1 = min(nI, r0 + per);
-    int mine = 0;
-    for (int I = r0; I < r1; ++I) mine += sym_nseg(n, IB, JL, I * W);
-    sh[t] = mine;
-    __syncthreads();
-    for (int w = 1; w < kPlanThreads; w <<= 1) {
-        const int add = t >= w ? sh[t - w] : 0;
-        __syncthreads();
-        sh[t] += add;
-        __syncthreads();
-    }
-    int acc = sh[t] - mine;  // exclusive prefix of this thread's rows
-    for (int I = r0; I < r1; ++I) {
-        rs[I] = acc;
-        rowstart[I] = acc;
-        acc += sym_nseg(n, IB, JL, I * W);
-    }
-    if (t == kPlanThreads - 1) {
-        rs[nI] = sh[t];
-        rowstart[nI] = sh[t];
-    }
-    __syncthreads();
-    const int lane = t & 63;
-    for (int I = t >> 6; I < nI; I += kPlanThreads / 64) {
-        const int s0 = rs[I], ns = rs[I + 1] - s0;
-        for (int sg = lane; sg < ns; sg += 64) tiles[s0 + sg] = make_int2(I, sg);
-    }
+    sym_plan_fill<kPlanThreads>(n, IB, JL, W, nI, rowstart, tiles);
 }
 
 static size_t al256(size_t b) { return (b + 255) / 256 * 256; }

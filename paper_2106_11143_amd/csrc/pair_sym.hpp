@@ -34,6 +34,52 @@ __host__ __device__ __forceinline__ int sym_nseg(int n, int IB, int JL, int I) {
     return a > 0 ? (a + JL - 1) / JL : 0;
 }
 
+// Tile table, by one workgroup of NT threads.  Rows are groups of W i-blocks
+// (W = 1: single blocks); group I's segments cut the j's above its first
+// block, W I.  rowstart[I] = first tile of group I (exclusive prefix sum over
+// groups of their segment counts), rowstart[nI] = tiles T; tiles[t] = (group,
+// segment) of tile t.  Each thread sums the segments of a contiguous share of
+// groups, the shares are scanned in LDS (Hillis-Steele), the group starts are
+// kept in LDS, and each wave then writes whole groups of the table, its lanes
+// taking consecutive segments.
+constexpr int kPlanMaxRows = 2048;  // n <= 2^18 ions in blocks of >= 128
+
+template <int NT>
+__device__ __forceinline__ void sym_plan_fill(int n, int IB, int JL, int W, int nI, int* __restrict__ rowstart,
+                                              int2* __restrict__ tiles) {
+    __shared__ int sh[NT];
+    __shared__ int rs[kPlanMaxRows + 1];
+    const int t = threadIdx.x;
+    const int per = (nI + NT - 1) / NT;
+    const int r0 = min(nI, t * per), r1 = min(nI, r0 + per);
+    int mine = 0;
+    for (int I = r0; I < r1; ++I) mine += sym_nseg(n, IB, JL, I * W);
+    sh[t] = mine;
+    __syncthreads();
+    for (int w = 1; w < NT; w <<= 1) {
+        const int add = t >= w ? sh[t - w] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    int acc = sh[t] - mine;  // exclusive prefix of this thread's rows
+    for (int I = r0; I < r1; ++I) {
+        rs[I] = acc;
+        rowstart[I] = acc;
+        acc += sym_nseg(n, IB, JL, I * W);
+    }
+    if (t == NT - 1) {
+        rs[nI] = sh[t];
+        rowstart[nI] = sh[t];
+    }
+    __syncthreads();
+    const int lane = t & 63;
+    for (int I = t >> 6; I < nI; I += NT / 64) {
+        const int s0 = rs[I], ns = rs[I + 1] - s0;
+        for (int sg = lane; sg < ns; sg += 64) tiles[s0 + sg] = make_int2(I, sg);
+    }
+}
+
 // s = q r^{-3} refined as in the direct kernel (the series on r^-3).
 template <int PREC>
 __device__ __forceinline__ double sym_s(double r2, double q, const SeriesK& K) {
