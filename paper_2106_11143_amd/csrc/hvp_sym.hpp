@@ -300,6 +300,9 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_hvp_sym_finish(
     int lo, hi;
     double d[3] = {0.0, 0.0, 0.0}, e[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
     share(b0, b1, w, lo, hi);
+    // four j's per iteration: their scalar loads are issued together
+    // (27.3 -> 22.9 us for 8 vectors at 8192 ions, measured on MI355X)
+#pragma unroll 4
     for (int j = lo; j < hi; ++j) {  // q_j T_kj over k's own block
         const double dx = xk - x[j], dy = yk - y[j], dz = zk - z[j];
         const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));

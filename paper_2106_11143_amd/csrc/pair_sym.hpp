@@ -536,6 +536,9 @@ __global__ void __launch_bounds__(64 * kFinishParts) k_sym_finish(int n, int IB,
     int lo, hi;
     double d0 = 0.0, d1 = 0.0, d2 = 0.0, ps = 0.0;
     share(b0, b1, w, lo, hi);
+    // four j's per iteration: their scalar loads are issued together (the
+    // finish at N = 1e5 with row groups: 95 -> 71 us, measured on MI355X)
+#pragma unroll 4
     for (int j = lo; j < hi; ++j) {
         const double dx = xk - x[j], dy = yk - y[j], dz = zk - z[j];
         const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
