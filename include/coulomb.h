@@ -60,7 +60,7 @@ typedef enum {
     CB_EHIP = 2,          /* a HIP runtime call or kernel launch failed */
     CB_ENOWS = 3,         /* workspace too small */
     CB_ENONFINITE = 4,    /* reported by cb_poll_flags when the flag is set */
-    CB_EUNSUPPORTED = 5   /* valid request this build does not handle */
+    CB_EUNSUPPORTED = 5   /* valid request the library does not handle */
 } cb_status;
 
 /* How 1/sqrt(r^2 + eps2) is evaluated (paper, sections 2 and 4: the cost and
