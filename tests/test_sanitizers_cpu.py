@@ -41,6 +41,13 @@ def _digest(paths, flags):
     return h.hexdigest()[:16]
 
 
+def _drop_stale(prefix, keep):
+    """Removes the cached builds of earlier sources (prefix*), keeping `keep`."""
+    for old in glob.glob(os.path.join(OUT, prefix + "*")):
+        if old != keep:
+            shutil.rmtree(old, ignore_errors=True) if os.path.isdir(old) else os.remove(old)
+
+
 def _run(cmd, **kw):
     r = subprocess.run(cmd, capture_output=True, text=True, **kw)
     if r.returncode != 0:
@@ -58,6 +65,7 @@ def test_oracle_under_asan_ubsan():
              "-fno-sanitize-recover=all"]
     exe = os.path.join(OUT, f"oracle_san_{_digest(deps, flags)}")
     if not os.path.exists(exe):
+        _drop_stale("oracle_san_", exe)
         _run(["gcc", *flags, src, "-o", exe, "-lm"])
     r = _run([exe], env=dict(ENV, OMP_NUM_THREADS="3"))
     assert "oracle_san ok" in r.stdout
@@ -77,6 +85,8 @@ def test_host_abi_under_asan_ubsan(tmp_path):
     key = _digest(deps, cflags)
     exe = os.path.join(OUT, f"abi_san_{key}")
     if not os.path.exists(exe):
+        _drop_stale("abi_san_", exe)
+        _drop_stale("obj_", "")
         objdir = os.path.join(OUT, f"obj_{key}")
         os.makedirs(objdir, exist_ok=True)
         jobs = [(s, os.path.join(objdir, os.path.basename(s) + ".o")) for s in srcs + [drv]]
