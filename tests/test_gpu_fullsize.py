@@ -138,3 +138,20 @@ def test_cloud100k_symmetric_variants_agree_and_repeat(api, oracle, algo, p, jl)
     assert per_ion_rel(F[:, idx], ref).max() <= 1e-12
     dflt = np.stack([t.cpu().numpy() for t in api.coulomb_forces(*args)])
     assert per_ion_rel(F, dflt).max() <= 1e-13
+
+
+def test_cloud100k_energy_on_the_default_stage(api, oracle):
+    """coulomb_energy of the headline system (N = 1e5) in the default launch,
+    the row-group tiles with the pair energies summed in the tiles and each
+    ion's share added by the finish, in the seeded order and grouped by
+    charge, against the oracle's compensated U_C."""
+    from _gpu_util import dev
+    d = inputs.cloud100k()
+    assert api.get_config("energy", d["n"], "fp64")["algo"] == 4
+    ref, _ = oracle.coulomb_energy(d["x"], d["y"], d["z"], d["q"])
+    for order, dd in (("seeded", d), ("grouped", inputs.group_by_charge(d))):
+        for prec, tol in (("fp64", 1e-12), ("mixed", 1e-9)):
+            u = float(api.coulomb_energy(*(dev(dd[k]) for k in "xyzq"), prec=prec)[0])
+            print(f"[cloud100k energy {order} {prec}] rel err {abs(u - ref) / abs(ref):.3e}", flush=True)
+            assert abs(u - ref) <= tol * abs(ref), (order, prec, u, ref)
+    api.clear_workspace_cache()
