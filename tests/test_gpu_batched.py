@@ -420,3 +420,42 @@ def test_ensemble_captured_in_a_hip_graph_replays_bitwise(api, path, sizes):
             api.md_run(other, qd, md, trap0, 0.0, dt, 3, offsets=ooffs, init_accel=True)
             torch.cuda.synchronize()
             assert torch.isfinite(torch.stack(other)).all()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_kz512_full_ensemble_sampled_runs_match_oracle(api, oracle, prec):
+    """The full Kibble-Zurek ensemble (512 runs, N uniform in [64, 4096],
+    about 1.07e6 ions, the ramped trap) in the default launch that bench.py
+    times: three steps with an energy record after each, then the largest
+    and the smallest run and six seeded others against the oracle run by
+    run, every ion of each.  FP64: positions, velocities, accelerations and
+    energies within ten times the oracle's own round-off envelope; mixed:
+    positions and velocities within 1e-9 of each block's scale."""
+    from _gpu_util import dev
+    d = inputs.kz512()
+    offs = d["offsets"]
+    sizes = np.diff(offs)
+    st = inputs.state9(d)
+    ts = [dev(st[k]) for k in range(9)]
+    nsteps, every = 3, 1
+    print(f"[kz512 full {prec}] {len(sizes)} runs, {int(offs[-1])} ions", flush=True)
+    en = api.md_run(ts, dev(d["q"]), dev(d["m"]), d["traps"], 0.0, d["dt"], nsteps, offsets=offs, every=every,
+                    prec=prec)
+    assert api.poll_flags() == 0
+    got = np.stack([t.cpu().numpy() for t in ts])
+    en = en.cpu().numpy()
+    assert np.isfinite(got).all() and np.isfinite(en).all()
+    g = np.random.Generator(np.random.PCG64(512))
+    runs = sorted({int(np.argmax(sizes)), int(np.argmin(sizes))} |
+                  {int(r) for r in g.choice(len(sizes), 6, replace=False)})
+    for r in runs:
+        sl = slice(int(offs[r]), int(offs[r + 1]))
+        tag = f"kz512 run {r} (N = {int(sizes[r])})"
+        if prec == "fp64":
+            _check_run(oracle, st[:, sl], d["q"][sl], d["m"][sl], d["traps"][r], d["dt"], nsteps, got[:, sl], en[r],
+                       every, tag)
+        else:
+            ref, _, _ = oracle.md_run(st[:, sl], d["q"][sl], d["m"][sl], d["traps"][r], 0.0, d["dt"], nsteps)
+            for blk in (slice(0, 3), slice(3, 6)):
+                assert np.abs(got[blk, sl] - ref[blk]).max() <= 1e-9 * np.abs(ref[blk]).max(), (tag, blk)
+    print(f"[kz512 full {prec}] runs {runs} match the oracle", flush=True)
