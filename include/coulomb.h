@@ -190,14 +190,17 @@ cb_status coulomb_forces_range(int64_t n, int64_t i0, int64_t i1, const double* 
  * the sums themselves.  With algorithm 0 (see cb_get_config) the all-pairs
  * kernel leaves its j-split partial force sums, before the fixed-order sum
  * over splits and the k_C q_i factor, at the start of ws as [splits][3][n]
- * doubles and *splits_out (host) is the number of splits; with algorithms 1
- * and 2 the start of ws holds the finished forces [3][n] and *splits_out is 0. */
+ * doubles and *splits_out (host) is the number of splits; with algorithms 1,
+ * 2 and 4 (the Newton's-third-law stages) the start of ws holds the finished
+ * forces [3][n] and *splits_out is 0. */
 cb_status coulomb_pair_stage(int64_t n, const double* x, const double* y, const double* z, const double* q,
                              double eps2, int32_t prec, int32_t* splits_out, void* ws, size_t ws_bytes,
                              void* stream);
 
-/* Coulomb energy U_C (J) into u_out[0] (device, one double).  Summed in a
- * fixed order (deterministic). */
+/* Coulomb energy U_C = k_C sum_{i<j} q_i q_j / (r_ij^2 + eps2)^{1/2} (J), the
+ * Coulomb part of the potential whose negative gradient is eq. (1)'s
+ * Coulomb force (section 2), into u_out[0] (device, one double).  x, y, z,
+ * q as for coulomb_forces.  Summed in a fixed order (deterministic). */
 cb_status coulomb_energy(int64_t n, const double* x, const double* y, const double* z, const double* q,
                          double eps2, int32_t prec, double* u_out, void* ws, size_t ws_bytes, void* stream);
 
@@ -231,7 +234,8 @@ cb_status cb_trap_k(const cb_trap* trap, double t, double k_out[3]);
 cb_status md_step(int64_t n, const cb_state* s, const double* q, const double* m, const cb_trap* trap,
                   double t, double dt, double eps2, int32_t prec, void* ws, size_t ws_bytes, void* stream);
 
-/* nsteps velocity-Verlet steps of nrun independent runs packed in s, q, m:
+/* nsteps velocity-Verlet steps (section 2, as md_step) of nrun independent
+ * runs packed in s, q, m:
  * run r owns ions offsets[r] .. offsets[r+1]-1 (offsets: host, nrun+1
  * entries, offsets[0] = 0, strictly increasing) and follows traps[r] (host,
  * nrun entries).  Step k of every run is at time t0 + k dt.  With flags &
@@ -249,8 +253,8 @@ cb_status md_step(int64_t n, const cb_state* s, const double* q, const double* m
  *    kick and drift (p i-particles per lane, j-segment length JL).
  * Without a forced or tuned entry the path with the smaller estimated step
  * time is taken (algorithm 0 wins only for ensembles of small runs whose
- * step is shorter than the stepped path's launch latency), with p = 4,
- * JL = 256.  Both paths give the same trajectories up to rounding
+ * step is shorter than the stepped path's launch latency), with p = 4 and
+ * JL = 256, or JL = 512 for ensembles of at least 2^30 ordered pairs.  Both paths give the same trajectories up to rounding
  * (different summation orders); each is deterministic.
  * Graph capture: md_run may be called on a stream that is being captured.
  * With nrun = 1 it enqueues kernels and device copies only.  With nrun > 1
