@@ -155,3 +155,30 @@ def test_cloud100k_energy_on_the_default_stage(api, oracle):
             print(f"[cloud100k energy {order} {prec}] rel err {abs(u - ref) / abs(ref):.3e}", flush=True)
             assert abs(u - ref) <= tol * abs(ref), (order, prec, u, ref)
     api.clear_workspace_cache()
+
+
+def test_cloud100k_energy_records_on_the_default_stage(api, oracle):
+    """md_run of the headline system (N = 1e5) on the default launch with an
+    energy record every step: the recording steps take the row-group tiles
+    with the pair energies.  The first record (the start state) and the last
+    (the state the run ends in) against the oracle's kinetic, Coulomb and
+    trap energies of those same states."""
+    from _gpu_util import dev, state_host, state_tensors
+    d = inputs.cloud100k()
+    assert api.get_config("md_run", d["n"], "fp64")["algo"] == 4
+    st = inputs.state9(d)
+    ts = state_tensors(st)
+    nsteps = 2
+    en = api.md_run(ts, dev(d["q"]), dev(d["m"]), d["trap"], 0.0, d["dt"], nsteps, every=1).cpu().numpy()[0]
+    got = state_host(ts)
+    assert en.shape[0] == nsteps + 1 and api.poll_flags() == 0
+    for rec, s in ((0, st), (nsteps, got)):
+        t = rec * d["dt"]
+        k = oracle.kinetic_energy(s[3], s[4], s[5], d["m"])
+        u, _ = oracle.coulomb_energy(s[0], s[1], s[2], d["q"])
+        tr = oracle.trap_energy(s[0], s[1], s[2], d["m"], d["trap"], t)
+        ref = np.array([k, u, tr, k + u + tr])
+        err = np.abs(en[rec] - ref)
+        rel = np.divide(err, np.abs(ref), out=np.zeros(4), where=ref != 0)
+        print(f"[cloud100k records] step {rec}: (K, U_C, U_trap, E) = {ref}, rel err {rel}", flush=True)
+        assert np.all(err <= 1e-12 * np.abs(ref)), (rec, en[rec], ref)  # exact where ref is 0 (K at rest)
